@@ -1,0 +1,290 @@
+"""Finite-volume right-hand side f(y) and its Jacobian-vector products.
+
+TEST INFRASTRUCTURE ONLY (CPU oracle; see the package docstring).
+
+What is computed (paper Sec. 3.2, eq. 11 and the paragraph after it):
+the semi-discrete compressible Euler / Navier-Stokes equations on a periodic,
+cell-centred Cartesian grid, written as the autonomous system y' = f(y) of
+Sec. 2, eq. 1.  The paper's solver uses MUSCL reconstruction with selectable
+limiters and an approximate Riemann flux; here the flux is Rusanov's and the
+limiter is minmod, and the grid is Cartesian and periodic.  Readings of what
+the paper leaves open:
+
+* state order per cell: [rho, rho*u, rho*v, (rho*w), E]  (the printed order
+  [rho, rho v, rho u, E_t] of Sec. 4.1 is a transposition; the L2 error is
+  invariant under it);
+* ideal gas, p = (gamma-1)(E - rho|u|^2/2), T = p/rho (R = 1), c = sqrt(gamma p/rho);
+* MUSCL acts on primitive variables (rho, u, v, (w), p) with
+  q_L = q_i + mm(q_i - q_{i-1}, q_{i+1} - q_i)/2,
+  q_R = q_{i+1} - mm(q_{i+1} - q_i, q_{i+2} - q_{i+1})/2,
+  mm(a, b) = 0 if a*b <= 0, a if |a| <= |b|, else b;
+* Rusanov flux with wave speed a = max(|u_n,L| + c_L, |u_n,R| + c_R);
+* viscous terms: Stokes hypothesis and q = -k grad T (eq. 11) with constant mu,
+  k = mu*gamma/((gamma-1) Pr); the energy equation is read in its standard form
+  dE/dt + div((E+p)u) = div(tau.u) - div(q) (the printed line repeats k and mu);
+  face gradients: two-point difference along the face normal, the average of
+  the two neighbouring cells' central differences along the face;
+* assembly f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d over d = x, y, z in
+  that order, with 1/dx_d rounded once.
+
+Every formula below is written in one fixed operation order (no fused
+multiply-add; left-to-right evaluation), which is the natural reading of the
+formula.  Branches of |.|, max and minmod are written with explicit `where` so
+that derivatives follow the branch the evaluation took (ties: |0|' = +1, max
+tie takes the left state, minmod tie |a| = |b| takes a).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+EULER = "euler"
+NS = "ns"
+FIRST_ORDER = "first"
+MUSCL = "muscl"
+
+
+@dataclass
+class Problem:
+    """Periodic box, physics and discretisation of f (Sec. 3.2)."""
+
+    n: tuple            # cells per direction, (nx, ny) or (nx, ny, nz)
+    lo: tuple           # lower corner per direction
+    hi: tuple           # upper corner per direction
+    physics: str = EULER
+    recon: str = FIRST_ORDER
+    gamma: float = 1.4
+    mu: float = 0.0
+    prandtl: float = 0.72
+    dtype: torch.dtype = field(default=torch.float64)
+
+    @property
+    def ndim(self) -> int:
+        return len(self.n)
+
+    @property
+    def nvar(self) -> int:
+        return self.ndim + 2
+
+    @property
+    def ncell(self) -> int:
+        return int(math.prod(self.n))
+
+    @property
+    def size(self) -> int:
+        return self.nvar * self.ncell
+
+    @property
+    def shape(self) -> tuple:
+        """Tensor shape of the state: variable-major, x fastest."""
+        return (self.nvar,) + tuple(reversed(self.n))
+
+    def dx(self, d: int) -> float:
+        return (self.hi[d] - self.lo[d]) / self.n[d]
+
+    def invdx(self, d: int) -> float:
+        return 1.0 / self.dx(d)
+
+
+def _at(a: torch.Tensor, s: int, d: int) -> torch.Tensor:
+    """Periodic neighbour: value at cell index + s along direction d (x = 0)."""
+    return torch.roll(a, shifts=-s, dims=-1 - d)
+
+
+def _absw(x):
+    return torch.where(x >= 0, x, -x)
+
+
+def _minmod(a, b):
+    zero = torch.zeros_like(a)
+    pick = torch.where(_absw(a) <= _absw(b), a, b)
+    return torch.where(a * b <= 0, zero, pick)
+
+
+def primitives(P: Problem, U):
+    """Conserved -> primitive variables (rho, velocity list, p) per cell."""
+    D = P.ndim
+    gm1 = P.gamma - 1.0
+    r = U[0]
+    vel = [U[1 + d] / r for d in range(D)]
+    E = U[D + 1]
+    ke = vel[0] * vel[0]
+    for d in range(1, D):
+        ke = ke + vel[d] * vel[d]
+    p = gm1 * (E - 0.5 * r * ke)
+    return r, vel, p
+
+
+def conserved(P: Problem, r, vel, p):
+    """Primitive -> conserved variables (list of nvar tensors)."""
+    D = P.ndim
+    gm1 = P.gamma - 1.0
+    ke = vel[0] * vel[0]
+    for d in range(1, D):
+        ke = ke + vel[d] * vel[d]
+    E = p / gm1 + 0.5 * r * ke
+    return [r] + [r * vel[d] for d in range(D)] + [E]
+
+
+def _euler_flux(P: Problem, U, vel, p, d):
+    """Physical inviscid flux along direction d, from conserved and primitive states."""
+    D = P.ndim
+    un = vel[d]
+    F = [U[1 + d]]
+    for e in range(D):
+        if e == d:
+            F.append(U[1 + e] * un + p)
+        else:
+            F.append(U[1 + e] * un)
+    F.append((U[D + 1] + p) * un)
+    return F
+
+
+def _rusanov(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, d):
+    g = P.gamma
+    cL = torch.sqrt(g * pL / rL)
+    cR = torch.sqrt(g * pR / rR)
+    sL = _absw(vL[d]) + cL
+    sR = _absw(vR[d]) + cR
+    a = torch.where(sL >= sR, sL, sR)
+    FL = _euler_flux(P, UL, vL, pL, d)
+    FR = _euler_flux(P, UR, vR, pR, d)
+    return [0.5 * (FL[m] + FR[m]) - 0.5 * a * (UR[m] - UL[m]) for m in range(P.nvar)]
+
+
+def _face_states(P: Problem, U, r, vel, p, d):
+    """Left/right states at the face c+1/2 along d, for every cell c."""
+    D = P.ndim
+    if P.recon == FIRST_ORDER:
+        UL = list(U)
+        UR = [_at(u, 1, d) for u in U]
+        return (UL, r, vel, p), (UR, _at(r, 1, d), [_at(u, 1, d) for u in vel], _at(p, 1, d))
+    if P.recon != MUSCL:
+        raise ValueError(f"unknown reconstruction {P.recon!r}")
+    q = [r] + list(vel) + [p]
+    qL, qR = [], []
+    for a in q:
+        am1, ap1, ap2 = _at(a, -1, d), _at(a, 1, d), _at(a, 2, d)
+        qL.append(a + 0.5 * _minmod(a - am1, ap1 - a))
+        qR.append(ap1 - 0.5 * _minmod(ap1 - a, ap2 - ap1))
+    rL, vL, pL = qL[0], qL[1:1 + D], qL[D + 1]
+    rR, vR, pR = qR[0], qR[1:1 + D], qR[D + 1]
+    return (conserved(P, rL, vL, pL), rL, vL, pL), (conserved(P, rR, vR, pR), rR, vR, pR)
+
+
+def _viscous_flux(P: Problem, r, vel, p, d):
+    """Viscous flux (tau row and energy term) at the face c+1/2 along d."""
+    D = P.ndim
+    mu = P.mu
+    c23mu = (2.0 / 3.0) * mu
+    kappa = mu * P.gamma / ((P.gamma - 1.0) * P.prandtl)
+    T = p / r
+    inv = [P.invdx(b) for b in range(D)]
+
+    def grad(a, b):
+        """d u_a / d x_b at the face c+1/2 along d."""
+        u = vel[a]
+        if b == d:
+            return (_at(u, 1, d) - u) * inv[d]
+        h = 0.5 * inv[b]
+        gc = (_at(u, 1, b) - _at(u, -1, b)) * h
+        return 0.5 * (gc + _at(gc, 1, d))
+
+    G = [[grad(a, b) for b in range(D)] for a in range(D)]
+    div = G[0][0]
+    for a in range(1, D):
+        div = div + G[a][a]
+    tau = []
+    for a in range(D):
+        if a == d:
+            tau.append(mu * (G[a][d] + G[d][a]) - c23mu * div)
+        else:
+            tau.append(mu * (G[a][d] + G[d][a]))
+    uf = [0.5 * (vel[a] + _at(vel[a], 1, d)) for a in range(D)]
+    work = uf[0] * tau[0]
+    for a in range(1, D):
+        work = work + uf[a] * tau[a]
+    dTdn = (_at(T, 1, d) - T) * inv[d]
+    energy = work + kappa * dTdn
+    return [torch.zeros_like(r)] + tau + [energy]
+
+
+def residual(P: Problem, y: torch.Tensor) -> torch.Tensor:
+    """f(y) for a flat state vector y of length P.size (float64)."""
+    U = y.reshape(P.shape)
+    U = [U[m] for m in range(P.nvar)]
+    r, vel, p = primitives(P, U)
+    out = None
+    for d in range(P.ndim):
+        (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, d)
+        Fh = _rusanov(P, UL, rL, vL, pL, UR, rR, vR, pR, d)
+        if P.physics == NS:
+            Fv = _viscous_flux(P, r, vel, p, d)
+            Fh = [Fh[m] - Fv[m] for m in range(P.nvar)]
+        elif P.physics != EULER:
+            raise ValueError(f"unknown physics {P.physics!r}")
+        inv = P.invdx(d)
+        term = torch.stack([(_at(Fh[m], -1, d) - Fh[m]) * inv for m in range(P.nvar)])
+        out = term if out is None else out + term
+    return out.reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# Jacobian-vector products (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+SQRT_EPS = math.sqrt(2.0 ** -52)
+
+
+def fd_epsilon(y: torch.Tensor, v: torch.Tensor) -> float:
+    """Default finite-difference increment: sqrt(eps_mach) (1 + ||y||) / ||v||.
+
+    The paper defers the choice of epsilon to the truncation/round-off balance
+    (Sec. 2.3); this is that balance for a per-entry perturbation of about
+    sqrt(eps_mach) times the size of y.
+    """
+    ny = math.sqrt(float(torch.dot(y, y)))
+    nv = math.sqrt(float(torch.dot(v, v)))
+    return SQRT_EPS * (1.0 + ny) / nv
+
+
+def jvp_fd(P: Problem, y, fy, v, eps: float):
+    """First-order finite-difference J(y) v = (f(y + eps v) - f(y)) / eps (Sec. 2.3, eq. 10)."""
+    return (residual(P, y + eps * v) - fy) / eps
+
+
+def jvp_exact(P: Problem, y, v):
+    """Exact J(y) v: forward-mode derivative of residual() (Sec. 2.3, exact products)."""
+    _, t = torch.func.jvp(lambda z: residual(P, z), (y,), (v,))
+    return t
+
+
+def vjp(P: Problem, y, wbar):
+    """Adjoint product J(y)^T wbar, by reverse-mode differentiation of residual()."""
+    z = y.detach().clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(residual(P, z), z, wbar)
+    return g
+
+
+def vjp_second(P: Problem, y, v, wbar):
+    """Second-order adjoint d/dt [J(y + t v)^T wbar] at t = 0 (forward-over-reverse)."""
+    _, t = torch.func.jvp(lambda z: vjp_fn(P, z, wbar), (y,), (v,))
+    return t
+
+
+def vjp_fn(P: Problem, y, wbar):
+    _, pull = torch.func.vjp(lambda z: residual(P, z), y)
+    return pull(wbar)[0]
+
+
+def dense_jacobian_fd(P: Problem, y, delta: float = 1e-6):
+    """Brute-force Jacobian by column-wise central differences (tiny grids only)."""
+    N = y.numel()
+    J = torch.empty(N, N, dtype=torch.float64)
+    for c in range(N):
+        e = torch.zeros(N, dtype=torch.float64)
+        e[c] = delta
+        J[:, c] = (residual(P, y + e) - residual(P, y - e)) / (2.0 * delta)
+    return J
