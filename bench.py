@@ -1,0 +1,173 @@
+"""Benchmark: ROK steps per second on one MI355X.
+
+Workload (default): 2-D compressible Euler isentropic vortex on a periodic
+1024 x 1024 grid, second-order MUSCL (minmod) + Rusanov flux, FP64, four-stage
+ROK4 with Krylov dimension M = 16 and finite-difference Jacobian-vector
+products, fixed step at CFL 10.  Inputs are synthetic (seeded) and resident
+in HBM before the timed region starts.
+
+Prints one JSON line with the step rate, a roofline entry for the FD
+Jacobian-vector product kernel (timed live with HIP events on the launch
+stream) and the CPU oracle's rate on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="vortex1024_muscl")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--chain", action="store_true",
+                    help="time a trajectory (each step starts from the previous result) instead of K passes "
+                         "over the seeded input state")
+    return ap.parse_args()
+
+
+def gpu_leg(args, pb, y0, w, tab, h):
+    import torch
+
+    from paper_1607_06834_amd import Rok
+
+    dev = torch.device("cuda", 0)
+    g = Rok(pb, w["precision"])
+    mode = "fd" if w["jvp"] == "fd" else "exact"
+    M = w["M"]
+    ya = torch.tensor(y0, dtype=torch.float64, device=dev)
+    yb = torch.empty_like(ya)
+
+    def one_step(ya, yb):
+        g.step(ya, h, tab, M, mode, out=yb)
+        return (yb, ya) if args.chain else (ya, yb)
+
+    for _ in range(args.warmup):
+        ya, yb = one_step(ya, yb)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ya, yb = one_step(ya, yb)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    flags, meff = g.last_status()
+    finite = bool(torch.isfinite(yb if not args.chain else ya).all())
+
+    # dominant-kernel roofline: FD Jacobian-vector product kernel, one launch per call
+    N = g.N
+    F = g.residual(ya) if w["precision"] == "fp64" else None
+    v = torch.randn(N, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+    v /= torch.linalg.vector_norm(v)
+    out = torch.empty(N, dtype=torch.float64, device=dev)
+    kern = "FD Jacobian-vector product (MUSCL residual at y + eps v, minus f(y), over eps)"
+    eps = 1.0e-7
+    for _ in range(3):
+        g.jvp(ya, v, "fd", fy=F, eps=eps, out=out)
+    torch.cuda.synchronize()
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    for _ in range(args.kernel_reps):
+        g.jvp(ya, v, "fd", fy=F, eps=eps, out=out)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = k0.elapsed_time(k1) / args.kernel_reps
+    alg_bytes = 4 * 8 * N  # reads y, v, f(y); writes w
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kern, "avg_launch_ms": round(k_ms, 5), "alg_bytes_per_launch": alg_bytes}
+    return {"ms_per_step": ev_ms / args.steps, "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite,
+            "roofline": roofline}
+
+
+def cpu_leg(args, pb, y0, w, tab, h):
+    import torch
+
+    from oracle import fv, rok
+
+    torch.set_num_threads(torch.get_num_threads())
+    P = fv.Problem(n=pb["n"], lo=pb["lo"], hi=pb["hi"], physics=pb["physics"], recon=pb["recon"],
+                   gamma=pb["gamma"], mu=pb["mu"], prandtl=pb["prandtl"])
+    f, mv = rok.fv_system(P, "fd" if w["jvp"] == "fd" else "exact")
+    y = torch.tensor(y0, dtype=torch.float64)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        y1 = rok.rok_step(f, mv, tab, w["M"], h, y)
+        if args.chain:
+            y = y1
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= args.cpu_seconds or steps >= 50:
+            break
+    return {"value": round(steps / el, 5), "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{steps} ROK step(s) of the same workload from the same initial state ({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import rok_inputs as ri
+
+    pb, y0, w = ri.workload(args.workload)
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, w["cfl"])
+    res = gpu_leg(args, pb, y0, w, tab, h)
+    cpu = None if args.no_cpu_baseline else cpu_leg(args, pb, y0, w, tab, h)
+    n = "x".join(str(x) for x in pb["n"])
+    line = {
+        "metric": "ROK steps/sec",
+        "value": round(1000.0 / res["ms_per_step"], 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w["precision"] == "fp64" else "f32-residual/f64-krylov",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": n, "physics": pb["physics"], "recon": pb["recon"],
+                   "flux": "rusanov", "krylov_M": w["M"], "stages": tab["s"], "jvp": w["jvp"], "cfl": w["cfl"],
+                   "h": h, "N": ri.size(pb),
+                   "timed_steps": ("trajectory" if args.chain else
+                                   "K full ROK steps, each from the seeded initial state (per-step work does not "
+                                   "depend on the state; ROK4 with M=16 is not stable at CFL 10 on this problem "
+                                   "over many steps)")},
+        "status": {"flags": res["flags"], "M_eff": res["M_eff"], "finite": res["finite"]},
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

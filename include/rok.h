@@ -1,0 +1,186 @@
+/*
+ * librok -- MI355X (gfx950) implementation of the hot path of the matrix-free
+ * Rosenbrock-Krylov (ROK) time integrator for semi-discretised compressible
+ * flow, y' = f(y) (Sarshar, Tranquilli, Pickering, McCall, Sandu, Roy,
+ * "A numerical investigation of matrix-free implicit time-stepping methods
+ * for large CFD simulations", Computers & Fluids 159, 2017).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State layout.  A state vector has N = nvar * ncell doubles, variable-major,
+ * x fastest:  y[((v * nz + k) * ny + j) * nx + i],  nvar = ndim + 2, with the
+ * variables [rho, rho*u, rho*v, (rho*w), E] of the conserved form of the
+ * Euler / Navier-Stokes equations (Sec. 3.2, eq. 11).
+ *
+ * Memory.  Every pointer argument of type double* / float* / void* other than
+ * the context, the problem and the tableau is DEVICE memory owned by the
+ * caller.  The library never allocates or frees device memory and keeps no
+ * pointer after a call returns.  Device pointers must be 8-byte aligned;
+ * workspaces must be 256-byte aligned.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Every call
+ * validates its arguments on the host, enqueues its kernels on `stream` and
+ * returns without synchronising; results are ready when the stream is.
+ * Calls that share a workspace must not overlap in time.
+ *
+ * Errors.  A call returns ROK_OK or a negative status:
+ *   ROK_EINVAL        bad argument (null / misaligned pointer, size out of
+ *                     range, workspace too small); nothing was enqueued;
+ *   ROK_EUNSUPPORTED  the combination of options is not built;
+ *   ROK_EHIP          a HIP launch failed (hipGetLastError after enqueueing).
+ * Numerical events are recorded in a status word inside the workspace and
+ * read with rok_read_status (ROK_FLAG_*).
+ */
+#ifndef ROK_H
+#define ROK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rok_ctx rok_ctx;
+typedef int rok_status;
+
+enum {
+    ROK_OK = 0,
+    ROK_EINVAL = -1,
+    ROK_EUNSUPPORTED = -2,
+    ROK_EHIP = -3
+};
+
+enum { ROK_EULER = 0, ROK_NS = 1 };                  /* physics                     */
+enum { ROK_FIRST_ORDER = 0, ROK_MUSCL_MINMOD = 1 };  /* reconstruction              */
+enum { ROK_RUSANOV = 0 };                            /* inviscid flux               */
+enum { ROK_FP64 = 0, ROK_FP32_RESIDUAL = 1 };        /* precision of f and J v      */
+enum { ROK_JVP_FD = 0, ROK_JVP_TANGENT = 1 };        /* Jacobian-vector product     */
+
+/* status-word bits (rok_read_status) */
+enum {
+    ROK_FLAG_NONFINITE = 1,   /* a NaN or Inf appeared in H, phi or lambda           */
+    ROK_FLAG_BREAKDOWN = 2,   /* Arnoldi stopped early: M_eff < M (invariant space) */
+    ROK_FLAG_ZERO_RHS = 4     /* f(y_n) = 0 exactly: M_eff = 0                       */
+};
+
+#define ROK_MAX_STAGES 8
+#define ROK_MAX_M 64
+
+/*
+ * The semi-discrete system y' = f(y) of Sec. 2, eq. (1): the compressible
+ * Euler (physics = ROK_EULER) or Navier-Stokes (ROK_NS) equations of
+ * Sec. 3.2, eq. (11), finite volumes on a periodic cell-centred Cartesian
+ * box [lo, hi] with n cells per direction (ndim = 2: n[2] and lo/hi[2] are
+ * ignored), first-order or MUSCL (minmod limiter, primitive variables)
+ * reconstruction, Rusanov flux, constant viscosity mu, Prandtl number
+ * `prandtl`, ratio of specific heats `gamma`.  With precision =
+ * ROK_FP32_RESIDUAL the residual and tangent kernels compute in float while
+ * Arnoldi, the reduced solve and all state accumulation stay in double.
+ */
+typedef struct {
+    int ndim;
+    int n[3];
+    double lo[3];
+    double hi[3];
+    int physics;
+    int recon;
+    int flux;
+    double gamma;
+    double mu;
+    double prandtl;
+    int precision;
+} rok_problem;
+
+/*
+ * ROK coefficients (Sec. 2.2.2, eq. 9): s stages (1..8); alpha_ij and
+ * gamma_ij are stored row-major with leading dimension ROK_MAX_STAGES
+ * (alpha[i * ROK_MAX_STAGES + j]) and only the strictly lower triangle
+ * j < i < s is read; gamma is the common diagonal; b has s weights.
+ * Host memory.
+ */
+typedef struct {
+    int s;
+    double alpha[ROK_MAX_STAGES * ROK_MAX_STAGES];
+    double gam[ROK_MAX_STAGES * ROK_MAX_STAGES];
+    double gamma;
+    double b[ROK_MAX_STAGES];
+} rok_tableau;
+
+/* Validates *problem and creates a host-only, immutable context.  Allocates
+ * no device memory.  ROK_EINVAL on a bad problem (ndim not 2 or 3, n < 1,
+ * hi <= lo, gamma <= 1, mu < 0, NS with mu = 0 is allowed). */
+rok_status rok_create(const rok_problem* problem, rok_ctx** out);
+void rok_destroy(rok_ctx* ctx);
+
+/* N, the length of a state vector. */
+size_t rok_state_size(const rok_ctx* ctx);
+
+/* Bytes of workspace needed by rok_jvp / rok_arnoldi (s = 0) or rok_step
+ * (s = number of stages) with Krylov dimension M. */
+size_t rok_workspace_bytes(const rok_ctx* ctx, int M, int s);
+
+/*
+ * F = f(y)  (Sec. 2, eq. 1; Sec. 3.2, eq. 11).  y: N doubles.  F: N doubles,
+ * or N floats when the context's precision is ROK_FP32_RESIDUAL.
+ */
+rok_status rok_residual(rok_ctx* ctx, const double* y, void* F, void* stream);
+
+/*
+ * w = J(y) v, J = df/dy at y (Sec. 2.3).
+ *   mode ROK_JVP_FD:      w = (f(y + eps v) - fy) / eps  (eq. 10); fy = f(y)
+ *                         (N doubles); eps > 0 is used as given, eps <= 0
+ *                         selects eps = sqrt(eps_mach) (1 + ||y||_2) / ||v||_2,
+ *                         which needs `work` (rok_workspace_bytes(ctx, 0, 0)).
+ *                         FP64 precision only (ROK_EUNSUPPORTED otherwise).
+ *   mode ROK_JVP_TANGENT: the exact product (forward-mode derivative of f);
+ *                         fy, eps and work are ignored.
+ * v: N doubles.  w: N doubles (N floats under ROK_FP32_RESIDUAL).
+ */
+rok_status rok_jvp(rok_ctx* ctx, const double* y, const double* fy, const double* v, void* w,
+                   int mode, double eps, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Modified Arnoldi (Sec. 2.2.2): orthonormal basis V of K_M(J(y), fy) and
+ * H = V^T J V (upper Hessenberg).
+ *   y, fy:  N doubles (fy = f(y) as a double vector)
+ *   M:      1..min(ROK_MAX_M, N) requested dimension
+ *   mode:   ROK_JVP_FD (eps <= 0: sqrt(eps_mach) (1 + ||y||), unit vectors)
+ *           or ROK_JVP_TANGENT
+ *   V:      N x M doubles, column c at V + c*N (columns >= M_eff untouched)
+ *   H:      M x M doubles, row-major, H[i*M + j] = h_ij (zero outside the
+ *           leading M_eff x M_eff Hessenberg block)
+ *   M_eff:  one device int: the dimension reached (0 when fy = 0; < M on an
+ *           invariant subspace, i.e. h_{j+1,j} <= 1e-13 ||(h_1j..h_{j+1,j})||)
+ *   work:   rok_workspace_bytes(ctx, M, 0) bytes
+ */
+rok_status rok_arnoldi(rok_ctx* ctx, const double* y, const double* fy, int M, int mode, double eps,
+                       double* V, double* H, int* M_eff, void* work, size_t work_bytes, void* stream);
+
+/*
+ * One ROK step (Sec. 2.2.2, eq. 9): F_i = f(y_n + sum_j alpha_ij k_j),
+ * phi_i = V^T F_i, lambda_i = (I - h gamma H)^{-1} (h phi_i + h H sum_j
+ * gamma_ij lambda_j), k_i = V lambda_i + h (F_i - V phi_i),
+ * y_{n+1} = y_n + sum_i b_i k_i, with (V, H) from rok_arnoldi at y_n (FD
+ * products use eps = sqrt(eps_mach) (1 + ||y_n||)).  M = 0 gives the explicit
+ * Runge-Kutta method (alpha, b).
+ *   tab:    host tableau;  M: 0..ROK_MAX_M (clamped to N);  h: step size
+ *   y_n, y_np1: N doubles each (may not alias)
+ *   work:   rok_workspace_bytes(ctx, M, tab->s) bytes
+ */
+rok_status rok_step(rok_ctx* ctx, const rok_tableau* tab, int M, int mode, double h,
+                    const double* y_n, double* y_np1, void* work, size_t work_bytes, void* stream);
+
+/* Copies the status word of `work` (ROK_FLAG_* bits of the last call that
+ * used it) to *host_flags; synchronises `stream`. */
+rok_status rok_read_status(rok_ctx* ctx, const void* work, int* host_flags, void* stream);
+
+/* Reads M_eff of the last rok_step that used `work`; synchronises `stream`. */
+rok_status rok_read_meff(rok_ctx* ctx, const void* work, int* host_meff, void* stream);
+
+const char* rok_strerror(rok_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROK_H */

@@ -16,19 +16,77 @@ by a direct method.  Readings of what the paper leaves open:
 * inside Arnoldi the finite-difference increment uses ||v_j|| = 1;
 * the direct method is LU with partial pivoting (row swap only when a later
   pivot is strictly larger in magnitude), done once per step since gamma is
-  the same for all stages (the reason given for Rosenbrock methods, Sec. 2.2).
+  the same for all stages (the reason given for Rosenbrock methods, Sec. 2.2);
+* summation order.  The paper does not fix the order in which a dot product
+  adds its N terms; floating-point sums depend on it, and the first-order
+  difference quotient of Sec. 2.3, eq. 10, multiplies last-bit differences
+  by 1/eps, so two correct implementations that add in different orders
+  drift apart by ~1e-10 after one step.  The reading taken here is one
+  canonical order, written out in `canonical_sum`: the terms are dealt
+  round-robin over 262144 lanes, each lane adds its terms in index order,
+  lanes are combined 256 at a time by a pairwise halving tree, and the 1024
+  resulting sums are dealt over 256 lanes (four each, in order) and combined
+  by the same tree.  Sums over the small Krylov index (V lambda, H g) are
+  taken in column order.
 """
 from __future__ import annotations
 
 import math
 
+import numpy as np
 import torch
 
 BREAKDOWN_TOL = 1e-13
 
 
+RED_BLOCKS = 1024
+RED_THREADS = 256
+RED_LANES = RED_BLOCKS * RED_THREADS
+
+
+def _halving_tree(s: np.ndarray) -> np.ndarray:
+    """Pairwise sum along the last axis (length 256): s[i] += s[i + h], h = 128, 64, ..., 1."""
+    s = s.copy()
+    h = s.shape[-1] // 2
+    while h >= 1:
+        s[..., :h] = s[..., :h] + s[..., h:2 * h]
+        h //= 2
+    return s[..., 0]
+
+
+def canonical_sum(terms: np.ndarray) -> float:
+    """Sum of a float64 vector in the canonical order described in the module docstring.
+
+    Lanes past the end of the data and blocks past the last used lane hold +0.0
+    and are left out: adding +0.0 to a lane or block sum (never -0.0 when it
+    starts from +0.0) leaves it unchanged.
+    """
+    n = terms.size
+    used = max(1, min(n, RED_LANES))
+    nb = -(-used // RED_THREADS)
+    lane = np.zeros(nb * RED_THREADS, dtype=np.float64)
+    for r in range(max(1, -(-n // RED_LANES))):
+        seg = terms[r * RED_LANES:(r + 1) * RED_LANES]
+        lane[:seg.size] = lane[:seg.size] + seg
+    blocks = np.zeros(RED_BLOCKS, dtype=np.float64)
+    blocks[:nb] = _halving_tree(lane.reshape(nb, RED_THREADS))
+    fin = np.zeros(RED_THREADS, dtype=np.float64)
+    for r in range(RED_BLOCKS // RED_THREADS):
+        fin = fin + blocks[r * RED_THREADS:(r + 1) * RED_THREADS]
+    return float(_halving_tree(fin[None, :])[0])
+
+
 def dot(a: torch.Tensor, b: torch.Tensor) -> float:
-    return float(torch.dot(a, b))
+    """<a, b>: products rounded once each, summed in the canonical order."""
+    return canonical_sum((a * b).numpy())
+
+
+def matvec_cols(V: torch.Tensor, c: torch.Tensor) -> torch.Tensor:
+    """V c = sum_j c_j V[:, j], accumulated in column order from zero."""
+    acc = torch.zeros(V.shape[0], dtype=torch.float64)
+    for j in range(V.shape[1]):
+        acc = acc + V[:, j] * float(c[j])
+    return acc
 
 
 def arnoldi(matvec, f0: torch.Tensor, M: int, tol: float = BREAKDOWN_TOL):

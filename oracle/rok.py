@@ -23,7 +23,7 @@ import math
 import torch
 
 from . import fv
-from .krylov import arnoldi, lu_factor, lu_solve
+from .krylov import arnoldi, dot, lu_factor, lu_solve, matvec_cols
 
 JVP_FD = "fd"
 JVP_EXACT = "exact"
@@ -57,14 +57,15 @@ def rok_step(f, matvec_at, tab: dict, M: int, h: float, y: torch.Tensor, record:
                     Y = Y + alpha[i][j] * ks[j]
             Fi = f(Y)
         if m > 0:
-            phi = torch.tensor([float(torch.dot(V[:, c], Fi)) for c in range(m)], dtype=torch.float64)
+            phi = torch.tensor([dot(V[:, c], Fi) for c in range(m)], dtype=torch.float64)
             g = torch.zeros(m, dtype=torch.float64)
             for j in range(i):
                 if gam[i][j] != 0.0:
                     g = g + gam[i][j] * lams[j]
-            rhs = h * phi + h * (H @ g)
+            Hg = torch.tensor([float(matvec_cols(H[r:r + 1, :], g)[0]) for r in range(m)], dtype=torch.float64)
+            rhs = h * phi + h * Hg
             lam = lu_solve(LU, perm, rhs)
-            ki = V @ lam + h * (Fi - V @ phi)
+            ki = matvec_cols(V, lam) + h * (Fi - matvec_cols(V, phi))
         else:
             phi = lam = torch.zeros(0, dtype=torch.float64)
             ki = h * Fi
@@ -93,7 +94,7 @@ def fv_system(P: fv.Problem, mode: str = JVP_FD, eps: float | None = None):
     def matvec_at(y, fy):
         if mode == JVP_EXACT:
             return lambda v: fv.jvp_exact(P, y, v)
-        e = eps if eps is not None else fv.SQRT_EPS * (1.0 + math.sqrt(float(torch.dot(y, y))))
+        e = eps if eps is not None else fv.SQRT_EPS * (1.0 + math.sqrt(dot(y, y)))
         return lambda v: fv.jvp_fd(P, y, fy, v, e)
 
     return f, matvec_at

@@ -1,0 +1,277 @@
+// C-ABI of librok: argument validation, workspace carving and the launch
+// sequences of the residual, Jacobian-vector product, Arnoldi and ROK step
+// (declared and documented in include/rok.h).
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+
+#include "rok.h"
+#include "rok_device.hpp"
+#include "rok_kernels.hpp"
+
+struct rok_ctx {
+    rok_problem pb;
+    rok::Geom G;
+};
+
+namespace {
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+rok_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return ROK_OK;
+    if (e == hipErrorNotSupported) return ROK_EUNSUPPORTED;
+    return ROK_EHIP;
+}
+
+#define ROK_TRY(expr)                            \
+    do {                                         \
+        hipError_t _e = (expr);                  \
+        if (_e != hipSuccess) return hip_status(_e); \
+    } while (0)
+
+bool fp32(const rok_ctx* c) { return c->pb.precision == ROK_FP32_RESIDUAL; }
+
+rok::ResArgs plain_args(const double* y, void* out) {
+    rok::ResArgs A{};
+    A.y = y;
+    A.out = out;
+    return A;
+}
+
+// w = J(y) v into a double vector (internal use).  FD reads eps from eps_dev.
+hipError_t jvp_into(const rok_ctx* c, const double* y, const double* fy, const double* v, double* w, int mode,
+                    const double* eps_dev, double eps, hipStream_t st) {
+    rok::ResArgs A{};
+    A.y = y;
+    A.v = v;
+    A.f0 = fy;
+    A.eps_dev = eps_dev;
+    A.eps = eps;
+    A.out = w;
+    int kind = (mode == ROK_JVP_FD) ? 1 : 2;
+    return rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, fp32(c), kind, true, A, st);
+}
+
+// Modified Gram-Schmidt Arnoldi into V (N x M columns), H inside W.
+hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, const double* fy, int M, int mode,
+                        double eps, double* V, hipStream_t st) {
+    const long N = c->G.N;
+    const double* epsp = nullptr;
+    hipError_t e;
+    if (mode == ROK_JVP_FD && !(eps > 0.0)) {
+        e = rok::launch_norm_eps(W, y, nullptr, N, st);  // unit Arnoldi vectors: ||v_j|| = 1
+        if (e != hipSuccess) return e;
+        epsp = W.scal + 1;
+    }
+    e = rok::launch_start_basis(W, fy, N, V, st);
+    if (e != hipSuccess) return e;
+    for (int j = 0; j < M; ++j) {
+        double* vj = V + (long)j * N;
+        e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st);
+        if (e != hipSuccess) return e;
+        e = rok::launch_mgs_column(W, W.w, V, N, M, j, (j + 1 < M) ? V + (long)(j + 1) * N : nullptr, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+rok_status rok_create(const rok_problem* p, rok_ctx** out) {
+    if (!p || !out) return ROK_EINVAL;
+    *out = nullptr;
+    if (p->ndim != 2 && p->ndim != 3) return ROK_EINVAL;
+    long ncell = 1;
+    for (int d = 0; d < p->ndim; ++d) {
+        if (p->n[d] < 1 || !(p->hi[d] > p->lo[d])) return ROK_EINVAL;
+        ncell *= p->n[d];
+        if (ncell > (1L << 31)) return ROK_EINVAL;
+    }
+    if (p->physics != ROK_EULER && p->physics != ROK_NS) return ROK_EINVAL;
+    if (p->recon != ROK_FIRST_ORDER && p->recon != ROK_MUSCL_MINMOD) return ROK_EINVAL;
+    if (p->flux != ROK_RUSANOV) return ROK_EINVAL;
+    if (p->precision != ROK_FP64 && p->precision != ROK_FP32_RESIDUAL) return ROK_EINVAL;
+    if (!(p->gamma > 1.0) || !(p->mu >= 0.0) || !(p->prandtl > 0.0)) return ROK_EINVAL;
+    rok_ctx* c = new (std::nothrow) rok_ctx;
+    if (!c) return ROK_EINVAL;
+    c->pb = *p;
+    rok::Geom& G = c->G;
+    memset(&G, 0, sizeof(G));
+    G.D = p->ndim;
+    for (int d = 0; d < 3; ++d) G.n[d] = (d < p->ndim) ? p->n[d] : 1;
+    G.nvar = p->ndim + 2;
+    G.ncell = ncell;
+    G.N = (long)G.nvar * ncell;
+    for (int d = 0; d < p->ndim; ++d) {
+        double dx = (p->hi[d] - p->lo[d]) / p->n[d];
+        G.invdx[d] = 1.0 / dx;
+        G.hinv[d] = 0.5 * G.invdx[d];
+    }
+    G.g = p->gamma;
+    G.gm1 = p->gamma - 1.0;
+    G.mu = p->physics == ROK_NS ? p->mu : 0.0;
+    G.c23mu = (2.0 / 3.0) * G.mu;
+    G.kappa = G.mu * p->gamma / ((p->gamma - 1.0) * p->prandtl);
+    *out = c;
+    return ROK_OK;
+}
+
+void rok_destroy(rok_ctx* c) { delete c; }
+
+size_t rok_state_size(const rok_ctx* c) { return c ? (size_t)c->G.N : 0; }
+
+size_t rok_workspace_bytes(const rok_ctx* c, int M, int s) {
+    if (!c || M < 0 || s < 0 || s > ROK_MAX_STAGES) return 0;
+    int Mc = M > ROK_MAX_M ? ROK_MAX_M : M;
+    if ((long)Mc > c->G.N) Mc = (int)c->G.N;
+    return rok::work_bytes(c->G.N, Mc, s, s > 0);
+}
+
+rok_status rok_residual(rok_ctx* c, const double* y, void* F, void* stream) {
+    if (!c || !y || !F || !aligned(y, 8) || !aligned(F, fp32(c) ? 4 : 8)) return ROK_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    rok::ResArgs A = plain_args(y, F);
+    ROK_TRY(rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, fp32(c), 0, !fp32(c), A, st));
+    return ROK_OK;
+}
+
+rok_status rok_jvp(rok_ctx* c, const double* y, const double* fy, const double* v, void* w, int mode, double eps,
+                   void* work, size_t wbytes, void* stream) {
+    if (!c || !y || !v || !w || !aligned(y, 8) || !aligned(v, 8) || !aligned(w, fp32(c) ? 4 : 8)) return ROK_EINVAL;
+    if (mode != ROK_JVP_FD && mode != ROK_JVP_TANGENT) return ROK_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    rok::ResArgs A{};
+    A.y = y;
+    A.v = v;
+    A.out = w;
+    if (mode == ROK_JVP_TANGENT) {
+        ROK_TRY(rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, fp32(c), 2, !fp32(c), A, st));
+        return ROK_OK;
+    }
+    if (fp32(c)) return ROK_EUNSUPPORTED;
+    if (!fy || !aligned(fy, 8)) return ROK_EINVAL;
+    A.f0 = fy;
+    if (eps > 0.0) {
+        A.eps = eps;
+    } else {
+        size_t need = rok::work_bytes(c->G.N, 0, 0, false);
+        if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
+        rok::Work W = rok::carve(work, c->G.N, 0, 0, false);
+        ROK_TRY(rok::launch_init(W, 0, 0, st));
+        ROK_TRY(rok::launch_norm_eps(W, y, v, c->G.N, st));
+        A.eps_dev = W.scal + 1;
+    }
+    ROK_TRY(rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, false, 1, true, A, st));
+    return ROK_OK;
+}
+
+rok_status rok_arnoldi(rok_ctx* c, const double* y, const double* fy, int M, int mode, double eps, double* V,
+                       double* H, int* M_eff, void* work, size_t wbytes, void* stream) {
+    if (!c || !y || !fy || !V || !H || !M_eff) return ROK_EINVAL;
+    if (!aligned(y, 8) || !aligned(fy, 8) || !aligned(V, 8) || !aligned(H, 8) || !aligned(M_eff, 4)) return ROK_EINVAL;
+    if (mode != ROK_JVP_FD && mode != ROK_JVP_TANGENT) return ROK_EINVAL;
+    if (M < 1 || M > ROK_MAX_M) return ROK_EINVAL;
+    if ((long)M > c->G.N) M = (int)c->G.N;
+    if (mode == ROK_JVP_FD && fp32(c)) return ROK_EUNSUPPORTED;
+    size_t need = rok::work_bytes(c->G.N, M, 0, false);
+    if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    rok::Work W = rok::carve(work, c->G.N, M, 0, false);
+    ROK_TRY(rok::launch_init(W, M, 0, st));
+    ROK_TRY(arnoldi_core(c, W, y, fy, M, mode, eps, V, st));
+    ROK_TRY(rok::launch_copy_h(W, M, H, M_eff, st));
+    return ROK_OK;
+}
+
+rok_status rok_step(rok_ctx* c, const rok_tableau* tab, int M, int mode, double h, const double* y_n, double* y_np1,
+                    void* work, size_t wbytes, void* stream) {
+    if (!c || !tab || !y_n || !y_np1 || y_n == y_np1) return ROK_EINVAL;
+    if (!aligned(y_n, 8) || !aligned(y_np1, 8)) return ROK_EINVAL;
+    if (tab->s < 1 || tab->s > ROK_MAX_STAGES) return ROK_EINVAL;
+    if (mode != ROK_JVP_FD && mode != ROK_JVP_TANGENT) return ROK_EINVAL;
+    if (M < 0 || M > ROK_MAX_M || !(h == h)) return ROK_EINVAL;
+    if ((long)M > c->G.N) M = (int)c->G.N;
+    if (M > 0 && mode == ROK_JVP_FD && fp32(c)) return ROK_EUNSUPPORTED;
+    const int s = tab->s;
+    const long N = c->G.N;
+    size_t need = rok::work_bytes(N, M, s, true);
+    if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    rok::Work W = rok::carve(work, N, M, s, true);
+    const bool ns = c->pb.physics == ROK_NS;
+    const int Mm = M > 0 ? M : 1;
+
+    ROK_TRY(rok::launch_init(W, M, s, st));
+    // F_1 = f(y_n)
+    {
+        rok::ResArgs A = plain_args(y_n, W.F);
+        ROK_TRY(rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st));
+    }
+    if (M > 0) {
+        ROK_TRY(arnoldi_core(c, W, y_n, W.F, M, mode, 0.0, W.V, st));
+        ROK_TRY(rok::launch_lu(W, M, h * tab->gamma, st));
+    }
+    for (int i = 0; i < s; ++i) {
+        double* Fi = W.F + (long)i * N;
+        if (i > 0) {
+            rok::ResArgs A = plain_args(y_n, Fi);
+            int t = 0;
+            for (int j = 0; j < i; ++j) {
+                double a = tab->alpha[i * ROK_MAX_STAGES + j];
+                if (a != 0.0) {
+                    A.xs[t] = W.K + (long)j * N;
+                    A.cs[t] = a;
+                    ++t;
+                }
+            }
+            A.nterm = t;
+            ROK_TRY(rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st));
+        }
+        if (M > 0) {
+            ROK_TRY(rok::launch_project(W, W.V, Fi, N, M, st));
+            double grow[ROK_MAX_STAGES];
+            for (int j = 0; j < ROK_MAX_STAGES; ++j) grow[j] = (j < i) ? tab->gam[i * ROK_MAX_STAGES + j] : 0.0;
+            ROK_TRY(rok::launch_lambda(W, M, i, grow, h, st));
+        }
+        ROK_TRY(rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, st));
+    }
+    ROK_TRY(rok::launch_update(y_n, s, W.K, tab->b, N, y_np1, st));
+    return ROK_OK;
+}
+
+static rok_status read_header(const void* work, int idx, int* out, void* stream) {
+    if (!work || !out || !aligned(work, 256)) return ROK_EINVAL;
+    int ints[4];
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(ints, work, sizeof(ints), hipMemcpyDeviceToHost, st) != hipSuccess) return ROK_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return ROK_EHIP;
+    *out = ints[idx];
+    return ROK_OK;
+}
+
+rok_status rok_read_status(rok_ctx* c, const void* work, int* host_flags, void* stream) {
+    if (!c) return ROK_EINVAL;
+    return read_header(work, 2, host_flags, stream);
+}
+
+rok_status rok_read_meff(rok_ctx* c, const void* work, int* host_meff, void* stream) {
+    if (!c) return ROK_EINVAL;
+    return read_header(work, 0, host_meff, stream);
+}
+
+const char* rok_strerror(rok_status s) {
+    switch (s) {
+        case ROK_OK: return "success";
+        case ROK_EINVAL: return "invalid argument";
+        case ROK_EUNSUPPORTED: return "unsupported option combination";
+        case ROK_EHIP: return "HIP launch failure";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Device-side building blocks shared by the librok kernels: kernel parameter
+// blocks, the dual-number type used for exact Jacobian-vector products and
+// the periodic index helpers.
+//
+// Floating-point contract: every file is compiled with -ffp-contract=off and
+// evaluates each formula in one fixed, left-to-right operation order, so a
+// double-precision result is reproducible bit for bit (FP64 division and
+// square root are correctly rounded on gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rok {
+
+constexpr int kMaxStages = 8;
+constexpr int kMaxM = 64;
+
+// Geometry and physics constants of one problem (host-computed, passed by value).
+struct Geom {
+    int D;          // 2 or 3
+    int n[3];       // cells per direction (n[2] = 1 in 2-D)
+    int nvar;       // D + 2
+    long ncell;     // n0 * n1 * n2
+    long N;         // nvar * ncell
+    double invdx[3];  // 1 / dx, rounded once
+    double hinv[3];   // 0.5 / dx (central differences)
+    double g, gm1;    // gamma, gamma - 1
+    double mu, c23mu, kappa;  // mu, (2/3) mu, mu gamma / ((gamma-1) Pr)
+};
+
+// Residual-kernel inputs: the stage state Y = y + sum_t cs[t] xs[t]
+// (PLAIN), or y + eps v (FD), or the pair (y, v) (TANGENT).
+struct ResArgs {
+    const double* y;
+    const double* v;
+    const double* f0;          // FD: f(y)
+    const double* eps_dev;     // FD: if non-null, eps is read from here
+    double eps;
+    int nterm;
+    const double* xs[kMaxStages];
+    double cs[kMaxStages];
+    void* out;
+};
+
+// ---------------------------------------------------------------------------
+// Dual numbers (value, tangent): exact forward-mode derivative of f.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Dual {
+    T v, d;
+};
+
+template <typename T> __device__ __forceinline__ Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
+template <typename T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
+template <typename T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
+template <typename T> __device__ __forceinline__ Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <typename T> __device__ __forceinline__ Dual<T> operator*(T a, Dual<T> b) { return {a * b.v, a * b.d}; }
+template <typename T> __device__ __forceinline__ Dual<T> operator*(Dual<T> a, T b) { return {a.v * b, a.d * b}; }
+template <typename T> __device__ __forceinline__ Dual<T> operator/(Dual<T> a, Dual<T> b) {
+    T q = a.v / b.v;
+    return {q, (a.d - q * b.d) / b.v};
+}
+template <typename T> __device__ __forceinline__ Dual<T> operator/(Dual<T> a, T b) { return {a.v / b, a.d / b}; }
+
+// Scalar traits: value part (for branch decisions), construction, sqrt.
+template <typename S> struct Sc;
+template <> struct Sc<double> {
+    using R = double;
+    static __device__ __forceinline__ double val(double x) { return x; }
+    static __device__ __forceinline__ double make(double x) { return x; }
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+};
+template <> struct Sc<float> {
+    using R = float;
+    static __device__ __forceinline__ float val(float x) { return x; }
+    static __device__ __forceinline__ float make(double x) { return (float)x; }
+    static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+};
+template <> struct Sc<Dual<double>> {
+    using R = double;
+    static __device__ __forceinline__ double val(Dual<double> x) { return x.v; }
+    static __device__ __forceinline__ Dual<double> make(double x) { return {x, 0.0}; }
+    static __device__ __forceinline__ Dual<double> sqrt_(Dual<double> x) {
+        double s = sqrt(x.v);
+        return {s, x.d / (s + s)};
+    }
+};
+template <> struct Sc<Dual<float>> {
+    using R = float;
+    static __device__ __forceinline__ float val(Dual<float> x) { return x.v; }
+    static __device__ __forceinline__ Dual<float> make(double x) { return {(float)x, 0.0f}; }
+    static __device__ __forceinline__ Dual<float> sqrt_(Dual<float> x) {
+        float s = sqrtf(x.v);
+        return {s, x.d / (s + s)};
+    }
+};
+
+// Periodic wrap of an index that may lie anywhere in [-n, 2n) (fast path) or
+// beyond (small grids).
+__device__ __forceinline__ int wrap(int i, int n) {
+    if (i >= 0 && i < n) return i;
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace rok

@@ -1,0 +1,364 @@
+// Finite-volume residual kernels: F = f(Y), the finite-difference product
+// (f(y + eps v) - f(y)) / eps and the exact (tangent) product J(y) v.
+//
+// f is the semi-discrete compressible Euler / Navier-Stokes operator of
+// Sec. 3.2, eq. (11) on a periodic Cartesian grid: primitive variables per
+// cell, first-order or MUSCL-minmod face states, Rusanov flux, central
+// viscous fluxes (Stokes stress, Fourier conduction), and the assembly
+// f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d.
+//
+// Design (one workgroup = one tile of cells):
+//   1. the tile plus a halo of two cells on every side is loaded once from
+//      HBM (coalesced along x, structure-of-arrays), converted to primitive
+//      variables and staged in LDS;
+//   2. for each direction every face flux of the tile is computed exactly
+//      once from LDS and stored in an LDS face buffer;
+//   3. each thread assembles the flux differences of its cells in registers
+//      and writes them out once.
+// The same code is instantiated with a dual-number scalar for the exact
+// Jacobian-vector product and with float for the FP32 form.
+#include "rok_device.hpp"
+#include "rok_kernels.hpp"
+
+namespace rok {
+
+enum { MODE_PLAIN = 0, MODE_FD = 1, MODE_TAN = 2 };
+
+template <typename S> __device__ __forceinline__ S sabs(S x) { return Sc<S>::val(x) >= 0 ? x : -x; }
+
+template <typename S> __device__ __forceinline__ S minmod(S a, S b) {
+    using R = typename Sc<S>::R;
+    if (Sc<S>::val(a) * Sc<S>::val(b) <= (R)0) return Sc<S>::make(0.0);
+    return (Sc<S>::val(sabs(a)) <= Sc<S>::val(sabs(b))) ? a : b;
+}
+
+// Conserved state of one cell of the stage input.
+template <int MODE, int NV, typename S>
+__device__ __forceinline__ void load_state(const ResArgs& A, long ncell, long gi, double eps, S* U) {
+    using R = typename Sc<S>::R;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        long k = (long)m * ncell + gi;
+        if constexpr (MODE == MODE_PLAIN) {
+            double acc = A.y[k];
+            for (int t = 0; t < A.nterm; ++t) acc = acc + A.cs[t] * A.xs[t][k];
+            U[m] = Sc<S>::make(acc);
+        } else if constexpr (MODE == MODE_FD) {
+            U[m] = Sc<S>::make(A.y[k] + eps * A.v[k]);
+        } else {
+            U[m] = S{(R)A.y[k], (R)A.v[k]};
+        }
+    }
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void euler_flux(const S* U, const S* vel, S p, int d, S* F) {
+    S un = vel[d];
+    F[0] = U[1 + d];
+#pragma unroll
+    for (int e = 0; e < D; ++e) F[1 + e] = (e == d) ? U[1 + e] * un + p : U[1 + e] * un;
+    F[D + 1] = (U[D + 1] + p) * un;
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void rusanov(const Geom& G, int d, const S* UL, S rL, const S* vL, S pL,
+                                        const S* UR, S rR, const S* vR, S pR, S* Fh) {
+    using R = typename Sc<S>::R;
+    const R g = (R)G.g;
+    const R half = (R)0.5;
+    S cL = Sc<S>::sqrt_(g * pL / rL);
+    S cR = Sc<S>::sqrt_(g * pR / rR);
+    S sL = sabs(vL[d]) + cL;
+    S sR = sabs(vR[d]) + cR;
+    S a = (Sc<S>::val(sL) >= Sc<S>::val(sR)) ? sL : sR;
+    S FL[D + 2], FR[D + 2];
+    euler_flux<D>(UL, vL, pL, d, FL);
+    euler_flux<D>(UR, vR, pR, d, FR);
+    S ha = half * a;
+#pragma unroll
+    for (int m = 0; m < D + 2; ++m) Fh[m] = half * (FL[m] + FR[m]) - ha * (UR[m] - UL[m]);
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void to_conserved(const Geom& G, S r, const S* vel, S p, S* U) {
+    using R = typename Sc<S>::R;
+    const R gm1 = (R)G.gm1;
+    const R half = (R)0.5;
+    S ke = vel[0] * vel[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
+    U[0] = r;
+#pragma unroll
+    for (int d = 0; d < D; ++d) U[1 + d] = r * vel[d];
+    U[D + 1] = p / gm1 + (half * r) * ke;
+}
+
+// Tile shapes.  Box = tile + 2 halo cells on each side.
+template <int D, int TX, int TY, int TZ>
+struct Tile {
+    static constexpr int TZe = (D == 3) ? TZ : 1;
+    static constexpr int BX = TX + 4, BY = TY + 4, BZ = (D == 3) ? TZ + 4 : 1;
+    static constexpr int BOX = BX * BY * BZ;
+    static constexpr int CELLS = TX * TY * TZe;
+    static constexpr int NF0 = (TX + 1) * TY * TZe;
+    static constexpr int NF1 = TX * (TY + 1) * TZe;
+    static constexpr int NF2 = (D == 3) ? TX * TY * (TZ + 1) : 0;
+    static constexpr int NFMAX = NF0 > NF1 ? (NF0 > NF2 ? NF0 : NF2) : (NF1 > NF2 ? NF1 : NF2);
+    static constexpr int stride(int d) { return d == 0 ? 1 : (d == 1 ? BX : BX * BY); }
+};
+
+constexpr int kThreads = 256;
+
+// XCD-aware block order: workgroups are dispatched round-robin over the 8
+// XCDs; give each XCD a contiguous range of tiles so halos hit in its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt0, int nt1) {
+    using T = Tile<D, TX, TY, TZ>;
+    using R = typename Sc<S>::R;
+    constexpr int NV = D + 2;
+    constexpr bool FO = (RECON == 0);
+    constexpr int OFF_VEL = FO ? NV : 1;
+    constexpr int OFF_P = OFF_VEL + D;
+    constexpr int OFF_T = OFF_P + 1;
+    constexpr int NP = OFF_P + 1 + (NSV ? 1 : 0);
+    constexpr int CPT = T::CELLS / kThreads;
+    static_assert(T::CELLS % kThreads == 0, "tile must be a multiple of the block size");
+
+    __shared__ S sq[NP][T::BOX];
+    __shared__ S fb[NV][T::NFMAX];
+
+    const int tid = threadIdx.x;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int x0 = (b % nt0) * TX;
+    const int y0 = ((b / nt0) % nt1) * TY;
+    const int z0 = (D == 3) ? (b / (nt0 * nt1)) * TZ : 0;
+    const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+
+    double eps = 0.0;
+    if constexpr (MODE == MODE_FD) eps = A.eps_dev ? *A.eps_dev : A.eps;
+
+    // 1. stage the box in LDS as primitive variables
+    for (int c = tid; c < T::BOX; c += kThreads) {
+        int bx = c % T::BX;
+        int by = (c / T::BX) % T::BY;
+        int bz = c / (T::BX * T::BY);
+        int gx = wrap(x0 - 2 + bx, n0);
+        int gy = wrap(y0 - 2 + by, n1);
+        int gz = (D == 3) ? wrap(z0 - 2 + bz, n2) : 0;
+        long gi = ((long)gz * n1 + gy) * n0 + gx;
+        S U[NV];
+        load_state<MODE, NV, S>(A, G.ncell, gi, eps, U);
+        const R gm1 = (R)G.gm1;
+        const R half = (R)0.5;
+        S r = U[0];
+        S vel[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) vel[d] = U[1 + d] / r;
+        S ke = vel[0] * vel[0];
+#pragma unroll
+        for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
+        S p = gm1 * (U[D + 1] - (half * r) * ke);
+        if constexpr (FO) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m) sq[m][c] = U[m];
+        } else {
+            sq[0][c] = r;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) sq[OFF_VEL + d][c] = vel[d];
+        sq[OFF_P][c] = p;
+        if constexpr (NSV) sq[OFF_T][c] = p / r;
+    }
+    __syncthreads();
+
+    S res[CPT][NV];
+
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int FX = TX + (d == 0), FY = TY + (d == 1);
+        const int NF = (d == 0) ? T::NF0 : (d == 1 ? T::NF1 : T::NF2);
+        const int sd = T::stride(d);
+        // 2. every face flux of the tile along d, once
+        for (int f = tid; f < NF; f += kThreads) {
+            int fx = f % FX;
+            int fy = (f / FX) % FY;
+            int fz = f / (FX * FY);
+            int cb = ((fz + ((D == 3) ? 2 : 0)) * T::BY + (fy + 2)) * T::BX + (fx + 2);
+            int ca = cb - sd;
+            S Fh[NV];
+            S UL[NV], UR[NV], vL[D], vR[D];
+            S rL, rR, pL, pR;
+            if constexpr (FO) {
+#pragma unroll
+                for (int m = 0; m < NV; ++m) { UL[m] = sq[m][ca]; UR[m] = sq[m][cb]; }
+                rL = UL[0];
+                rR = UR[0];
+#pragma unroll
+                for (int e = 0; e < D; ++e) { vL[e] = sq[OFF_VEL + e][ca]; vR[e] = sq[OFF_VEL + e][cb]; }
+                pL = sq[OFF_P][ca];
+                pR = sq[OFF_P][cb];
+            } else {
+                const R half = (R)0.5;
+                S qL[NV], qR[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    S am1 = sq[k][ca - sd], a0 = sq[k][ca], ap1 = sq[k][cb], ap2 = sq[k][cb + sd];
+                    qL[k] = a0 + half * minmod(a0 - am1, ap1 - a0);
+                    qR[k] = ap1 - half * minmod(ap1 - a0, ap2 - ap1);
+                }
+                rL = qL[0];
+                rR = qR[0];
+#pragma unroll
+                for (int e = 0; e < D; ++e) { vL[e] = qL[1 + e]; vR[e] = qR[1 + e]; }
+                pL = qL[D + 1];
+                pR = qR[D + 1];
+                to_conserved<D>(G, rL, vL, pL, UL);
+                to_conserved<D>(G, rR, vR, pR, UR);
+            }
+            rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+            if constexpr (NSV) {
+                const R half = (R)0.5;
+                const R mu = (R)G.mu, c23mu = (R)G.c23mu, kappa = (R)G.kappa;
+                S Gr[D][D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+#pragma unroll
+                    for (int bb = 0; bb < D; ++bb) {
+                        if (bb == d) {
+                            Gr[a][bb] = (sq[OFF_VEL + a][cb] - sq[OFF_VEL + a][ca]) * (R)G.invdx[d];
+                        } else {
+                            const int st = T::stride(bb);
+                            const R h = (R)G.hinv[bb];
+                            S gca = (sq[OFF_VEL + a][ca + st] - sq[OFF_VEL + a][ca - st]) * h;
+                            S gcb = (sq[OFF_VEL + a][cb + st] - sq[OFF_VEL + a][cb - st]) * h;
+                            Gr[a][bb] = half * (gca + gcb);
+                        }
+                    }
+                }
+                S div = Gr[0][0];
+#pragma unroll
+                for (int a = 1; a < D; ++a) div = div + Gr[a][a];
+                S work;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    S tau = (a == d) ? mu * (Gr[a][d] + Gr[d][a]) - c23mu * div : mu * (Gr[a][d] + Gr[d][a]);
+                    S uf = half * (sq[OFF_VEL + a][ca] + sq[OFF_VEL + a][cb]);
+                    work = (a == 0) ? uf * tau : work + uf * tau;
+                    Fh[1 + a] = Fh[1 + a] - tau;
+                }
+                S dTdn = (sq[OFF_T][cb] - sq[OFF_T][ca]) * (R)G.invdx[d];
+                Fh[D + 1] = Fh[D + 1] - (work + kappa * dTdn);
+            }
+#pragma unroll
+            for (int m = 0; m < NV; ++m) fb[m][f] = Fh[m];
+        }
+        __syncthreads();
+        // 3. flux differences of this thread's cells
+        const int fs = (d == 0) ? 1 : (d == 1 ? FX : FX * FY);
+        const R inv = (R)G.invdx[d];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            int cell = tid + k * kThreads;
+            int cx = cell % TX;
+            int cy = (cell / TX) % TY;
+            int cz = cell / (TX * TY);
+            int fl = (cz * FY + cy) * FX + cx;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                S term = (fb[m][fl] - fb[m][fl + fs]) * inv;
+                res[k][m] = (d == 0) ? term : res[k][m] + term;
+            }
+        }
+        __syncthreads();
+    }
+
+    // 4. write out
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        int cell = tid + k * kThreads;
+        int gx = x0 + cell % TX;
+        int gy = y0 + (cell / TX) % TY;
+        int gz = z0 + cell / (TX * TY);
+        if (gx >= n0 || gy >= n1 || (D == 3 && gz >= n2)) continue;
+        long gi = ((long)gz * n1 + gy) * n0 + gx;
+        OUT* out = (OUT*)A.out;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            long o = (long)m * G.ncell + gi;
+            if constexpr (MODE == MODE_PLAIN) {
+                out[o] = (OUT)res[k][m];
+            } else if constexpr (MODE == MODE_FD) {
+                out[o] = (OUT)((res[k][m] - A.f0[o]) / eps);
+            } else {
+                out[o] = (OUT)res[k][m].d;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
+static hipError_t launch_t(const Geom& G, const ResArgs& A, hipStream_t st) {
+    int nt0 = (G.n[0] + TX - 1) / TX;
+    int nt1 = (G.n[1] + TY - 1) / TY;
+    int nt2 = (D == 3) ? (G.n[2] + TZ - 1) / TZ : 1;
+    long nb = (long)nt0 * nt1 * nt2;
+    if (nb <= 0 || nb > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_residual<D, RECON, NSV, S, MODE, OUT, TX, TY, TZ>), dim3((unsigned)nb), dim3(kThreads), 0, st,
+                       G, A, nt0, nt1);
+    return hipGetLastError();
+}
+
+// Tile shape per variant: bigger tiles where the LDS footprint allows.
+template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT>
+static hipError_t launch_v(const Geom& G, const ResArgs& A, hipStream_t st) {
+    constexpr bool wide = sizeof(S) <= 8;   // double or float (not a dual number)
+    if constexpr (D == 2) {
+        if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 16, 1>(G, A, st);
+        else return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 8, 1>(G, A, st);
+    } else {
+        // first-order 3-D keeps conserved and primitive states in LDS: too large for dual numbers
+        if constexpr (RECON == 0 && sizeof(S) > 8) return hipErrorNotSupported;
+        else return launch_t<D, RECON, NSV, S, MODE, OUT, 16, 4, 4>(G, A, st);
+    }
+}
+
+template <int D, int RECON, bool NSV>
+static hipError_t dispatch_prec(const Geom& G, const ResArgs& A, int kind, bool fp32, bool out_double, hipStream_t st) {
+    if (!fp32) {
+        if (kind == MODE_PLAIN) return launch_v<D, RECON, NSV, double, MODE_PLAIN, double>(G, A, st);
+        if (kind == MODE_FD) return launch_v<D, RECON, NSV, double, MODE_FD, double>(G, A, st);
+        return launch_v<D, RECON, NSV, Dual<double>, MODE_TAN, double>(G, A, st);
+    }
+    if (kind == MODE_FD) return hipErrorNotSupported;
+    if (kind == MODE_PLAIN) {
+        if (out_double) return launch_v<D, RECON, NSV, float, MODE_PLAIN, double>(G, A, st);
+        return launch_v<D, RECON, NSV, float, MODE_PLAIN, float>(G, A, st);
+    }
+    if (out_double) return launch_v<D, RECON, NSV, Dual<float>, MODE_TAN, double>(G, A, st);
+    return launch_v<D, RECON, NSV, Dual<float>, MODE_TAN, float>(G, A, st);
+}
+
+hipError_t launch_residual(const Geom& G, int recon, bool ns, bool fp32, int kind, bool out_double,
+                           const ResArgs& A, hipStream_t st) {
+    if (G.D == 2) {
+        if (recon == 0) return ns ? dispatch_prec<2, 0, true>(G, A, kind, fp32, out_double, st)
+                                  : dispatch_prec<2, 0, false>(G, A, kind, fp32, out_double, st);
+        return ns ? dispatch_prec<2, 1, true>(G, A, kind, fp32, out_double, st)
+                  : dispatch_prec<2, 1, false>(G, A, kind, fp32, out_double, st);
+    }
+    if (recon == 0) return ns ? dispatch_prec<3, 0, true>(G, A, kind, fp32, out_double, st)
+                              : dispatch_prec<3, 0, false>(G, A, kind, fp32, out_double, st);
+    return ns ? dispatch_prec<3, 1, true>(G, A, kind, fp32, out_double, st)
+              : dispatch_prec<3, 1, false>(G, A, kind, fp32, out_double, st);
+}
+
+}  // namespace rok

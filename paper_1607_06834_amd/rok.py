@@ -1,0 +1,220 @@
+"""Python binding of librok (argument marshalling only).
+
+Every computation runs in the HIP kernels of librok.so; this module converts
+torch device tensors to pointers, owns the workspace tensors and forwards
+the current torch stream.  If the library is missing the calls raise: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librok.so")
+
+ROK_OK, ROK_EINVAL, ROK_EUNSUPPORTED, ROK_EHIP = 0, -1, -2, -3
+EULER, NS = 0, 1
+FIRST_ORDER, MUSCL_MINMOD = 0, 1
+RUSANOV = 0
+FP64, FP32_RESIDUAL = 0, 1
+JVP_FD, JVP_TANGENT = 0, 1
+FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS = 1, 2, 4
+MAX_STAGES, MAX_M = 8, 64
+
+SYMBOLS = ["rok_create", "rok_destroy", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_jvp",
+           "rok_arnoldi", "rok_step", "rok_read_status", "rok_read_meff", "rok_strerror"]
+
+
+class RokProblem(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("physics", ctypes.c_int), ("recon", ctypes.c_int),
+                ("flux", ctypes.c_int), ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("prandtl", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class RokTableau(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int), ("alpha", ctypes.c_double * (MAX_STAGES * MAX_STAGES)),
+                ("gam", ctypes.c_double * (MAX_STAGES * MAX_STAGES)), ("gamma", ctypes.c_double),
+                ("b", ctypes.c_double * MAX_STAGES)]
+
+
+class RokError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librok.so (built by paper_1607_06834_amd.build) and declare its C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RokError(f"{path} is missing: build it with `python -m paper_1607_06834_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.rok_create.argtypes = [ctypes.POINTER(RokProblem), ctypes.POINTER(vp)]
+    lib.rok_create.restype = i
+    lib.rok_destroy.argtypes = [vp]
+    lib.rok_destroy.restype = None
+    lib.rok_state_size.argtypes = [vp]
+    lib.rok_state_size.restype = sz
+    lib.rok_workspace_bytes.argtypes = [vp, i, i]
+    lib.rok_workspace_bytes.restype = sz
+    lib.rok_residual.argtypes = [vp, vp, vp, vp]
+    lib.rok_residual.restype = i
+    lib.rok_jvp.argtypes = [vp, vp, vp, vp, vp, i, d, vp, sz, vp]
+    lib.rok_jvp.restype = i
+    lib.rok_arnoldi.argtypes = [vp, vp, vp, i, i, d, vp, vp, vp, vp, sz, vp]
+    lib.rok_arnoldi.restype = i
+    lib.rok_step.argtypes = [vp, ctypes.POINTER(RokTableau), i, i, d, vp, vp, vp, sz, vp]
+    lib.rok_step.restype = i
+    lib.rok_read_status.argtypes = [vp, vp, ctypes.POINTER(i), vp]
+    lib.rok_read_status.restype = i
+    lib.rok_read_meff.argtypes = [vp, vp, ctypes.POINTER(i), vp]
+    lib.rok_read_meff.restype = i
+    lib.rok_strerror.argtypes = [i]
+    lib.rok_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != ROK_OK:
+        msg = _lib.rok_strerror(status).decode()
+        raise RokError(f"{what} failed: {msg} ({status})")
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_tableau(tab: dict) -> RokTableau:
+    s = int(tab["s"])
+    if not 1 <= s <= MAX_STAGES:
+        raise ValueError("1 <= s <= 8 stages")
+    t = RokTableau()
+    t.s = s
+    t.gamma = float(tab["gamma"])
+    for i in range(s):
+        t.b[i] = float(tab["b"][i])
+        for j in range(i):
+            t.alpha[i * MAX_STAGES + j] = float(tab["alpha"][i][j])
+            t.gam[i * MAX_STAGES + j] = float(tab["gam"][i][j])
+    return t
+
+
+class Rok:
+    """One problem (grid, physics, discretisation, precision) on the current GPU."""
+
+    def __init__(self, problem: dict, precision: str = "fp64"):
+        lib = load_library()
+        p = RokProblem()
+        D = len(problem["n"])
+        p.ndim = D
+        for d in range(3):
+            p.n[d] = int(problem["n"][d]) if d < D else 1
+            p.lo[d] = float(problem["lo"][d]) if d < D else 0.0
+            p.hi[d] = float(problem["hi"][d]) if d < D else 1.0
+        p.physics = NS if problem["physics"] == "ns" else EULER
+        p.recon = MUSCL_MINMOD if problem["recon"] == "muscl" else FIRST_ORDER
+        p.flux = RUSANOV
+        p.gamma = float(problem["gamma"])
+        p.mu = float(problem.get("mu", 0.0))
+        p.prandtl = float(problem.get("prandtl", 0.72))
+        p.precision = FP32_RESIDUAL if precision == "fp32" else FP64
+        self.precision = precision
+        self._ctx = ctypes.c_void_p()
+        _check(lib.rok_create(ctypes.byref(p), ctypes.byref(self._ctx)), "rok_create")
+        self.N = int(lib.rok_state_size(self._ctx))
+        self._work = {}
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def __del__(self):
+        if getattr(self, "_ctx", None) and _lib is not None:
+            _lib.rok_destroy(self._ctx)
+            self._ctx = None
+
+    # -- workspace ---------------------------------------------------------
+    def workspace(self, M: int, s: int) -> torch.Tensor:
+        nb = int(_lib.rok_workspace_bytes(self._ctx, int(M), int(s)))
+        key = (int(M), int(s))
+        w = self._work.get(key)
+        if w is None or w.numel() < nb:
+            w = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            self._work[key] = w
+        off = (-w.data_ptr()) % 256
+        return w[off:off + nb]
+
+    def _vec(self, t: torch.Tensor, name: str):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.N):
+            raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor of {self.N} elements")
+        return t
+
+    def _out_dtype(self):
+        return torch.float32 if self.precision == "fp32" else torch.float64
+
+    # -- entry points --------------------------------------------------------
+    def residual(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._vec(y, "y")
+        F = out if out is not None else torch.empty(self.N, dtype=self._out_dtype(), device=y.device)
+        _check(_lib.rok_residual(self._ctx, _ptr(y), _ptr(F), _stream()), "rok_residual")
+        return F
+
+    def jvp(self, y, v, mode: str = "fd", fy=None, eps: float = 0.0, out=None) -> torch.Tensor:
+        self._vec(y, "y")
+        self._vec(v, "v")
+        m = JVP_FD if mode == "fd" else JVP_TANGENT
+        if m == JVP_FD:
+            if fy is None:
+                raise ValueError("the finite-difference product needs fy = f(y)")
+            self._vec(fy, "fy")
+        w = out if out is not None else torch.empty(self.N, dtype=self._out_dtype(), device=y.device)
+        ws = self.workspace(0, 0)
+        _check(_lib.rok_jvp(self._ctx, _ptr(y), _ptr(fy), _ptr(v), _ptr(w), m, float(eps), _ptr(ws), ws.numel(),
+                            _stream()), "rok_jvp")
+        return w
+
+    def arnoldi(self, y, fy, M: int, mode: str = "fd", eps: float = 0.0):
+        """Returns (V as an (M, N) tensor whose rows are the basis vectors, H (M, M), M_eff)."""
+        self._vec(y, "y")
+        self._vec(fy, "fy")
+        M = min(int(M), self.N)
+        V = torch.zeros(M, self.N, dtype=torch.float64, device=y.device)
+        H = torch.empty(M, M, dtype=torch.float64, device=y.device)
+        meff = torch.empty(1, dtype=torch.int32, device=y.device)
+        ws = self.workspace(M, 0)
+        m = JVP_FD if mode == "fd" else JVP_TANGENT
+        _check(_lib.rok_arnoldi(self._ctx, _ptr(y), _ptr(fy), M, m, float(eps), _ptr(V), _ptr(H), _ptr(meff),
+                                _ptr(ws), ws.numel(), _stream()), "rok_arnoldi")
+        k = int(meff.item())
+        return V[:k], H[:k, :k], k
+
+    def step(self, y, h: float, tableau: dict, M: int, mode: str = "fd", out=None) -> torch.Tensor:
+        self._vec(y, "y")
+        y1 = out if out is not None else torch.empty_like(y)
+        tab = make_tableau(tableau)
+        ws = self.workspace(M, tab.s)
+        m = JVP_FD if mode == "fd" else JVP_TANGENT
+        _check(_lib.rok_step(self._ctx, ctypes.byref(tab), int(M), m, float(h), _ptr(y), _ptr(y1), _ptr(ws),
+                             ws.numel(), _stream()), "rok_step")
+        self._last_step_ws = ws
+        return y1
+
+    def last_status(self) -> tuple[int, int]:
+        """(flags, M_eff) of the last step (synchronises the stream)."""
+        ws = self._last_step_ws
+        f, m = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.rok_read_status(self._ctx, _ptr(ws), ctypes.byref(f), _stream()), "rok_read_status")
+        _check(_lib.rok_read_meff(self._ctx, _ptr(ws), ctypes.byref(m), _stream()), "rok_read_meff")
+        return f.value, m.value

@@ -1,0 +1,243 @@
+"""GPU (librok) against the CPU oracle, element by element, on the same seeded inputs.
+
+Tolerances (normwise relative, ||gpu - oracle|| / ||oracle||):
+* FP64 residual and FD product with a given eps: bitwise (same operation
+  order, no contraction, correctly rounded / and sqrt on both sides);
+* FP64 exact (tangent) products, Arnoldi (V, H) and ROK steps: 1e-12;
+* FP32 residual / tangent (precision form): error stated against the FP64
+  oracle, bounded by 1e-5 relative to the size of f's perturbation.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import rok_inputs as ri
+from oracle import fv, krylov, rok
+from tests._util import oracle_problem, relerr, t64
+
+pytestmark = pytest.mark.gpu
+
+cuda = pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1607_06834_amd import load_library
+    load_library()
+    return torch.device("cuda", 0)
+
+
+def gpu(pb, precision="fp64"):
+    from paper_1607_06834_amd import Rok
+    return Rok(pb, precision)
+
+
+VARIANTS = {
+    "euler_fo": lambda n: ri.problem(n, (-1.0, -1.5), (1.0, 1.0), "euler", "first"),
+    "euler_muscl": lambda n: ri.problem(n, (-1.0, -1.5), (1.0, 1.0), "euler", "muscl"),
+    "ns_fo": lambda n: ri.problem(n, (0.0, 0.0), (1.0, 1.3), "ns", "first", mu=0.05),
+    "ns_muscl": lambda n: ri.problem(n, (0.0, 0.0), (1.0, 1.3), "ns", "muscl", mu=0.05),
+    "ns3d_muscl": lambda n: ri.problem(n, (0.0, 0.0, 0.0), (1.0, 0.9, 1.2), "ns", "muscl", mu=0.05),
+    "euler3d_muscl": lambda n: ri.problem(n, (0.0, 0.0, 0.0), (1.0, 0.9, 1.2), "euler", "muscl"),
+    "ns3d_fo": lambda n: ri.problem(n, (0.0, 0.0, 0.0), (1.0, 0.9, 1.2), "ns", "first", mu=0.05),
+}
+SHAPES_2D = [(6, 5), (37, 21), (70, 33)]      # tiny (wraps inside a tile), ragged, several tiles
+SHAPES_3D = [(5, 4, 3), (19, 9, 7)]
+CASES = [(k, s) for k in VARIANTS if "3d" not in k for s in SHAPES_2D] + \
+        [(k, s) for k in VARIANTS if "3d" in k for s in SHAPES_3D]
+
+
+def _state(pb, seed):
+    return ri.smooth_random_state(pb, seed=seed, amplitude=0.2)
+
+
+@pytest.mark.parametrize("name,shape", CASES)
+def test_residual_bitwise(dev, name, shape):
+    say("residual", name, shape)
+    pb = VARIANTS[name](shape)
+    y = _state(pb, 1)
+    ref = fv.residual(oracle_problem(pb), t64(y))
+    out = gpu(pb).residual(torch.tensor(y, device=dev)).cpu()
+    assert relerr(out, ref) <= 1e-15
+    assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("name,shape", CASES)
+def test_fd_jvp_bitwise_given_eps(dev, name, shape):
+    say("fd jvp", name, shape)
+    pb = VARIANTS[name](shape)
+    P = oracle_problem(pb)
+    y = t64(_state(pb, 2))
+    v = t64(ri.random_direction(P.size, seed=3))
+    F = fv.residual(P, y)
+    eps = 1.7e-7
+    ref = fv.jvp_fd(P, y, F, v, eps)
+    out = gpu(pb).jvp(y.to(dev), v.to(dev), "fd", fy=F.to(dev), eps=eps).cpu()
+    assert torch.equal(out, ref), relerr(out, ref)
+
+
+@pytest.mark.parametrize("name,shape", [c for c in CASES if c[0] != "ns3d_fo"])
+def test_tangent_jvp(dev, name, shape):
+    say("tangent jvp", name, shape)
+    pb = VARIANTS[name](shape)
+    P = oracle_problem(pb)
+    y = t64(_state(pb, 4))
+    v = t64(ri.random_direction(P.size, seed=5))
+    ref = fv.jvp_exact(P, y, v)
+    out = gpu(pb).jvp(y.to(dev), v.to(dev), "exact").cpu()
+    assert relerr(out, ref) <= 1e-12
+
+
+def test_fd_jvp_default_eps(dev):
+    pb = VARIANTS["euler_muscl"]((37, 21))
+    say("fd jvp default eps")
+    P = oracle_problem(pb)
+    y = t64(_state(pb, 6))
+    v = t64(ri.random_direction(P.size, seed=7, scale=3.0))
+    F = fv.residual(P, y)
+    ref = fv.jvp_fd(P, y, F, v, fv.fd_epsilon(y, v))
+    out = gpu(pb).jvp(y.to(dev), v.to(dev), "fd", fy=F.to(dev)).cpu()
+    assert relerr(out, ref) <= 1e-12
+
+
+def test_3d_first_order_tangent_is_unsupported(dev):
+    from paper_1607_06834_amd import RokError
+    pb = VARIANTS["ns3d_fo"]((5, 4, 3))
+    r = gpu(pb)
+    y = torch.tensor(_state(pb, 1), device=dev)
+    with pytest.raises(RokError):
+        r.jvp(y, y, "exact")
+
+
+@pytest.mark.parametrize("name", ["euler_muscl", "ns_muscl", "ns3d_muscl"])
+def test_fp32_residual_and_tangent_error_vs_fp64_oracle(dev, name):
+    say("fp32", name)
+    shape = (37, 21) if "3d" not in name else (19, 9, 7)
+    pb = VARIANTS[name](shape)
+    P = oracle_problem(pb)
+    y = t64(_state(pb, 8))
+    v = t64(ri.random_direction(P.size, seed=9))
+    g = gpu(pb, "fp32")
+    F = g.residual(y.to(dev)).cpu().double()
+    Fr = fv.residual(P, y)
+    w = g.jvp(y.to(dev), v.to(dev), "exact").cpu().double()
+    wr = fv.jvp_exact(P, y, v)
+    eF, ew = relerr(F, Fr), relerr(w, wr)
+    say("fp32 errors", name, eF, ew)
+    assert eF <= 2e-5 and ew <= 2e-5
+
+
+def _arnoldi_case(mode, M=8, shape=(24, 20), recon="muscl"):
+    pb = ri.vortex_problem(shape[0], recon)
+    pb["n"] = shape
+    P = oracle_problem(pb)
+    y = t64(ri.perturb_density(pb, ri.vortex_state(pb), 0.01, seed=11))
+    F = fv.residual(P, y)
+    f, mv = rok.fv_system(P, mode)
+    return pb, P, y, F, mv(y, F)
+
+
+@pytest.mark.parametrize("mode", ["fd", "exact"])
+def test_arnoldi_parity(dev, mode):
+    say("arnoldi", mode)
+    pb, P, y, F, matvec = _arnoldi_case(mode)
+    V, H, m = krylov.arnoldi(matvec, F, 8)
+    Vg, Hg, mg = gpu(pb).arnoldi(y.to(dev), F.to(dev), 8, "fd" if mode == "fd" else "exact")
+    assert mg == m == 8
+    assert relerr(Hg.cpu(), H) <= 1e-12
+    assert relerr(Vg.cpu().T, V) <= 1e-12
+
+
+def test_arnoldi_zero_rhs_and_breakdown(dev):
+    say("arnoldi breakdown")
+    pb = ri.vortex_problem(8, "muscl")
+    y = torch.tensor(ri.uniform_state(pb, 1.0, [0.3, 0.2], 1.0), device=dev)
+    g = gpu(pb)
+    F = g.residual(y)
+    assert int(torch.count_nonzero(F)) == 0
+    V, H, m = g.arnoldi(y, F, 5, "exact")
+    assert m == 0
+
+
+@pytest.mark.parametrize("mode,recon,M", [("fd", "muscl", 8), ("exact", "muscl", 8), ("fd", "first", 6),
+                                          ("exact", "first", 0)])
+def test_rok_step_parity(dev, mode, recon, M):
+    say("step", mode, recon, M)
+    pb = ri.vortex_problem(24, recon)
+    pb["n"] = (24, 20)
+    P = oracle_problem(pb)
+    y = t64(ri.perturb_density(pb, ri.vortex_state(pb), 0.01, seed=12))
+    h = ri.cfl_step(pb, y.numpy(), 2.0)
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, mode)
+    ref = rok.rok_step(f, mv, tab, M, h, y)
+    g = gpu(pb)
+    out = g.step(y.to(dev), h, tab, M, "fd" if mode == "fd" else "exact").cpu()
+    flags, meff = g.last_status()
+    assert meff == M and flags == 0
+    assert relerr(out, ref) <= 1e-12
+    assert relerr(out - y, ref - y) <= 1e-11     # the increment itself
+
+
+def test_vortex32_first_order_trajectory(dev):
+    """32^2 vortex, first order, FD products, M = 8, 10 steps at CFL 5."""
+    pb, y0, w = ri.workload("vortex32_fo")
+    say("vortex32 trajectory", w)
+    P = oracle_problem(pb)
+    h = ri.cfl_step(pb, y0, w["cfl"])
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, "fd")
+    g = gpu(pb)
+    yr = t64(y0)
+    yg = torch.tensor(y0, device=dev)
+    for n in range(w["steps"]):
+        yr = rok.rok_step(f, mv, tab, w["M"], h, yr)
+        yg = g.step(yg, h, tab, w["M"], "fd")
+        e = relerr(yg.cpu(), yr)
+        say("step", n, e, "bitwise" if torch.equal(yg.cpu(), yr) else "")
+        assert e <= 1e-12
+
+
+def test_free_stream_step_is_bitwise_identity(dev):
+    say("free stream step")
+    pb = ri.vortex_problem(40, "muscl")
+    y = torch.tensor(ri.uniform_state(pb, 1.0, [0.3, 0.2], 1.0), device=dev)
+    g = gpu(pb)
+    y1 = g.step(y, 0.01, ri.rok4_tableau(), 8, "fd")
+    flags, meff = g.last_status()
+    assert meff == 0 and flags & 4
+    assert torch.equal(y1, y)
+
+
+def test_step_is_deterministic(dev):
+    say("determinism")
+    pb = ri.vortex_problem(64, "muscl")
+    y = torch.tensor(ri.perturb_density(pb, ri.vortex_state(pb)), device=dev)
+    g = gpu(pb)
+    a = g.step(y, 0.01, ri.rok4_tableau(), 8, "fd").clone()
+    b = g.step(y, 0.01, ri.rok4_tableau(), 8, "fd").clone()
+    assert torch.equal(a, b)
+
+
+def test_bad_arguments_raise(dev):
+    from paper_1607_06834_amd import RokError
+    say("bad arguments")
+    pb = ri.vortex_problem(8, "muscl")
+    g = gpu(pb)
+    y = torch.tensor(ri.vortex_state(pb), device=dev)
+    with pytest.raises(RokError):
+        g.step(y, 0.01, ri.rok4_tableau(), 65, "fd")
+    with pytest.raises(ValueError):
+        g.residual(y.float())
+    with pytest.raises(RokError):
+        g.step(y, 0.01, ri.rok4_tableau(), 4, "fd", out=y)

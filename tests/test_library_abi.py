@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every entry point declared in include/rok.h (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "rok.h")).read()
+    return sorted(set(re.findall(r"\b(rok_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["rok_residual", "rok_jvp", "rok_arnoldi", "rok_step", "rok_create", "rok_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1607_06834_amd import rok
+    path = rok.LIB_PATH
+    if not os.path.exists(path):
+        pytest.skip("librok.so not built")
+    lib = ctypes.CDLL(path)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(rok.SYMBOLS) <= set(_declared())
+
+
+def test_host_validation_without_gpu():
+    """rok_create validates the problem on the host (no device call)."""
+    from paper_1607_06834_amd import rok
+    if not os.path.exists(rok.LIB_PATH):
+        pytest.skip("librok.so not built")
+    lib = rok.load_library()
+    p = rok.RokProblem()
+    p.ndim = 4
+    ctx = ctypes.c_void_p()
+    assert lib.rok_create(ctypes.byref(p), ctypes.byref(ctx)) == rok.ROK_EINVAL
+    p.ndim = 2
+    p.n[0], p.n[1] = 8, 8
+    p.lo[0], p.lo[1] = 0.0, 0.0
+    p.hi[0], p.hi[1] = 1.0, 1.0
+    p.gamma, p.prandtl = 1.4, 0.72
+    assert lib.rok_create(ctypes.byref(p), ctypes.byref(ctx)) == rok.ROK_OK
+    assert lib.rok_state_size(ctx) == 4 * 64
+    assert lib.rok_workspace_bytes(ctx, 8, 4) > lib.rok_workspace_bytes(ctx, 8, 0) > 0
+    assert lib.rok_workspace_bytes(ctx, 8, 9) == 0
+    tab = rok.RokTableau()
+    tab.s = 0
+    assert lib.rok_step(ctx, ctypes.byref(tab), 4, 0, 0.1, ctypes.c_void_p(8), ctypes.c_void_p(16),
+                        ctypes.c_void_p(256), 1 << 20, None) == rok.ROK_EINVAL
+    lib.rok_destroy(ctx)

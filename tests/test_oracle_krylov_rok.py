@@ -26,6 +26,20 @@ def _tiny():
     return P, y
 
 
+@pytest.mark.parametrize("n", [1, 255, 257, 4099, 262147, 600001])
+def test_canonical_sum_is_a_faithful_sum(n):
+    """The canonical-order sum is within the classical recursive-summation
+    bound of the exactly rounded sum (math.fsum) and exact on integers."""
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) * np.exp(rng.uniform(-5, 5, n))
+    s = krylov.canonical_sum(x)
+    depth = -(-n // krylov.RED_LANES) + 8 + 2 + 8
+    bound = depth * 2.0**-53 * float(np.abs(x).sum())
+    assert abs(s - math.fsum(x)) <= bound
+    xi = rng.integers(-1000, 1000, n).astype(np.float64)
+    assert krylov.canonical_sum(xi) == float(xi.sum())
+
+
 def test_arnoldi_invariants_against_bruteforce_jacobian():
     P, y = _tiny()
     J = fv.dense_jacobian_fd(P, y, 1e-6)
