@@ -60,8 +60,12 @@ enum { ROK_JVP_FD = 0, ROK_JVP_TANGENT = 1 };        /* Jacobian-vector product 
 enum {
     ROK_FLAG_NONFINITE = 1,   /* a NaN or Inf appeared in H, phi or lambda           */
     ROK_FLAG_BREAKDOWN = 2,   /* Arnoldi stopped early: M_eff < M (invariant space) */
-    ROK_FLAG_ZERO_RHS = 4     /* f(y_n) = 0 exactly: M_eff = 0                       */
+    ROK_FLAG_ZERO_RHS = 4,    /* f(y_n) = 0 exactly: M_eff = 0                       */
+    ROK_FLAG_BARRIER = 8      /* an in-kernel grid barrier timed out (results invalid) */
 };
+
+/* Implementation of the modified Gram-Schmidt passes (rok_set_mgs_path). */
+enum { ROK_MGS_AUTO = 0, ROK_MGS_PER_PASS = 1, ROK_MGS_RESIDENT = 2 };
 
 #define ROK_MAX_STAGES 8
 #define ROK_MAX_M 64
@@ -111,6 +115,16 @@ typedef struct {
  * hi <= lo, gamma <= 1, mu < 0, NS with mu = 0 is allowed). */
 rok_status rok_create(const rok_problem* problem, rok_ctx** out);
 void rok_destroy(rok_ctx* ctx);
+
+/* Selects how the modified Gram-Schmidt passes of rok_arnoldi / rok_step
+ * run: ROK_MGS_PER_PASS launches one kernel per pass (the work vector is
+ * streamed through memory); ROK_MGS_RESIDENT runs one cooperative kernel per
+ * Arnoldi column with the work vector held in registers (N up to 16 * 2^18 = 4194304);
+ * ROK_MGS_AUTO (default) takes the resident kernel when the device and N
+ * allow it.  Both produce bit-identical results.  Changes the context: not
+ * to be called while other calls on the same context are being made.
+ * ROK_EINVAL for an unknown path. */
+rok_status rok_set_mgs_path(rok_ctx* ctx, int path);
 
 /* N, the length of a state vector. */
 size_t rok_state_size(const rok_ctx* ctx);

@@ -14,6 +14,7 @@
 struct rok_ctx {
     rok_problem pb;
     rok::Geom G;
+    int mgs_path;
 };
 
 namespace {
@@ -68,11 +69,17 @@ hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, c
     }
     e = rok::launch_start_basis(W, fy, N, V, st);
     if (e != hipSuccess) return e;
+    bool resident = c->mgs_path != ROK_MGS_PER_PASS && rok::mgs_resident_per(N) > 0 && rok::mgs_resident_available();
+    if (c->mgs_path == ROK_MGS_RESIDENT && !resident) return hipErrorNotSupported;
     for (int j = 0; j < M; ++j) {
         double* vj = V + (long)j * N;
         e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st);
         if (e != hipSuccess) return e;
-        e = rok::launch_mgs_column(W, W.w, V, N, M, j, (j + 1 < M) ? V + (long)(j + 1) * N : nullptr, st);
+        double* vnext = (j + 1 < M) ? V + (long)(j + 1) * N : nullptr;
+        if (resident)
+            e = rok::launch_mgs_resident(W, W.w, V, N, M, j, vnext, st);
+        else
+            e = rok::launch_mgs_column(W, W.w, V, N, M, j, vnext, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -100,6 +107,7 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
     rok_ctx* c = new (std::nothrow) rok_ctx;
     if (!c) return ROK_EINVAL;
     c->pb = *p;
+    c->mgs_path = ROK_MGS_AUTO;
     rok::Geom& G = c->G;
     memset(&G, 0, sizeof(G));
     G.D = p->ndim;
@@ -122,6 +130,12 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
 }
 
 void rok_destroy(rok_ctx* c) { delete c; }
+
+rok_status rok_set_mgs_path(rok_ctx* c, int path) {
+    if (!c || (path != ROK_MGS_AUTO && path != ROK_MGS_PER_PASS && path != ROK_MGS_RESIDENT)) return ROK_EINVAL;
+    c->mgs_path = path;
+    return ROK_OK;
+}
 
 size_t rok_state_size(const rok_ctx* c) { return c ? (size_t)c->G.N : 0; }
 
@@ -238,9 +252,11 @@ rok_status rok_step(rok_ctx* c, const rok_tableau* tab, int M, int mode, double 
             for (int j = 0; j < ROK_MAX_STAGES; ++j) grow[j] = (j < i) ? tab->gam[i * ROK_MAX_STAGES + j] : 0.0;
             ROK_TRY(rok::launch_lambda(W, M, i, grow, h, st));
         }
-        ROK_TRY(rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, st));
+        if (i + 1 < s)
+            ROK_TRY(rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, nullptr, nullptr, 0, nullptr, st));
+        else
+            ROK_TRY(rok::launch_recover(W, W.V, Fi, N, M, i, h, y_np1, y_n, W.K, s, tab->b, st));
     }
-    ROK_TRY(rok::launch_update(y_n, s, W.K, tab->b, N, y_np1, st));
     return ROK_OK;
 }
 

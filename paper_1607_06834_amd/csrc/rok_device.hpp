@@ -96,6 +96,30 @@ template <> struct Sc<Dual<float>> {
     }
 };
 
+// Pairwise halving tree over groups of 256 consecutive threads of a block:
+// with x_i the value of lane i of a group, computes s_i <- s_i + s_{i+h} for
+// h = 128, 64, ..., 1 (i < h) and returns s_0 in lane 0 of each group (other
+// lanes return partial values).  The two cross-wave levels go through LDS
+// (`s`, one double per thread), the six in-wave levels through lane
+// shuffles; the additions and their order are those of the LDS tree.
+__device__ __forceinline__ double tree256(double v, double* s) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 255;
+    s[tid] = v;
+    __syncthreads();
+    if (lane < 128) {
+        v = v + s[tid + 128];
+        s[tid] = v;
+    }
+    __syncthreads();
+    if (lane < 64) {
+        v = v + s[tid + 64];
+#pragma unroll
+        for (int h = 32; h > 0; h >>= 1) v = v + __shfl_down(v, h, 64);
+    }
+    return v;
+}
+
 // Periodic wrap of an index that may lie anywhere in [-n, 2n) (fast path) or
 // beyond (small grids).
 __device__ __forceinline__ int wrap(int i, int n) {

@@ -23,6 +23,8 @@ struct Work {
     int* perm;        // M
     double* partials; // npart x kRedBlocks reduction partials
     int npart;
+    double* gpart;    // 2 x kRedBlocks partials exchanged inside the resident MGS kernel
+    unsigned* bar;    // grid barrier counters (kBarWords unsigned, zeroed by launch_init)
     // full-length vectors (double, N each)
     double* w;        // Arnoldi work vector
     double* V;        // M columns (rok_step only; rok_arnoldi uses the caller's V)
@@ -32,6 +34,7 @@ struct Work {
 
 constexpr int kRedBlocks = 1024;   // reduction grid (fixed: it fixes the summation order)
 constexpr int kRedThreads = 256;
+constexpr int kBarWords = 1024;   // grid-barrier state (4 KiB)
 
 size_t work_small_bytes(int M, int s);
 size_t work_bytes(long N, int M, int s, bool step);
@@ -44,13 +47,18 @@ hipError_t launch_norm_eps(const Work& W, const double* y, const double* v, long
 hipError_t launch_start_basis(const Work& W, const double* f, long n, double* v0, hipStream_t st);
 hipError_t launch_mgs_column(const Work& W, double* w, const double* V, long n, int M, int j, double* vnext,
                              hipStream_t st);
+// Resident-w MGS for one column (rok_mgs.hip).
+int mgs_resident_per(long n);
+bool mgs_resident_available();
+hipError_t launch_mgs_resident(const Work& W, const double* w, const double* V, long n, int M, int j, double* vnext,
+                               hipStream_t st);
 hipError_t launch_copy_h(const Work& W, int M, double* Hout, int* meff_out, hipStream_t st);
 hipError_t launch_lu(const Work& W, int M, double hg, hipStream_t st);
 hipError_t launch_project(const Work& W, const double* V, const double* F, long n, int M, hipStream_t st);
 hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, double h, hipStream_t st);
+// k_i = V lambda_i + h (F_i - V phi_i) into k; if y is non-null (last stage)
+// writes y_{n+1} = y + sum_{q<s} b_q k_q into k instead, K holding k_0..k_{s-2}.
 hipError_t launch_recover(const Work& W, const double* V, const double* F, long n, int M, int i, double h, double* k,
-                          hipStream_t st);
-hipError_t launch_update(const double* y, int s, const double* K, const double* b, long n, double* y1,
-                         hipStream_t st);
+                          const double* y, const double* K, int s, const double* b, hipStream_t st);
 
 }  // namespace rok

@@ -21,16 +21,13 @@ namespace rok {
 constexpr double kBreakdownTol = 1e-13;
 constexpr double kSqrtEps = 1.4901161193847656e-08;  // sqrt(2^-52) = 2^-26
 
+// Block of kRedThreads threads: the halving tree; every thread gets the sum.
 __device__ __forceinline__ double block_sum(double acc, double* s) {
-    const int tid = threadIdx.x;
-    s[tid] = acc;
+    __shared__ double s_r;
+    double r = tree256(acc, s);
+    if (threadIdx.x == 0) s_r = r;
     __syncthreads();
-#pragma unroll
-    for (int st = kRedThreads / 2; st > 0; st >>= 1) {
-        if (tid < st) s[tid] = s[tid] + s[tid + st];
-        __syncthreads();
-    }
-    double r = s[0];
+    r = s_r;
     __syncthreads();
     return r;
 }
@@ -158,19 +155,17 @@ __global__ __launch_bounds__(kRedThreads) void k_normalize(const double* w, cons
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) v[e] = w[e] / hn;
 }
 
-__global__ void k_init(double* H, int nh, double* phi, double* lam, int nsm, double* scal, int* ints, int meff0) {
+__global__ void k_init(double* H, int nh, double* phi, double* lam, int nsm, double* scal, int* ints, int meff0,
+                       unsigned* bar) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int e = t; e < kBarWords; e += gridDim.x * blockDim.x) bar[e] = 0u;
     for (int e = t; e < nh; e += gridDim.x * blockDim.x) H[e] = 0.0;
     for (int e = t; e < nsm; e += gridDim.x * blockDim.x) {
         phi[e] = 0.0;
         lam[e] = 0.0;
     }
     if (t < 16) scal[t] = 0.0;
-    if (t == 0) {
-        ints[0] = meff0;
-        ints[1] = 0;
-        ints[2] = 0;
-    }
+    if (t < 32) ints[t] = (t == 0) ? meff0 : 0;   // M_eff, stop, flags, barrier words
 }
 
 __global__ void k_copy_h(const double* H, int M, double* Hout, const int* ints, int* meff_out) {
@@ -183,53 +178,96 @@ __global__ void k_copy_h(const double* H, int M, double* Hout, const int* ints, 
     if (t == 0 && meff_out) *meff_out = m;
 }
 
-// LU with partial pivoting of A = I - hg H (M_eff x M_eff), one thread.
-__global__ void k_lu(const double* H, int M, double hg, double* LU, int* perm, const int* ints) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int m = ints[0];
-    for (int i = 0; i < m; ++i) {
-        perm[i] = i;
-        for (int j = 0; j < m; ++j) LU[i * M + j] = (i == j ? 1.0 : 0.0) - hg * H[i * M + j];
+// LU with partial pivoting of A = I - hg H (M_eff x M_eff) in LDS, one block.
+// Each entry sees the same sequence of operations as the textbook
+// right-looking elimination; rows (and columns) are updated in parallel.
+__global__ __launch_bounds__(kRedThreads) void k_lu(const double* H, int M, double hg, double* LU, int* perm,
+                                                   const int* ints) {
+    __shared__ double A[kMaxM * kMaxM];
+    __shared__ int P[kMaxM];
+    __shared__ int s_piv;
+    const int m = ints[0];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+        int i = e / m, j = e % m;
+        A[i * kMaxM + j] = (i == j ? 1.0 : 0.0) - hg * H[i * M + j];
     }
+    for (int i = tid; i < m; i += blockDim.x) P[i] = i;
+    __syncthreads();
     for (int k = 0; k < m; ++k) {
-        int piv = k;
-        for (int r = k + 1; r < m; ++r)
-            if (fabs(LU[r * M + k]) > fabs(LU[piv * M + k])) piv = r;
-        if (piv != k) {
-            for (int c = 0; c < m; ++c) {
-                double t = LU[k * M + c];
-                LU[k * M + c] = LU[piv * M + c];
-                LU[piv * M + c] = t;
+        if (tid == 0) {
+            int piv = k;
+            for (int r = k + 1; r < m; ++r)
+                if (fabs(A[r * kMaxM + k]) > fabs(A[piv * kMaxM + k])) piv = r;
+            s_piv = piv;
+            if (piv != k) {
+                int t = P[k];
+                P[k] = P[piv];
+                P[piv] = t;
             }
-            int t = perm[k];
-            perm[k] = perm[piv];
-            perm[piv] = t;
         }
-        for (int r = k + 1; r < m; ++r) {
-            LU[r * M + k] = LU[r * M + k] / LU[k * M + k];
-            for (int c = k + 1; c < m; ++c) LU[r * M + c] = LU[r * M + c] - LU[r * M + k] * LU[k * M + c];
+        __syncthreads();
+        const int piv = s_piv;
+        if (piv != k) {
+            for (int c = tid; c < m; c += blockDim.x) {
+                double t = A[k * kMaxM + c];
+                A[k * kMaxM + c] = A[piv * kMaxM + c];
+                A[piv * kMaxM + c] = t;
+            }
         }
+        __syncthreads();
+        for (int r = k + 1 + tid; r < m; r += blockDim.x) A[r * kMaxM + k] = A[r * kMaxM + k] / A[k * kMaxM + k];
+        __syncthreads();
+        const int w = m - k - 1;
+        for (int e = tid; e < w * w; e += blockDim.x) {
+            int r = k + 1 + e / w, c = k + 1 + e % w;
+            A[r * kMaxM + c] = A[r * kMaxM + c] - A[r * kMaxM + k] * A[k * kMaxM + c];
+        }
+        __syncthreads();
     }
+    for (int e = tid; e < m * m; e += blockDim.x) {
+        int i = e / m, j = e % m;
+        LU[i * M + j] = A[i * kMaxM + j];
+    }
+    for (int i = tid; i < m; i += blockDim.x) perm[i] = P[i];
 }
 
 struct GamRow {
     double g[kMaxStages];
 };
 
-// phi_i = V^T F_i finished from the projection partials, then
+// phi_i = V^T F_i finished from the projection partials (all columns at once,
+// canonical order per column), then
 // lambda_i = LU^{-1} (h phi_i + h H sum_{j<i} gamma_ij lambda_j) on one thread.
 __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const double* LU, const int* perm, int M,
                                                        int i, GamRow gr, double h, const double* partials,
                                                        double* phi, double* lam, int* ints) {
-    __shared__ double s[kRedThreads];
+    __shared__ double s[16][kRedThreads];
+    __shared__ double sphi[kMaxM];
     const int m = ints[0];
-    for (int c = 0; c < m; ++c) {
-        double t = final_sum(partials + (long)c * kRedBlocks, s);
-        if (threadIdx.x == 0) phi[i * M + c] = t;
+    const int tid = threadIdx.x;
+    for (int c0 = 0; c0 < m; c0 += 16) {
+        const int nc = (m - c0) < 16 ? (m - c0) : 16;
+        for (int c = 0; c < nc; ++c) {
+            double acc = 0.0;
+            for (int b = tid; b < kRedBlocks; b += kRedThreads) acc = acc + partials[(long)(c0 + c) * kRedBlocks + b];
+            s[c][tid] = acc;
+        }
+        __syncthreads();
+        for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+            if (tid < st)
+                for (int c = 0; c < nc; ++c) s[c][tid] = s[c][tid] + s[c][tid + st];
+            __syncthreads();
+        }
+        if (tid < nc) sphi[c0 + tid] = s[tid][0];
+        __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    double g[kMaxM], x[kMaxM], rhs[kMaxM];
-    for (int c = 0; c < m; ++c) g[c] = 0.0;
+    if (tid != 0) return;
+    __shared__ double g[kMaxM], x[kMaxM], y[kMaxM];
+    for (int c = 0; c < m; ++c) {
+        phi[i * M + c] = sphi[c];
+        g[c] = 0.0;
+    }
     for (int j = 0; j < i; ++j) {
         if (gr.g[j] != 0.0)
             for (int c = 0; c < m; ++c) g[c] = g[c] + gr.g[j] * lam[j * M + c];
@@ -237,25 +275,26 @@ __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const d
     for (int r = 0; r < m; ++r) {
         double hg = 0.0;
         for (int c = 0; c < m; ++c) hg = hg + H[r * M + c] * g[c];
-        rhs[r] = h * phi[i * M + r] + h * hg;
+        x[r] = h * sphi[r] + h * hg;
     }
-    for (int r = 0; r < m; ++r) x[r] = rhs[perm[r]];
+    for (int r = 0; r < m; ++r) y[r] = x[perm[r]];
     for (int r = 0; r < m; ++r)
-        for (int c = 0; c < r; ++c) x[r] = x[r] - LU[r * M + c] * x[c];
+        for (int c = 0; c < r; ++c) y[r] = y[r] - LU[r * M + c] * y[c];
     for (int r = m - 1; r >= 0; --r) {
-        for (int c = r + 1; c < m; ++c) x[r] = x[r] - LU[r * M + c] * x[c];
-        x[r] = x[r] / LU[r * M + r];
+        for (int c = r + 1; c < m; ++c) y[r] = y[r] - LU[r * M + c] * y[c];
+        y[r] = y[r] / LU[r * M + r];
     }
     bool bad = false;
     for (int r = 0; r < m; ++r) {
-        lam[i * M + r] = x[r];
-        bad = bad || nonfinite(x[r]);
+        lam[i * M + r] = y[r];
+        bad = bad || nonfinite(y[r]);
     }
     if (bad) ints[2] |= ROK_FLAG_NONFINITE;
 }
 
 // Projection partials: for c < M_eff, canonical per-block partial sums of
-// V[:, c] . F (finished by k_lambda).  MB >= M.
+// V[:, c] . F (finished by k_lambda).  MB >= M; the common case M_eff == MB
+// runs a branch-free loop so all loads of an element are in flight together.
 template <int MB>
 __global__ __launch_bounds__(kRedThreads) void k_project(const double* V, const double* F, long n, const int* ints,
                                                         double* partials) {
@@ -265,11 +304,22 @@ __global__ __launch_bounds__(kRedThreads) void k_project(const double* V, const 
 #pragma unroll
     for (int c = 0; c < MB; ++c) acc[c] = 0.0;
     const long stride = (long)kRedBlocks * kRedThreads;
-    for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
-        double fe = F[e];
+    if (m == MB) {
+        for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
+            double fe = F[e];
+            double vc[MB];
 #pragma unroll
-        for (int c = 0; c < MB; ++c)
-            if (c < m) acc[c] = acc[c] + V[(long)c * n + e] * fe;
+            for (int c = 0; c < MB; ++c) vc[c] = V[(long)c * n + e];
+#pragma unroll
+            for (int c = 0; c < MB; ++c) acc[c] = acc[c] + vc[c] * fe;
+        }
+    } else {
+        for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
+            double fe = F[e];
+#pragma unroll
+            for (int c = 0; c < MB; ++c)
+                if (c < m) acc[c] = acc[c] + V[(long)c * n + e] * fe;
+        }
     }
 #pragma unroll
     for (int c = 0; c < MB; ++c) {
@@ -280,35 +330,58 @@ __global__ __launch_bounds__(kRedThreads) void k_project(const double* V, const 
     }
 }
 
-// k = V lambda + h (F - V phi), column sums in order from zero.
-__global__ void k_recover(const double* V, const double* F, long n, const int* ints, const double* lam,
-                          const double* phi, double h, double* k) {
-    const int m = ints[0];
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        double a = 0.0, b = 0.0;
-        for (int c = 0; c < m; ++c) {
-            double vc = V[(long)c * n + e];
-            a = a + vc * lam[c];
-            b = b + vc * phi[c];
-        }
-        k[e] = a + h * (F[e] - b);
-    }
-}
-
 struct BRow {
     double b[kMaxStages];
 };
 
-__global__ void k_update(const double* y, int s, const double* K, BRow br, long n, double* y1) {
+// k = V lambda + h (F - V phi), column sums in order from zero.  FINAL: the
+// last stage, which writes y_{n+1} = y + sum_i b_i k_i instead of k
+// (sum in stage order, terms with b_i = 0 skipped).
+template <int MB, bool FINAL>
+__global__ __launch_bounds__(256) void k_recover(const double* V, const double* F, long n, const int* ints,
+                                                const double* lam, const double* phi, double h, double* k,
+                                                const double* y, const double* K, int s, BRow br) {
+    const int m = ints[0];
+    double lm[MB], ph[MB];
+    if (m == MB) {
+#pragma unroll
+        for (int c = 0; c < MB; ++c) {
+            lm[c] = lam[c];
+            ph[c] = phi[c];
+        }
+    }
     const long stride = (long)gridDim.x * blockDim.x;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        double acc = y[e];
-        for (int i = 0; i < s; ++i)
-            if (br.b[i] != 0.0) acc = acc + br.b[i] * K[(long)i * n + e];
-        y1[e] = acc;
+        double a = 0.0, b = 0.0;
+        if (m == MB) {
+            double vc[MB];
+#pragma unroll
+            for (int c = 0; c < MB; ++c) vc[c] = V[(long)c * n + e];
+#pragma unroll
+            for (int c = 0; c < MB; ++c) {
+                a = a + vc[c] * lm[c];
+                b = b + vc[c] * ph[c];
+            }
+        } else {
+            for (int c = 0; c < m; ++c) {
+                double vc = V[(long)c * n + e];
+                a = a + vc * lam[c];
+                b = b + vc * phi[c];
+            }
+        }
+        double ke = a + h * (F[e] - b);
+        if constexpr (FINAL) {
+            double acc = y[e];
+            for (int i = 0; i < s - 1; ++i)
+                if (br.b[i] != 0.0) acc = acc + br.b[i] * K[(long)i * n + e];
+            if (br.b[s - 1] != 0.0) acc = acc + br.b[s - 1] * ke;
+            k[e] = acc;
+        } else {
+            k[e] = ke;
+        }
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Workspace: a 256-byte header (status ints, scalars) at offset 0 for every M
@@ -329,6 +402,8 @@ size_t work_small_bytes(int M, int s) {
     b += al256(sizeof(double) * ss * Mm);                        // lam
     b += al256(sizeof(int) * Mm);                                // perm
     b += al256(sizeof(double) * (size_t)npart(M) * kRedBlocks);  // partials
+    b += al256(sizeof(double) * 2 * kRedBlocks);                 // gpart
+    b += al256(sizeof(unsigned) * kBarWords);                    // barrier
     return b;
 }
 
@@ -355,6 +430,8 @@ Work carve(void* base, long N, int M, int s, bool step) {
     W.perm = (int*)p;        p += al256(sizeof(int) * Mm);
     W.partials = (double*)p; p += al256(sizeof(double) * (size_t)npart(M) * kRedBlocks);
     W.npart = npart(M);
+    W.gpart = (double*)p;    p += al256(sizeof(double) * 2 * kRedBlocks);
+    W.bar = (unsigned*)p;    p += al256(sizeof(unsigned) * kBarWords);
     size_t vec = al256(sizeof(double) * (size_t)N);
     W.w = (double*)p;        p += vec;
     if (step) {
@@ -386,7 +463,7 @@ hipError_t launch_init(const Work& W, int M, int s, hipStream_t st) {
     int Mm = M > 0 ? M : 1;
     int ss = s > 0 ? s : 1;
     hipLaunchKernelGGL(k_init, dim3(16), dim3(256), 0, st, W.H, (Mm + 1) * Mm, W.phi, W.lam, ss * Mm, W.scal, W.ints,
-                       M);
+                       M, W.bar);
     return hipGetLastError();
 }
 
@@ -442,17 +519,37 @@ hipError_t launch_copy_h(const Work& W, int M, double* Hout, int* meff_out, hipS
 }
 
 hipError_t launch_lu(const Work& W, int M, double hg, hipStream_t st) {
-    hipLaunchKernelGGL(k_lu, dim3(1), dim3(64), 0, st, W.H, M, hg, W.LU, W.perm, W.ints);
+    hipLaunchKernelGGL(k_lu, dim3(1), dim3(kRedThreads), 0, st, W.H, M, hg, W.LU, W.perm, W.ints);
     return hipGetLastError();
 }
+
+// Smallest compiled column count >= M.
+static int mbucket(int M) {
+    static const int b[] = {1, 2, 4, 8, 12, 16, 20, 24, 32, 48, 64};
+    for (int x : b)
+        if (M <= x) return x;
+    return 64;
+}
+
+#define ROK_MB_SWITCH(MBV, CALL)       \
+    switch (MBV) {                     \
+        case 1: CALL(1); break;        \
+        case 2: CALL(2); break;        \
+        case 4: CALL(4); break;        \
+        case 8: CALL(8); break;        \
+        case 12: CALL(12); break;      \
+        case 16: CALL(16); break;      \
+        case 20: CALL(20); break;      \
+        case 24: CALL(24); break;      \
+        case 32: CALL(32); break;      \
+        case 48: CALL(48); break;      \
+        default: CALL(64); break;      \
+    }
 
 hipError_t launch_project(const Work& W, const double* V, const double* F, long n, int M, hipStream_t st) {
 #define ROK_PROJ(MB) \
     hipLaunchKernelGGL((k_project<MB>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, F, n, W.ints, W.partials)
-    if (M <= 8) ROK_PROJ(8);
-    else if (M <= 16) ROK_PROJ(16);
-    else if (M <= 32) ROK_PROJ(32);
-    else ROK_PROJ(64);
+    ROK_MB_SWITCH(mbucket(M), ROK_PROJ)
 #undef ROK_PROJ
     return hipGetLastError();
 }
@@ -466,18 +563,20 @@ hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, dou
 }
 
 hipError_t launch_recover(const Work& W, const double* V, const double* F, long n, int M, int i, double h, double* k,
-                          hipStream_t st) {
+                          const double* y, const double* K, int s, const double* b, hipStream_t st) {
     int Mm = M > 0 ? M : 1;
-    hipLaunchKernelGGL(k_recover, dim3(grid_for(n, 256)), dim3(256), 0, st, V, F, n, W.ints, W.lam + (long)i * Mm,
-                       W.phi + (long)i * Mm, h, k);
-    return hipGetLastError();
-}
-
-hipError_t launch_update(const double* y, int s, const double* K, const double* b, long n, double* y1,
-                         hipStream_t st) {
     BRow br{};
-    for (int i = 0; i < kMaxStages; ++i) br.b[i] = (i < s) ? b[i] : 0.0;
-    hipLaunchKernelGGL(k_update, dim3(grid_for(n, 256)), dim3(256), 0, st, y, s, K, br, n, y1);
+    for (int q = 0; q < kMaxStages; ++q) br.b[q] = (b && q < s) ? b[q] : 0.0;
+    const double* lam = W.lam + (long)i * Mm;
+    const double* phi = W.phi + (long)i * Mm;
+    const unsigned g = grid_for(n, 256);
+#define ROK_REC(MB)                                                                                             \
+    if (y) hipLaunchKernelGGL((k_recover<MB, true>), dim3(g), dim3(256), 0, st, V, F, n, W.ints, lam, phi, h, k, \
+                              y, K, s, br);                                                                     \
+    else hipLaunchKernelGGL((k_recover<MB, false>), dim3(g), dim3(256), 0, st, V, F, n, W.ints, lam, phi, h, k,  \
+                            y, K, s, br)
+    ROK_MB_SWITCH(mbucket(M > 0 ? M : 1), ROK_REC)
+#undef ROK_REC
     return hipGetLastError();
 }
 

@@ -21,11 +21,12 @@ FIRST_ORDER, MUSCL_MINMOD = 0, 1
 RUSANOV = 0
 FP64, FP32_RESIDUAL = 0, 1
 JVP_FD, JVP_TANGENT = 0, 1
-FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS = 1, 2, 4
+FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER = 1, 2, 4, 8
 MAX_STAGES, MAX_M = 8, 64
 
-SYMBOLS = ["rok_create", "rok_destroy", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_jvp",
-           "rok_arnoldi", "rok_step", "rok_read_status", "rok_read_meff", "rok_strerror"]
+SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual",
+           "rok_jvp", "rok_arnoldi", "rok_step", "rok_read_status", "rok_read_meff", "rok_strerror"]
+MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
 class RokProblem(ctypes.Structure):
@@ -61,6 +62,8 @@ def load_library(path: str = LIB_PATH):
     lib.rok_create.restype = i
     lib.rok_destroy.argtypes = [vp]
     lib.rok_destroy.restype = None
+    lib.rok_set_mgs_path.argtypes = [vp, i]
+    lib.rok_set_mgs_path.restype = i
     lib.rok_state_size.argtypes = [vp]
     lib.rok_state_size.restype = sz
     lib.rok_workspace_bytes.argtypes = [vp, i, i]
@@ -117,7 +120,7 @@ def make_tableau(tab: dict) -> RokTableau:
 class Rok:
     """One problem (grid, physics, discretisation, precision) on the current GPU."""
 
-    def __init__(self, problem: dict, precision: str = "fp64"):
+    def __init__(self, problem: dict, precision: str = "fp64", mgs: str = "auto"):
         lib = load_library()
         p = RokProblem()
         D = len(problem["n"])
@@ -137,6 +140,7 @@ class Rok:
         self._ctx = ctypes.c_void_p()
         _check(lib.rok_create(ctypes.byref(p), ctypes.byref(self._ctx)), "rok_create")
         self.N = int(lib.rok_state_size(self._ctx))
+        _check(lib.rok_set_mgs_path(self._ctx, MGS_PATHS[mgs]), "rok_set_mgs_path")
         self._work = {}
         self.device = torch.device("cuda", torch.cuda.current_device())
 

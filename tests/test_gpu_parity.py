@@ -37,9 +37,12 @@ def dev():
     return torch.device("cuda", 0)
 
 
-def gpu(pb, precision="fp64"):
+def gpu(pb, precision="fp64", mgs="auto"):
     from paper_1607_06834_amd import Rok
-    return Rok(pb, precision)
+    return Rok(pb, precision, mgs)
+
+
+MGS = ["pass", "resident"]
 
 
 VARIANTS = {
@@ -147,12 +150,13 @@ def _arnoldi_case(mode, M=8, shape=(24, 20), recon="muscl"):
     return pb, P, y, F, mv(y, F)
 
 
+@pytest.mark.parametrize("mgs", MGS)
 @pytest.mark.parametrize("mode", ["fd", "exact"])
-def test_arnoldi_parity(dev, mode):
-    say("arnoldi", mode)
+def test_arnoldi_parity(dev, mode, mgs):
+    say("arnoldi", mode, mgs)
     pb, P, y, F, matvec = _arnoldi_case(mode)
     V, H, m = krylov.arnoldi(matvec, F, 8)
-    Vg, Hg, mg = gpu(pb).arnoldi(y.to(dev), F.to(dev), 8, "fd" if mode == "fd" else "exact")
+    Vg, Hg, mg = gpu(pb, mgs=mgs).arnoldi(y.to(dev), F.to(dev), 8, "fd" if mode == "fd" else "exact")
     assert mg == m == 8
     assert relerr(Hg.cpu(), H) <= 1e-12
     assert relerr(Vg.cpu().T, V) <= 1e-12
@@ -169,10 +173,11 @@ def test_arnoldi_zero_rhs_and_breakdown(dev):
     assert m == 0
 
 
+@pytest.mark.parametrize("mgs", MGS)
 @pytest.mark.parametrize("mode,recon,M", [("fd", "muscl", 8), ("exact", "muscl", 8), ("fd", "first", 6),
-                                          ("exact", "first", 0)])
-def test_rok_step_parity(dev, mode, recon, M):
-    say("step", mode, recon, M)
+                                          ("exact", "first", 0), ("fd", "muscl", 20)])
+def test_rok_step_parity(dev, mode, recon, M, mgs):
+    say("step", mode, recon, M, mgs)
     pb = ri.vortex_problem(24, recon)
     pb["n"] = (24, 20)
     P = oracle_problem(pb)
@@ -181,12 +186,14 @@ def test_rok_step_parity(dev, mode, recon, M):
     tab = ri.rok4_tableau()
     f, mv = rok.fv_system(P, mode)
     ref = rok.rok_step(f, mv, tab, M, h, y)
-    g = gpu(pb)
+    g = gpu(pb, mgs=mgs)
     out = g.step(y.to(dev), h, tab, M, "fd" if mode == "fd" else "exact").cpu()
     flags, meff = g.last_status()
     assert meff == M and flags == 0
     assert relerr(out, ref) <= 1e-12
     assert relerr(out - y, ref - y) <= 1e-11     # the increment itself
+    if mode == "fd":
+        assert torch.equal(out, ref)             # canonical arithmetic: bit for bit
 
 
 def test_vortex32_first_order_trajectory(dev):
@@ -205,6 +212,29 @@ def test_vortex32_first_order_trajectory(dev):
         yg = g.step(yg, h, tab, w["M"], "fd")
         e = relerr(yg.cpu(), yr)
         say("step", n, e, "bitwise" if torch.equal(yg.cpu(), yr) else "")
+        assert e <= 1e-12
+        assert torch.equal(yg.cpu(), yr)
+
+
+def test_bench_workload_one_step_full_size(dev):
+    """The benchmark configuration itself: 1024^2 MUSCL vortex, M = 16, FD
+    products, CFL 10, one step from the seeded state, in the launch
+    configuration the benchmark times (default MGS path) and with the
+    per-pass MGS path; both against the oracle."""
+    pb, y0, w = ri.workload("vortex1024_muscl")
+    say("bench workload one step", w)
+    P = oracle_problem(pb)
+    h = ri.cfl_step(pb, y0, w["cfl"])
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, "fd")
+    ref = rok.rok_step(f, mv, tab, w["M"], h, t64(y0))
+    for mgs in ("auto", "pass"):
+        g = gpu(pb, mgs=mgs)
+        out = g.step(torch.tensor(y0, device=dev), h, tab, w["M"], "fd").cpu()
+        flags, meff = g.last_status()
+        e = relerr(out, ref)
+        say("bench workload", mgs, e, "bitwise" if torch.equal(out, ref) else "")
+        assert meff == w["M"] and flags == 0
         assert e <= 1e-12
 
 
