@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU oracle sample")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="run only the roofline kernel loop and a calibration copy (for counter runs)")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with HBM bytes per launch of the roofline kernel (from counter runs)")
     ap.add_argument("--chain", action="store_true",
                     help="time a trajectory (each step starts from the previous result) instead of K passes "
                          "over the seeded input state")
@@ -59,7 +63,8 @@ def gpu_leg(args, pb, y0, w, tab, h):
         g.step(ya, h, tab, M, mode, out=yb)
         return (yb, ya) if args.chain else (ya, yb)
 
-    for _ in range(args.warmup):
+    steps = 0 if args.roofline_only else args.steps
+    for _ in range(0 if args.roofline_only else args.warmup):
         ya, yb = one_step(ya, yb)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -67,14 +72,14 @@ def gpu_leg(args, pb, y0, w, tab, h):
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         ya, yb = one_step(ya, yb)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
-    flags, meff = g.last_status()
-    finite = bool(torch.isfinite(yb if not args.chain else ya).all())
+    flags, meff = g.last_status() if steps else (0, 0)
+    finite = bool(torch.isfinite(yb if not args.chain else ya).all()) if steps else True
 
     # dominant-kernel roofline: FD Jacobian-vector product kernel, one launch per call
     N = g.N
@@ -95,12 +100,20 @@ def gpu_leg(args, pb, y0, w, tab, h):
     k1.record(stream)
     torch.cuda.synchronize()
     k_ms = k0.elapsed_time(k1) / args.kernel_reps
+    # calibration kernel for the HBM counters: a plain copy of one state vector (8 N bytes read, 8 N written)
+    calib = torch.empty_like(ya)
+    calib.copy_(ya)
+    torch.cuda.synchronize()
     alg_bytes = 4 * 8 * N  # reads y, v, f(y); writes w
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as fh:
+            traffic = json.load(fh).get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kern, "avg_launch_ms": round(k_ms, 5), "alg_bytes_per_launch": alg_bytes}
-    return {"ms_per_step": ev_ms / args.steps, "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite,
+    return {"ms_per_step": ev_ms / max(steps, 1), "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite,
             "roofline": roofline}
 
 
