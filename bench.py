@@ -39,12 +39,22 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the roofline kernel loop and a calibration copy (for counter runs)")
-    ap.add_argument("--traffic", default=None,
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_fd_jvp_vortex1024_muscl.json"),
                     help="JSON file with HBM bytes per launch of the roofline kernel (from counter runs)")
     ap.add_argument("--chain", action="store_true",
                     help="time a trajectory (each step starts from the previous result) instead of K passes "
                          "over the seeded input state")
     return ap.parse_args()
+
+
+def _residual_source_hash():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1607_06834_amd", "csrc")
+    data = b""
+    for name in ("rok_residual.hip", "rok_device.hpp"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            data += fh.read()
+    return hashlib.sha256(data).hexdigest()[:16]
 
 
 def gpu_leg(args, pb, y0, w, tab, h):
@@ -107,9 +117,12 @@ def gpu_leg(args, pb, y0, w, tab, h):
     alg_bytes = 4 * 8 * N  # reads y, v, f(y); writes w
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
+    if args.traffic and os.path.exists(args.traffic) and args.workload == "vortex1024_muscl":
         with open(args.traffic) as fh:
-            traffic = json.load(fh).get("hbm_bytes_per_launch")
+            rec = json.load(fh)
+        # counters are only valid for the kernel source they were taken on
+        if rec.get("source_sha256_16") == _residual_source_hash():
+            traffic = rec.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kern, "avg_launch_ms": round(k_ms, 5), "alg_bytes_per_launch": alg_bytes}
