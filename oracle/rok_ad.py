@@ -23,13 +23,21 @@ from . import fv
 from .krylov import BREAKDOWN_TOL
 
 
-def jvp_exact(P: fv.Problem, y: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
-    """J(y) v, differentiable with respect to y and v (double-backward form)."""
+def jvp_exact(P: fv.Problem, y: torch.Tensor, v: torch.Tensor, forward: bool = False) -> torch.Tensor:
+    """J(y) v, differentiable with respect to y and v.
+
+    forward=False: double-backward form, for reverse-mode differentiation of
+    the step; forward=True: forward-mode product, which nests inside an outer
+    forward-mode derivative (directional derivatives of whole trajectories).
+    """
+    if forward:
+        return fv.jvp_exact(P, y, v)
     _, t = torch.autograd.functional.jvp(lambda z: fv.residual(P, z), y, v, create_graph=True)
     return t
 
 
-def arnoldi(P: fv.Problem, y: torch.Tensor, f0: torch.Tensor, M: int, tol: float = BREAKDOWN_TOL):
+def arnoldi(P: fv.Problem, y: torch.Tensor, f0: torch.Tensor, M: int, tol: float = BREAKDOWN_TOL,
+            forward: bool = False):
     """Modified Gram-Schmidt Arnoldi on K_M(J(y), f0); returns (V N x m, H m x m, m).
 
     The breakdown decision (h_{j+1,j} <= tol ||(h_1j..h_{j+1,j})||) is taken
@@ -38,14 +46,14 @@ def arnoldi(P: fv.Problem, y: torch.Tensor, f0: torch.Tensor, M: int, tol: float
     N = f0.numel()
     M = min(M, N)
     beta = torch.sqrt(torch.dot(f0, f0))
-    if M == 0 or float(beta) == 0.0:
+    if M == 0 or float(beta.detach()) == 0.0:
         return f0.new_zeros(N, 0), f0.new_zeros(0, 0), 0
     zero = f0.new_zeros(())
     H = [[zero] * M for _ in range(M + 1)]
     cols = [f0 / beta]
     m = M
     for j in range(M):
-        w = jvp_exact(P, y, cols[j])
+        w = jvp_exact(P, y, cols[j], forward)
         for i in range(j + 1):
             hij = torch.dot(cols[i], w)
             H[i][j] = hij
@@ -54,8 +62,8 @@ def arnoldi(P: fv.Problem, y: torch.Tensor, f0: torch.Tensor, M: int, tol: float
             break
         hn = torch.sqrt(torch.dot(w, w))
         H[j + 1][j] = hn
-        colnorm = sum(float(H[i][j]) ** 2 for i in range(j + 2)) ** 0.5
-        if float(hn) <= tol * colnorm:
+        colnorm = sum(float(H[i][j].detach()) ** 2 for i in range(j + 2)) ** 0.5
+        if float(hn.detach()) <= tol * colnorm:
             m = j + 1
             break
         cols.append(w / hn)
@@ -64,17 +72,19 @@ def arnoldi(P: fv.Problem, y: torch.Tensor, f0: torch.Tensor, M: int, tol: float
     return V, Hm, m
 
 
-def rok_step(P: fv.Problem, tab: dict, M: int, h: float, y: torch.Tensor, frozen_basis: bool = False):
+def rok_step(P: fv.Problem, tab: dict, M: int, h: float, y: torch.Tensor, frozen_basis: bool = False,
+             forward: bool = False):
     """One ROK step (eq. 9) with exact products, differentiable in y.
 
     frozen_basis=True detaches V and H from y: the gradient then misses the
     dependence of the Krylov approximation on the state.  It exists only so
     that a test can show the gradient pins detect that omission.
+    forward=True: for use under an outer forward-mode derivative.
     """
     s = tab["s"]
     alpha, gam, b, gamma = tab["alpha"], tab["gam"], tab["b"], tab["gamma"]
     F1 = fv.residual(P, y)
-    V, H, m = arnoldi(P, y, F1, M)
+    V, H, m = arnoldi(P, y, F1, M, forward=forward)
     if frozen_basis:
         V, H = V.detach(), H.detach()
     if m > 0:
@@ -109,10 +119,10 @@ def rok_step(P: fv.Problem, tab: dict, M: int, h: float, y: torch.Tensor, frozen
     return yn
 
 
-def trajectory(P: fv.Problem, tab: dict, M: int, h: float, y0: torch.Tensor, nsteps: int):
+def trajectory(P: fv.Problem, tab: dict, M: int, h: float, y0: torch.Tensor, nsteps: int, forward: bool = False):
     y = y0
     for _ in range(nsteps):
-        y = rok_step(P, tab, M, h, y)
+        y = rok_step(P, tab, M, h, y, forward=forward)
     return y
 
 
@@ -127,6 +137,12 @@ def kinetic_energy(P: fv.Problem, y: torch.Tensor) -> torch.Tensor:
     for d in range(P.ndim):
         dV = dV * P.dx(d)
     return (0.5 * ke / rho).sum() * dV
+
+
+def directional_derivative(fn, y: torch.Tensor, d: torch.Tensor) -> float:
+    """<grad fn(y), d> by forward-mode differentiation (fn built with forward=True)."""
+    _, t = torch.func.jvp(fn, (y,), (d,))
+    return float(t)
 
 
 def gradient(fn, y: torch.Tensor) -> torch.Tensor:

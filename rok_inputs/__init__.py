@@ -239,7 +239,8 @@ WORKLOADS = {
     "vortex32_fo": dict(kind="vortex", n=32, recon="first", M=8, steps=10, cfl=5.0, jvp="fd", precision="fp64"),
     "vortex1024_muscl": dict(kind="vortex", n=1024, recon="muscl", M=16, steps=100, cfl=10.0, jvp="fd", precision="fp64"),
     "tgv2048_ns": dict(kind="tgv2", n=2048, recon="muscl", M=20, steps=20, cfl=50.0, jvp="exact", precision="fp32"),
-    "vortex512_adjoint": dict(kind="vortex", n=512, recon="first", M=16, steps=50, cfl=10.0, jvp="exact", precision="fp64"),
+    "vortex512_adjoint": dict(kind="vortex", n=512, recon="first", M=16, steps=50, cfl=2.0, jvp="exact", precision="fp64",
+                              perturb=True),
     "tgv256_3d": dict(kind="tgv3", n=256, recon="muscl", M=16, steps=20, cfl=10.0, jvp="exact", precision="fp32"),
 }
 
@@ -257,4 +258,6 @@ def workload(name, n=None):
     else:
         pb = tgv_problem(n, 3)
         y0 = tgv_state(pb)
+    if w.get("perturb"):
+        y0 = perturb_density(pb, y0)
     return pb, y0, w
