@@ -184,6 +184,52 @@ rok_status rok_arnoldi(rok_ctx* ctx, const double* y, const double* fy, int M, i
 rok_status rok_step(rok_ctx* ctx, const rok_tableau* tab, int M, int mode, double h,
                     const double* y_n, double* y_np1, void* work, size_t work_bytes, void* stream);
 
+/*
+ * Discrete adjoint of one ROK step (Sec. 2.2.2, eq. 9) taken with exact
+ * (tangent) Jacobian-vector products:
+ *   ybar_n = (d y_{n+1} / d y_n)^T ybar_np1
+ * where y_{n+1} is the step of rok_step with mode ROK_JVP_TANGENT.  The step
+ * is recomputed from y_n (checkpoint recomputation); its result is written
+ * to y_np1 when that pointer is non-null.  The reverse sweep differentiates
+ * every operation of the step, including the dependence of the Krylov basis
+ * V and of H on y_n (modified Gram-Schmidt in reverse, the normalisation of
+ * the first basis vector and the second-order residual adjoint of each
+ * product J(y_n) v_j), so the result is the gradient of the computed step,
+ * not of an idealised one.
+ *   tab, M, h:  as rok_step
+ *   y_n, ybar_np1, ybar_n, y_np1: N doubles each, device memory; ybar_n and
+ *               y_np1 may not alias any other argument
+ *   work:       rok_step_vjp_workspace_bytes(ctx, M, tab->s) bytes
+ * Euler physics and FP64 precision only (ROK_EUNSUPPORTED otherwise).
+ */
+rok_status rok_step_vjp(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
+                        const double* ybar_np1, double* ybar_n, double* y_np1, void* work, size_t work_bytes,
+                        void* stream);
+
+/* Bytes of device workspace rok_step_vjp needs (0 on invalid arguments). */
+size_t rok_step_vjp_workspace_bytes(const rok_ctx* ctx, int M, int s);
+
+/*
+ * Adjoint product of the residual (transposed Jacobian, Sec. 2.3 / eq. 11):
+ *   ybar = J(y)^T wbar          (accumulate = 0)
+ *   ybar = ybar + J(y)^T wbar   (accumulate = 1)
+ * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  Euler physics and
+ * FP64 precision only (ROK_EUNSUPPORTED otherwise).  Deterministic: each cell
+ * gathers its own contributions.
+ */
+rok_status rok_residual_vjp(rok_ctx* ctx, const double* y, const double* wbar, double* ybar, int accumulate,
+                            void* stream);
+
+/*
+ * First- and second-order adjoint in one pass: ybar (+)= J(y)^T wbar and
+ * ybar2 (+)= d/dt [J(y + t v)^T wbar] at t = 0 (the derivative of the adjoint
+ * product along v, needed to differentiate a Krylov basis built from exact
+ * products).  All arrays N doubles, device memory; same restrictions as
+ * rok_residual_vjp.
+ */
+rok_status rok_residual_vjp2(rok_ctx* ctx, const double* y, const double* v, const double* wbar, double* ybar,
+                             double* ybar2, int accumulate, void* stream);
+
 /* Copies the status word of `work` (ROK_FLAG_* bits of the last call that
  * used it) to *host_flags; synchronises `stream`. */
 rok_status rok_read_status(rok_ctx* ctx, const void* work, int* host_flags, void* stream);

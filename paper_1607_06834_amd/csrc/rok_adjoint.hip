@@ -1,0 +1,123 @@
+// Adjoint (transposed) Jacobian products of the finite-volume residual:
+//   ybar (+)= J(y)^T wbar                          (first-order adjoint)
+//   ybar2 (+)= d/dt [J(y + t v)^T wbar] at t = 0   (second-order adjoint)
+// for the Euler right-hand side f of Sec. 3.2, eq. (11) (first-order or
+// MUSCL-minmod reconstruction, Rusanov flux, periodic grid).
+//
+// f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d, so the adjoint of the face
+// a+1/2 (between cells a and a+1) is Fbar = (wbar_{a+1} - wbar_a) / dx_d, and
+// cell c collects Fbar^T dFhat/dU_c from every face whose stencil contains c
+// (first order: faces c-1/2, c+1/2; MUSCL: the four faces c-3/2 .. c+3/2).
+// Each thread owns one cell and gathers its own contributions, so the result
+// is deterministic without atomics; dFhat/dU_c is taken by forward-mode dual
+// numbers seeded on one conserved variable of c at a time, on the same flux
+// code as the residual.  With a second dual level (y + t v) the same kernel
+// returns the second-order adjoint in the tangent part.
+#include "rok.h"
+#include "rok_device.hpp"
+#include "rok_flux.hpp"
+#include "rok_kernels.hpp"
+
+namespace rok {
+
+template <int D, int RECON, bool SECOND>
+__global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const double* v, const double* wbar,
+                                            double* ybar, double* ybar2, int accumulate, const int* gate, int col) {
+    if (gate && col >= gate[0]) return;   // Krylov column beyond M_eff: nothing to add
+    constexpr int NV = D + 2;
+    constexpr int NS = (RECON == 0) ? 2 : 4;   // stencil cells of a face
+    constexpr int NF = (RECON == 0) ? 2 : 4;   // faces per direction whose stencil contains a cell
+    using T = typename std::conditional<SECOND, Dual<double>, double>::type;   // base: value (+ t-derivative)
+    using S = Dual<T>;                                                           // + derivative along e_{c,k}
+    const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+    const long ncell = G.ncell;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += stride) {
+        const int cx = (int)(c % n0);
+        const int cy = (int)((c / n0) % n1);
+        const int cz = (int)(c / ((long)n0 * n1));
+        T acc[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] = Sc<T>::make(0.0);
+        for (int d = 0; d < D; ++d) {
+            const double inv = G.invdx[d];
+            for (int f = 0; f < NF; ++f) {
+                // face between cells a and a+1 along d; stencil starts at s0
+                const int off_a = (RECON == 0) ? f - 1 : f - 2;      // a - c
+                const int off_s0 = (RECON == 0) ? off_a : off_a - 1;  // first stencil cell - c
+                const int kc = -off_s0;                               // position of c in the stencil
+                long cell[NS];
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    int o = off_s0 + q;
+                    int x = cx, yy = cy, z = cz;
+                    if (d == 0) x = wrap(cx + o, n0);
+                    else if (d == 1) yy = wrap(cy + o, n1);
+                    else z = wrap(cz + o, n2);
+                    cell[q] = ((long)z * n1 + yy) * n0 + x;
+                }
+                const long ca = cell[(RECON == 0) ? 0 : 1];
+                const long cb = cell[(RECON == 0) ? 1 : 2];
+                double fbar[NV];
+#pragma unroll
+                for (int m = 0; m < NV; ++m) fbar[m] = (wbar[m * ncell + cb] - wbar[m * ncell + ca]) * inv;
+                T base[NS][NV];
+#pragma unroll
+                for (int q = 0; q < NS; ++q)
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) {
+                        const long i = m * ncell + cell[q];
+                        if constexpr (SECOND) base[q][m] = T{y[i], v[i]};
+                        else base[q][m] = y[i];
+                    }
+                for (int k = 0; k < NV; ++k) {
+                    S U[NS][NV];
+#pragma unroll
+                    for (int q = 0; q < NS; ++q)
+#pragma unroll
+                        for (int m = 0; m < NV; ++m)
+                            U[q][m] = S{base[q][m], Sc<T>::make((q == kc && m == k) ? 1.0 : 0.0)};
+                    S Fh[NV];
+                    face_flux_cells<D, RECON, S>(G, U, d, Fh);
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) acc[k] = acc[k] + fbar[m] * Fh[m].d;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const long o = k * ncell + c;
+            if constexpr (SECOND) {
+                ybar[o] = accumulate ? ybar[o] + acc[k].v : acc[k].v;
+                ybar2[o] = accumulate ? ybar2[o] + acc[k].d : acc[k].d;
+            } else {
+                ybar[o] = accumulate ? ybar[o] + acc[k] : acc[k];
+            }
+        }
+    }
+}
+
+template <int D, int RECON>
+static hipError_t launch_vjp_t(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
+                               double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
+    long g = (G.ncell + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (v)
+        hipLaunchKernelGGL((k_vjp<D, RECON, true>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar, ybar2,
+                           accumulate, gate, col);
+    else
+        hipLaunchKernelGGL((k_vjp<D, RECON, false>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar,
+                           ybar2, accumulate, gate, col);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp(const Geom& G, int recon, const double* y, const double* v, const double* wbar, double* ybar,
+                      double* ybar2, int accumulate, hipStream_t st, const int* gate, int col) {
+    if (G.D == 2) return recon == 0 ? launch_vjp_t<2, 0>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st)
+                                    : launch_vjp_t<2, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+    return recon == 0 ? launch_vjp_t<3, 0>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st)
+                      : launch_vjp_t<3, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+}
+
+}  // namespace rok
+

@@ -85,6 +85,119 @@ hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, c
     return hipSuccess;
 }
 
+// The launch sequence of one ROK step into the carved workspace W.
+hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, double h, const double* y_n,
+                     double* y_np1, const rok::Work& W, hipStream_t st) {
+    const int s = tab->s;
+    const long N = c->G.N;
+    const bool ns = c->pb.physics == ROK_NS;
+    hipError_t e = rok::launch_init(W, M, s, st);
+    if (e != hipSuccess) return e;
+    {   // F_1 = f(y_n)
+        rok::ResArgs A = plain_args(y_n, W.F);
+        e = rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st);
+        if (e != hipSuccess) return e;
+    }
+    if (M > 0) {
+        e = arnoldi_core(c, W, y_n, W.F, M, mode, 0.0, W.V, st);
+        if (e != hipSuccess) return e;
+        e = rok::launch_lu(W, M, h * tab->gamma, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < s; ++i) {
+        double* Fi = W.F + (long)i * N;
+        if (i > 0) {
+            rok::ResArgs A = plain_args(y_n, Fi);
+            int t = 0;
+            for (int j = 0; j < i; ++j) {
+                double a = tab->alpha[i * ROK_MAX_STAGES + j];
+                if (a != 0.0) {
+                    A.xs[t] = W.K + (long)j * N;
+                    A.cs[t] = a;
+                    ++t;
+                }
+            }
+            A.nterm = t;
+            e = rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st);
+            if (e != hipSuccess) return e;
+        }
+        if (M > 0) {
+            e = rok::launch_project(W, W.V, Fi, N, M, st);
+            if (e != hipSuccess) return e;
+            double grow[ROK_MAX_STAGES];
+            for (int j = 0; j < ROK_MAX_STAGES; ++j) grow[j] = (j < i) ? tab->gam[i * ROK_MAX_STAGES + j] : 0.0;
+            e = rok::launch_lambda(W, M, i, grow, h, st);
+            if (e != hipSuccess) return e;
+        }
+        if (i + 1 < s)
+            e = rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, nullptr, nullptr, 0, nullptr, st);
+        else
+            e = rok::launch_recover(W, W.V, Fi, N, M, i, h, y_np1, y_n, W.K, s, tab->b, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Reverse sweep of one step whose forward quantities sit in W (exact
+// products): ybar_n = (d y_{n+1} / d y_n)^T ybar_np1.
+hipError_t step_adjoint(const rok_ctx* c, const rok_tableau* tab, int M, double h, const double* y_n,
+                        const double* ybar_np1, double* ybar_n, const rok::Work& W, const rok::AdjWork& A,
+                        hipStream_t st) {
+    const int s = tab->s;
+    const long N = c->G.N;
+    const int Mm = M > 0 ? M : 1;
+    const int recon = c->pb.recon;
+    hipError_t e = rok::launch_adj_init(A, M, s, st);
+    if (e != hipSuccess) return e;
+    e = rok::launch_adj_seed(A, ybar_np1, ybar_n, N, s, tab->b, st);
+    if (e != hipSuccess) return e;
+    rok::Work Wp = W;      // projection partials of V^T kbar go to the adjoint's buffer
+    Wp.partials = A.part;
+    for (int i = s - 1; i >= 0; --i) {
+        double* kbi = A.kbar + (long)i * N;
+        if (M > 0) {
+            e = rok::launch_project(Wp, W.V, kbi, N, M, st);
+            if (e != hipSuccess) return e;
+        }
+        double grow[ROK_MAX_STAGES];
+        for (int j = 0; j < ROK_MAX_STAGES; ++j) grow[j] = (j < i) ? tab->gam[i * ROK_MAX_STAGES + j] : 0.0;
+        if (M > 0) {
+            e = rok::launch_small_rev(W, A, Mm, i, grow, h, st);
+            if (e != hipSuccess) return e;
+        }
+        double* Fbar = (i == 0) ? A.Fbar0 : A.FB;
+        e = rok::launch_vbar_stage(W, A, Mm, i, h, Fbar, N, i == s - 1, st);
+        if (e != hipSuccess) return e;
+        if (i > 0) {   // Y_i = y_n + sum_j alpha_ij k_j;  ybar += J(Y_i)^T Fbar, kbar_j += alpha_ij (...)
+            const double* arow = tab->alpha + i * ROK_MAX_STAGES;
+            e = rok::launch_stage_state(y_n, W.K, arow, i, A.Yt, N, st);
+            if (e != hipSuccess) return e;
+            e = rok::launch_vjp(c->G, recon, A.Yt, nullptr, A.FB, A.Ybar, nullptr, 0, st);
+            if (e != hipSuccess) return e;
+            e = rok::launch_scatter(A, A.Ybar, ybar_n, arow, i, N, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (M > 0) {
+        e = rok::launch_abar_to_hbar(W, A, Mm, h * tab->gamma, st);
+        if (e != hipSuccess) return e;
+        for (int j = M - 1; j >= 0; --j) {
+            const double* vj = W.V + (long)j * N;
+            e = jvp_into(c, y_n, nullptr, vj, W.w, ROK_JVP_TANGENT, nullptr, 0.0, st);
+            if (e != hipSuccess) return e;
+            e = rok::launch_arnoldi_rev_col(W, A, M, j, N, st);
+            if (e != hipSuccess) return e;
+            // w = J(y) v_j:  vbar_j += J^T wbar,  ybar += d/dt [J(y + t v_j)^T wbar]
+            e = rok::launch_vjp(c->G, recon, y_n, vj, A.wbar, A.Vbar + (long)j * N, ybar_n, 1, st, W.ints, j);
+            if (e != hipSuccess) return e;
+        }
+        e = rok::launch_beta_rev(W, A, N, st);
+        if (e != hipSuccess) return e;
+    }
+    // F_1 = f(y_n)
+    return rok::launch_vjp(c->G, recon, y_n, nullptr, A.Fbar0, ybar_n, nullptr, 1, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -211,52 +324,63 @@ rok_status rok_step(rok_ctx* c, const rok_tableau* tab, int M, int mode, double 
     if (M < 0 || M > ROK_MAX_M || !(h == h)) return ROK_EINVAL;
     if ((long)M > c->G.N) M = (int)c->G.N;
     if (M > 0 && mode == ROK_JVP_FD && fp32(c)) return ROK_EUNSUPPORTED;
+    size_t need = rok::work_bytes(c->G.N, M, tab->s, true);
+    if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
+    rok::Work W = rok::carve(work, c->G.N, M, tab->s, true);
+    ROK_TRY(step_core(c, tab, M, mode, h, y_n, y_np1, W, (hipStream_t)stream));
+    return ROK_OK;
+}
+
+size_t rok_step_vjp_workspace_bytes(const rok_ctx* c, int M, int s) {
+    if (!c || M < 0 || s < 1 || s > ROK_MAX_STAGES) return 0;
+    int Mc = M > ROK_MAX_M ? ROK_MAX_M : M;
+    if ((long)Mc > c->G.N) Mc = (int)c->G.N;
+    return rok::work_bytes(c->G.N, Mc, s, true) + rok::adj_bytes(c->G.N, Mc, s);
+}
+
+rok_status rok_step_vjp(rok_ctx* c, const rok_tableau* tab, int M, double h, const double* y_n,
+                        const double* ybar_np1, double* ybar_n, double* y_np1, void* work, size_t wbytes,
+                        void* stream) {
+    if (!c || !tab || !y_n || !ybar_np1 || !ybar_n) return ROK_EINVAL;
+    if (!aligned(y_n, 8) || !aligned(ybar_np1, 8) || !aligned(ybar_n, 8) || (y_np1 && !aligned(y_np1, 8)))
+        return ROK_EINVAL;
+    if (ybar_n == y_n || ybar_n == ybar_np1 || (y_np1 && (y_np1 == y_n || y_np1 == ybar_n || y_np1 == ybar_np1)))
+        return ROK_EINVAL;
+    if (tab->s < 1 || tab->s > ROK_MAX_STAGES) return ROK_EINVAL;
+    if (M < 0 || M > ROK_MAX_M || !(h == h)) return ROK_EINVAL;
+    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    if ((long)M > c->G.N) M = (int)c->G.N;
     const int s = tab->s;
     const long N = c->G.N;
-    size_t need = rok::work_bytes(N, M, s, true);
-    if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
+    const size_t fwd = rok::work_bytes(N, M, s, true);
+    if (!work || !aligned(work, 256) || wbytes < fwd + rok::adj_bytes(N, M, s)) return ROK_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     rok::Work W = rok::carve(work, N, M, s, true);
-    const bool ns = c->pb.physics == ROK_NS;
-    const int Mm = M > 0 ? M : 1;
+    rok::AdjWork A = rok::adj_carve((char*)work + fwd, N, M, s);
+    ROK_TRY(step_core(c, tab, M, ROK_JVP_TANGENT, h, y_n, y_np1 ? y_np1 : A.Yt, W, st));
+    ROK_TRY(step_adjoint(c, tab, M, h, y_n, ybar_np1, ybar_n, W, A, st));
+    return ROK_OK;
+}
 
-    ROK_TRY(rok::launch_init(W, M, s, st));
-    // F_1 = f(y_n)
-    {
-        rok::ResArgs A = plain_args(y_n, W.F);
-        ROK_TRY(rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st));
-    }
-    if (M > 0) {
-        ROK_TRY(arnoldi_core(c, W, y_n, W.F, M, mode, 0.0, W.V, st));
-        ROK_TRY(rok::launch_lu(W, M, h * tab->gamma, st));
-    }
-    for (int i = 0; i < s; ++i) {
-        double* Fi = W.F + (long)i * N;
-        if (i > 0) {
-            rok::ResArgs A = plain_args(y_n, Fi);
-            int t = 0;
-            for (int j = 0; j < i; ++j) {
-                double a = tab->alpha[i * ROK_MAX_STAGES + j];
-                if (a != 0.0) {
-                    A.xs[t] = W.K + (long)j * N;
-                    A.cs[t] = a;
-                    ++t;
-                }
-            }
-            A.nterm = t;
-            ROK_TRY(rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st));
-        }
-        if (M > 0) {
-            ROK_TRY(rok::launch_project(W, W.V, Fi, N, M, st));
-            double grow[ROK_MAX_STAGES];
-            for (int j = 0; j < ROK_MAX_STAGES; ++j) grow[j] = (j < i) ? tab->gam[i * ROK_MAX_STAGES + j] : 0.0;
-            ROK_TRY(rok::launch_lambda(W, M, i, grow, h, st));
-        }
-        if (i + 1 < s)
-            ROK_TRY(rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, nullptr, nullptr, 0, nullptr, st));
-        else
-            ROK_TRY(rok::launch_recover(W, W.V, Fi, N, M, i, h, y_np1, y_n, W.K, s, tab->b, st));
-    }
+rok_status rok_residual_vjp(rok_ctx* c, const double* y, const double* wbar, double* ybar, int accumulate,
+                            void* stream) {
+    if (!c || !y || !wbar || !ybar || !aligned(y, 8) || !aligned(wbar, 8) || !aligned(ybar, 8)) return ROK_EINVAL;
+    if (ybar == y || ybar == wbar) return ROK_EINVAL;
+    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    ROK_TRY(rok::launch_vjp(c->G, c->pb.recon, y, nullptr, wbar, ybar, nullptr, accumulate ? 1 : 0,
+                            (hipStream_t)stream));
+    return ROK_OK;
+}
+
+rok_status rok_residual_vjp2(rok_ctx* c, const double* y, const double* v, const double* wbar, double* ybar,
+                             double* ybar2, int accumulate, void* stream) {
+    if (!c || !y || !v || !wbar || !ybar || !ybar2) return ROK_EINVAL;
+    if (!aligned(y, 8) || !aligned(v, 8) || !aligned(wbar, 8) || !aligned(ybar, 8) || !aligned(ybar2, 8))
+        return ROK_EINVAL;
+    if (ybar == ybar2 || ybar == y || ybar == wbar || ybar == v || ybar2 == y || ybar2 == wbar || ybar2 == v)
+        return ROK_EINVAL;
+    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    ROK_TRY(rok::launch_vjp(c->G, c->pb.recon, y, v, wbar, ybar, ybar2, accumulate ? 1 : 0, (hipStream_t)stream));
     return ROK_OK;
 }
 

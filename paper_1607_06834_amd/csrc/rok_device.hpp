@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rok {
 
 constexpr int kMaxStages = 8;
@@ -55,13 +57,17 @@ template <typename T> __device__ __forceinline__ Dual<T> operator+(Dual<T> a, Du
 template <typename T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
 template <typename T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
 template <typename T> __device__ __forceinline__ Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-template <typename T> __device__ __forceinline__ Dual<T> operator*(T a, Dual<T> b) { return {a * b.v, a * b.d}; }
-template <typename T> __device__ __forceinline__ Dual<T> operator*(Dual<T> a, T b) { return {a.v * b, a.d * b}; }
 template <typename T> __device__ __forceinline__ Dual<T> operator/(Dual<T> a, Dual<T> b) {
     T q = a.v / b.v;
     return {q, (a.d - q * b.d) / b.v};
 }
-template <typename T> __device__ __forceinline__ Dual<T> operator/(Dual<T> a, T b) { return {a.v / b, a.d / b}; }
+// products and quotients with a plain floating-point constant (any nesting depth)
+template <typename T, typename R, typename = typename std::enable_if<std::is_floating_point<R>::value>::type>
+__device__ __forceinline__ Dual<T> operator*(R a, Dual<T> b) { return {a * b.v, a * b.d}; }
+template <typename T, typename R, typename = typename std::enable_if<std::is_floating_point<R>::value>::type>
+__device__ __forceinline__ Dual<T> operator*(Dual<T> a, R b) { return {a.v * b, a.d * b}; }
+template <typename T, typename R, typename = typename std::enable_if<std::is_floating_point<R>::value>::type>
+__device__ __forceinline__ Dual<T> operator/(Dual<T> a, R b) { return {a.v / b, a.d / b}; }
 
 // Scalar traits: value part (for branch decisions), construction, sqrt.
 template <typename S> struct Sc;
@@ -77,21 +83,12 @@ template <> struct Sc<float> {
     static __device__ __forceinline__ float make(double x) { return (float)x; }
     static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
 };
-template <> struct Sc<Dual<double>> {
-    using R = double;
-    static __device__ __forceinline__ double val(Dual<double> x) { return x.v; }
-    static __device__ __forceinline__ Dual<double> make(double x) { return {x, 0.0}; }
-    static __device__ __forceinline__ Dual<double> sqrt_(Dual<double> x) {
-        double s = sqrt(x.v);
-        return {s, x.d / (s + s)};
-    }
-};
-template <> struct Sc<Dual<float>> {
-    using R = float;
-    static __device__ __forceinline__ float val(Dual<float> x) { return x.v; }
-    static __device__ __forceinline__ Dual<float> make(double x) { return {(float)x, 0.0f}; }
-    static __device__ __forceinline__ Dual<float> sqrt_(Dual<float> x) {
-        float s = sqrtf(x.v);
+template <typename T> struct Sc<Dual<T>> {
+    using R = typename Sc<T>::R;
+    static __device__ __forceinline__ R val(Dual<T> x) { return Sc<T>::val(x.v); }
+    static __device__ __forceinline__ Dual<T> make(double x) { return {Sc<T>::make(x), Sc<T>::make(0.0)}; }
+    static __device__ __forceinline__ Dual<T> sqrt_(Dual<T> x) {
+        T s = Sc<T>::sqrt_(x.v);
         return {s, x.d / (s + s)};
     }
 };

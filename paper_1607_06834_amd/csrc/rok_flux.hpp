@@ -1,0 +1,128 @@
+// Pointwise pieces of the finite-volume right-hand side f (Sec. 3.2, eq. 11),
+// templated on the scalar type (double, float, or dual numbers for exact
+// derivatives): |.| and minmod with the branch rules of the reconstruction,
+// the physical Euler flux, Rusanov's flux, primitive <-> conserved variables
+// and the flux of one face from the conserved states of its stencil cells.
+// Every formula keeps one fixed, left-to-right operation order.
+#pragma once
+
+#include "rok_device.hpp"
+
+namespace rok {
+
+template <typename S> __device__ __forceinline__ S sabs(S x) { return Sc<S>::val(x) >= 0 ? x : -x; }
+
+template <typename S> __device__ __forceinline__ S minmod(S a, S b) {
+    using R = typename Sc<S>::R;
+    if (Sc<S>::val(a) * Sc<S>::val(b) <= (R)0) return Sc<S>::make(0.0);
+    return (Sc<S>::val(sabs(a)) <= Sc<S>::val(sabs(b))) ? a : b;
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void euler_flux(const S* U, const S* vel, S p, int d, S* F) {
+    S un = vel[d];
+    F[0] = U[1 + d];
+#pragma unroll
+    for (int e = 0; e < D; ++e) F[1 + e] = (e == d) ? U[1 + e] * un + p : U[1 + e] * un;
+    F[D + 1] = (U[D + 1] + p) * un;
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void rusanov(const Geom& G, int d, const S* UL, S rL, const S* vL, S pL,
+                                        const S* UR, S rR, const S* vR, S pR, S* Fh) {
+    using R = typename Sc<S>::R;
+    const R g = (R)G.g;
+    const R half = (R)0.5;
+    S cL = Sc<S>::sqrt_(g * pL / rL);
+    S cR = Sc<S>::sqrt_(g * pR / rR);
+    S sL = sabs(vL[d]) + cL;
+    S sR = sabs(vR[d]) + cR;
+    S a = (Sc<S>::val(sL) >= Sc<S>::val(sR)) ? sL : sR;
+    S FL[D + 2], FR[D + 2];
+    euler_flux<D>(UL, vL, pL, d, FL);
+    euler_flux<D>(UR, vR, pR, d, FR);
+    S ha = half * a;
+#pragma unroll
+    for (int m = 0; m < D + 2; ++m) Fh[m] = half * (FL[m] + FR[m]) - ha * (UR[m] - UL[m]);
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void to_conserved(const Geom& G, S r, const S* vel, S p, S* U) {
+    using R = typename Sc<S>::R;
+    const R gm1 = (R)G.gm1;
+    const R half = (R)0.5;
+    S ke = vel[0] * vel[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
+    U[0] = r;
+#pragma unroll
+    for (int d = 0; d < D; ++d) U[1 + d] = r * vel[d];
+    U[D + 1] = p / gm1 + (half * r) * ke;
+}
+
+
+template <int D, typename S>
+__device__ __forceinline__ void primitives(const Geom& G, const S* U, S& r, S* vel, S& p) {
+    using R = typename Sc<S>::R;
+    const R gm1 = (R)G.gm1;
+    const R half = (R)0.5;
+    r = U[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) vel[d] = U[1 + d] / r;
+    S ke = vel[0] * vel[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
+    p = gm1 * (U[D + 1] - (half * r) * ke);
+}
+
+// Inviscid flux of the face between stencil cells a and b = a + 1 along d,
+// from the conserved states of the stencil: first order U[0] = a, U[1] = b;
+// MUSCL U[0..3] = a-1, a, b, b+1.
+template <int D, int RECON, typename S>
+__device__ __forceinline__ void face_flux_cells(const Geom& G, const S (*U)[D + 2], int d, S* Fh) {
+    using R = typename Sc<S>::R;
+    constexpr int NV = D + 2;
+    S UL[NV], UR[NV], vL[D], vR[D], rL, rR, pL, pR;
+    if constexpr (RECON == 0) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            UL[m] = U[0][m];
+            UR[m] = U[1][m];
+        }
+        primitives<D>(G, UL, rL, vL, pL);
+        primitives<D>(G, UR, rR, vR, pR);
+    } else {
+        const R half = (R)0.5;
+        S q[4][NV];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            S rr, vv[D], pp;
+            primitives<D>(G, U[k], rr, vv, pp);
+            q[k][0] = rr;
+#pragma unroll
+            for (int e = 0; e < D; ++e) q[k][1 + e] = vv[e];
+            q[k][D + 1] = pp;
+        }
+        S qL[NV], qR[NV];
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            S am1 = q[0][m], a0 = q[1][m], ap1 = q[2][m], ap2 = q[3][m];
+            qL[m] = a0 + half * minmod(a0 - am1, ap1 - a0);
+            qR[m] = ap1 - half * minmod(ap1 - a0, ap2 - ap1);
+        }
+        rL = qL[0];
+        rR = qR[0];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            vL[e] = qL[1 + e];
+            vR[e] = qR[1 + e];
+        }
+        pL = qL[D + 1];
+        pR = qR[D + 1];
+        to_conserved<D>(G, rL, vL, pL, UL);
+        to_conserved<D>(G, rR, vR, pR, UR);
+    }
+    rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+}
+
+}  // namespace rok

@@ -11,6 +11,11 @@ namespace rok {
 hipError_t launch_residual(const Geom& G, int recon, bool ns, bool fp32, int kind, bool out_double,
                            const ResArgs& A, hipStream_t st);
 
+// Adjoint products (rok_adjoint.hip): ybar (+)= J^T wbar; with v: ybar2 (+)= d/dt J(y+tv)^T wbar.
+// With gate: does nothing when col >= gate[0] (gate = the step's M_eff word).
+hipError_t launch_vjp(const Geom& G, int recon, const double* y, const double* v, const double* wbar, double* ybar,
+                      double* ybar2, int accumulate, hipStream_t st, const int* gate = nullptr, int col = 0);
+
 // Device scratch layout of the Krylov / step kernels (carved from the
 // caller's workspace; 256-byte aligned regions).
 struct Work {
@@ -60,5 +65,41 @@ hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, dou
 // writes y_{n+1} = y + sum_{q<s} b_q k_q into k instead, K holding k_0..k_{s-2}.
 hipError_t launch_recover(const Work& W, const double* V, const double* F, long n, int M, int i, double h, double* k,
                           const double* y, const double* K, int s, const double* b, hipStream_t st);
+
+// Discrete adjoint of the ROK step (rok_step_adjoint.hip).  Carved after the
+// forward step's workspace; lambar, phibar are s x M, Hbar (M+1) x M, Abar
+// M x M (leading dimension M, as H and LU).
+struct AdjWork {
+    double* Hbar;
+    double* Abar;
+    double* lambar;
+    double* phibar;
+    double* part;    // (M + 3) x kRedBlocks: projection columns, then three MGS-reverse buffers
+    double* Vbar;    // M vectors
+    double* kbar;    // s vectors
+    double* Fbar0;   // adjoint of F_1 = f(y_n) (stage 0 and the first basis vector)
+    double* FB;      // adjoint of the current stage residual
+    double* Yt;      // current stage state
+    double* Ybar;    // J(Y_i)^T FB
+    double* wbar;    // adjoint of the MGS work vector
+    int M;
+};
+size_t adj_bytes(long N, int M, int s);
+AdjWork adj_carve(void* base, long N, int M, int s);
+hipError_t launch_adj_init(const AdjWork& A, int M, int s, hipStream_t st);
+hipError_t launch_adj_seed(const AdjWork& A, const double* ybar_out, double* ybar, long n, int s, const double* b,
+                           hipStream_t st);
+hipError_t launch_stage_state(const double* y, const double* K, const double* alpha_row, int i, double* Y, long n,
+                              hipStream_t st);
+hipError_t launch_scatter(const AdjWork& A, const double* Ybar, double* ybar, const double* alpha_row, int i, long n,
+                          hipStream_t st);
+hipError_t launch_small_rev(const Work& W, const AdjWork& A, int M, int i, const double* gam_row, double h,
+                            hipStream_t st);
+// first: initialise Vbar (the first stage reversed) instead of accumulating.
+hipError_t launch_vbar_stage(const Work& W, const AdjWork& A, int M, int i, double h, double* Fbar, long n,
+                             bool first, hipStream_t st);
+hipError_t launch_abar_to_hbar(const Work& W, const AdjWork& A, int M, double hg, hipStream_t st);
+hipError_t launch_arnoldi_rev_col(const Work& W, const AdjWork& A, int M, int j, long n, hipStream_t st);
+hipError_t launch_beta_rev(const Work& W, const AdjWork& A, long n, hipStream_t st);
 
 }  // namespace rok

@@ -19,18 +19,11 @@
 // Jacobian-vector product and with float for the FP32 form.
 #include "rok_device.hpp"
 #include "rok_kernels.hpp"
+#include "rok_flux.hpp"
 
 namespace rok {
 
 enum { MODE_PLAIN = 0, MODE_FD = 1, MODE_TAN = 2 };
-
-template <typename S> __device__ __forceinline__ S sabs(S x) { return Sc<S>::val(x) >= 0 ? x : -x; }
-
-template <typename S> __device__ __forceinline__ S minmod(S a, S b) {
-    using R = typename Sc<S>::R;
-    if (Sc<S>::val(a) * Sc<S>::val(b) <= (R)0) return Sc<S>::make(0.0);
-    return (Sc<S>::val(sabs(a)) <= Sc<S>::val(sabs(b))) ? a : b;
-}
 
 // Conserved state of one cell of the stage input.
 template <int MODE, int NV, typename S>
@@ -49,48 +42,6 @@ __device__ __forceinline__ void load_state(const ResArgs& A, long ncell, long gi
             U[m] = S{(R)A.y[k], (R)A.v[k]};
         }
     }
-}
-
-template <int D, typename S>
-__device__ __forceinline__ void euler_flux(const S* U, const S* vel, S p, int d, S* F) {
-    S un = vel[d];
-    F[0] = U[1 + d];
-#pragma unroll
-    for (int e = 0; e < D; ++e) F[1 + e] = (e == d) ? U[1 + e] * un + p : U[1 + e] * un;
-    F[D + 1] = (U[D + 1] + p) * un;
-}
-
-template <int D, typename S>
-__device__ __forceinline__ void rusanov(const Geom& G, int d, const S* UL, S rL, const S* vL, S pL,
-                                        const S* UR, S rR, const S* vR, S pR, S* Fh) {
-    using R = typename Sc<S>::R;
-    const R g = (R)G.g;
-    const R half = (R)0.5;
-    S cL = Sc<S>::sqrt_(g * pL / rL);
-    S cR = Sc<S>::sqrt_(g * pR / rR);
-    S sL = sabs(vL[d]) + cL;
-    S sR = sabs(vR[d]) + cR;
-    S a = (Sc<S>::val(sL) >= Sc<S>::val(sR)) ? sL : sR;
-    S FL[D + 2], FR[D + 2];
-    euler_flux<D>(UL, vL, pL, d, FL);
-    euler_flux<D>(UR, vR, pR, d, FR);
-    S ha = half * a;
-#pragma unroll
-    for (int m = 0; m < D + 2; ++m) Fh[m] = half * (FL[m] + FR[m]) - ha * (UR[m] - UL[m]);
-}
-
-template <int D, typename S>
-__device__ __forceinline__ void to_conserved(const Geom& G, S r, const S* vel, S p, S* U) {
-    using R = typename Sc<S>::R;
-    const R gm1 = (R)G.gm1;
-    const R half = (R)0.5;
-    S ke = vel[0] * vel[0];
-#pragma unroll
-    for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
-    U[0] = r;
-#pragma unroll
-    for (int d = 0; d < D; ++d) U[1 + d] = r * vel[d];
-    U[D + 1] = p / gm1 + (half * r) * ke;
 }
 
 // Tile shapes.  Box = tile + 2 halo cells on each side.

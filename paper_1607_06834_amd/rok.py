@@ -25,7 +25,8 @@ FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER = 1, 2, 4, 8
 MAX_STAGES, MAX_M = 8, 64
 
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual",
-           "rok_jvp", "rok_arnoldi", "rok_step", "rok_read_status", "rok_read_meff", "rok_strerror"]
+           "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
+           "rok_step_vjp_workspace_bytes", "rok_read_status", "rok_read_meff", "rok_strerror"]
 MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
@@ -76,6 +77,14 @@ def load_library(path: str = LIB_PATH):
     lib.rok_arnoldi.restype = i
     lib.rok_step.argtypes = [vp, ctypes.POINTER(RokTableau), i, i, d, vp, vp, vp, sz, vp]
     lib.rok_step.restype = i
+    lib.rok_residual_vjp.argtypes = [vp, vp, vp, vp, i, vp]
+    lib.rok_residual_vjp.restype = i
+    lib.rok_residual_vjp2.argtypes = [vp, vp, vp, vp, vp, vp, i, vp]
+    lib.rok_residual_vjp2.restype = i
+    lib.rok_step_vjp.argtypes = [vp, ctypes.POINTER(RokTableau), i, d, vp, vp, vp, vp, vp, sz, vp]
+    lib.rok_step_vjp.restype = i
+    lib.rok_step_vjp_workspace_bytes.argtypes = [vp, i, i]
+    lib.rok_step_vjp_workspace_bytes.restype = sz
     lib.rok_read_status.argtypes = [vp, vp, ctypes.POINTER(i), vp]
     lib.rok_read_status.restype = i
     lib.rok_read_meff.argtypes = [vp, vp, ctypes.POINTER(i), vp]
@@ -150,9 +159,14 @@ class Rok:
             self._ctx = None
 
     # -- workspace ---------------------------------------------------------
-    def workspace(self, M: int, s: int) -> torch.Tensor:
-        nb = int(_lib.rok_workspace_bytes(self._ctx, int(M), int(s)))
-        key = (int(M), int(s))
+    def workspace(self, M: int, s: int, adjoint: bool = False) -> torch.Tensor:
+        if adjoint:
+            nb = int(_lib.rok_step_vjp_workspace_bytes(self._ctx, int(M), int(s)))
+        else:
+            nb = int(_lib.rok_workspace_bytes(self._ctx, int(M), int(s)))
+        if nb == 0:
+            raise ValueError(f"invalid workspace request M={M}, s={s}")
+        key = (int(M), int(s), bool(adjoint))
         w = self._work.get(key)
         if w is None or w.numel() < nb:
             w = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
@@ -214,6 +228,43 @@ class Rok:
                              ws.numel(), _stream()), "rok_step")
         self._last_step_ws = ws
         return y1
+
+    def vjp(self, y, wbar, v=None, accumulate_into=None, accumulate_into2=None):
+        """J(y)^T wbar; with v also d/dt [J(y + t v)^T wbar] (returned as a pair).
+
+        accumulate_into(2): add to these tensors instead of returning new ones.
+        """
+        self._vec(y, "y")
+        self._vec(wbar, "wbar")
+        acc = accumulate_into is not None
+        yb = accumulate_into if acc else torch.empty_like(y)
+        self._vec(yb, "ybar")
+        if v is None:
+            _check(_lib.rok_residual_vjp(self._ctx, _ptr(y), _ptr(wbar), _ptr(yb), int(acc), _stream()),
+                   "rok_residual_vjp")
+            return yb
+        self._vec(v, "v")
+        if acc != (accumulate_into2 is not None):
+            raise ValueError("accumulate both outputs or neither")
+        yb2 = accumulate_into2 if acc else torch.empty_like(y)
+        self._vec(yb2, "ybar2")
+        _check(_lib.rok_residual_vjp2(self._ctx, _ptr(y), _ptr(v), _ptr(wbar), _ptr(yb), _ptr(yb2), int(acc),
+                                      _stream()), "rok_residual_vjp2")
+        return yb, yb2
+
+    def step_vjp(self, y, ybar_next, h: float, tableau: dict, M: int, y_next_out=None, out=None):
+        """(d y_{n+1}/d y_n)^T ybar_next for the exact-product step from y; optionally writes y_{n+1}."""
+        self._vec(y, "y")
+        self._vec(ybar_next, "ybar_next")
+        yb = out if out is not None else torch.empty_like(y)
+        self._vec(yb, "out")
+        if y_next_out is not None:
+            self._vec(y_next_out, "y_next_out")
+        tab = make_tableau(tableau)
+        ws = self.workspace(M, tab.s, adjoint=True)
+        _check(_lib.rok_step_vjp(self._ctx, ctypes.byref(tab), int(M), float(h), _ptr(y), _ptr(ybar_next), _ptr(yb),
+                                 _ptr(y_next_out), _ptr(ws), ws.numel(), _stream()), "rok_step_vjp")
+        return yb
 
     def last_status(self) -> tuple[int, int]:
         """(flags, M_eff) of the last step (synchronises the stream)."""

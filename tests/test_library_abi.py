@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "rok.h")).read()
-    return sorted(set(re.findall(r"\b(rok_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(rok_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
