@@ -29,6 +29,9 @@ constexpr int kPT = 1024;                       // threads per block
 constexpr int kPB = kRedBlocks * kRedThreads / kPT;  // 256 blocks
 constexpr double kBreakdownTolR = 1e-13;
 constexpr long kSpinLimit = 1L << 22;
+// s_waitcnt operand with vmcnt = 0 and the other counters at their maximum
+// (gfx9 encoding: vmcnt[3:0] and [15:14], expcnt[6:4], lgkmcnt[11:8]).
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 #define AGENT __HIP_MEMORY_SCOPE_AGENT
 
@@ -81,20 +84,30 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar) {
     return s_err != 0;
 }
 
-// Canonical sum of the lane values `acc` over the grid; every block returns
-// the same value.  part: 2 x kRedBlocks doubles, `phase` selects the half.
-__device__ __forceinline__ bool grid_sum(double acc, double* part, int phase, unsigned* bar, double* s, double* out) {
+// Canonical sum of the lane values `acc` over the grid, in two halves so the
+// caller can issue independent loads in between: publish() combines the
+// block's lanes and stores its partials, collect() waits for every block and
+// finishes the sum (every block obtains the same bits).
+// part: 2 x kRedBlocks doubles, `phase` selects the half.
+__device__ __forceinline__ void publish(double acc, double* part, int phase, double* s) {
     const int tid = threadIdx.x;
-    const int lane = tid & (kRedThreads - 1);
-    double g = tree256(acc, s);
-    double* p = part + phase * kRedBlocks;
-    if (lane == 0) __hip_atomic_store(p + blockIdx.x * (kPT / kRedThreads) + tid / kRedThreads, g,
-                                      __ATOMIC_RELAXED, AGENT);
+    const double g = tree256(acc, s);
+    if ((tid & (kRedThreads - 1)) == 0) {
+        __hip_atomic_store(part + phase * kRedBlocks + blockIdx.x * (kPT / kRedThreads) + tid / kRedThreads, g,
+                           __ATOMIC_RELAXED, AGENT);
+        // the partial must have reached the coherent level before this block
+        // can arrive at the grid barrier (the arrival is made by another wave)
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    }
+}
+
+__device__ __forceinline__ bool collect(const double* part, int phase, unsigned* bar, double* s, double* out) {
+    const int tid = threadIdx.x;
     if (grid_sync(bar)) return false;
     // all kRedBlocks partials fetched in parallel (one per thread), then lane t
     // adds partials t, t+256, t+512, t+768 in order and the halving tree finishes
     static_assert(kPT == kRedBlocks, "one partial per thread");
-    double pv = __hip_atomic_load(p + tid, __ATOMIC_RELAXED, AGENT);
+    double pv = __hip_atomic_load(part + phase * kRedBlocks + tid, __ATOMIC_RELAXED, AGENT);
     s[tid] = pv;
     __syncthreads();
     double a = 0.0;
@@ -109,61 +122,123 @@ __device__ __forceinline__ bool grid_sum(double acc, double* part, int phase, un
     return true;
 }
 
+// x[k] = src[t + k T] for the nk chunks of lane t that lie below n, +0.0
+// past the end.  Each chunk is addressed from a uniform base (one scalar base
+// per chunk, one offset register for all), so the loads of all chunks are
+// issued back to back.
+template <int PER>
+__device__ __forceinline__ void load_lane(const double* __restrict__ src, int t, int nk, double (&x)[PER]) {
+    constexpr long T = (long)kPB * kPT;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const double* base = src + k * T;
+        x[k] = (k < nk) ? base[t] : 0.0;
+    }
+}
+
+// Work vector storage of one lane: registers, or (PER = 16, where three
+// register arrays of 16 doubles would exceed the 128 registers a lane has at
+// 1024 threads per block) the lane's own LDS slots, used as private storage.
+template <int PER, bool LDSW>
+struct LaneVec {
+    double r[LDSW ? 1 : PER];
+    double* l;
+    __device__ __forceinline__ double get(int k) const { return LDSW ? l[k * kPT + threadIdx.x] : r[k]; }
+    __device__ __forceinline__ void set(int k, double x) {
+        if constexpr (LDSW) l[k * kPT + threadIdx.x] = x;
+        else r[k] = x;
+    }
+};
+
 template <int PER>
 __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const double* V, long n, int M, int j,
                                                      double* H, double* vnext, int* ints, double* part,
                                                      unsigned* bar) {
+    constexpr bool LDSW = PER >= 16;
     __shared__ double s[kPT];
+    __shared__ double s_w[LDSW ? PER * kPT : 1];
     __shared__ int s_stop;
     if (threadIdx.x == 0) s_stop = ints[1];
     __syncthreads();
     if (s_stop) return;
-    const long T = (long)kPB * kPT;
-    const long t = (long)blockIdx.x * kPT + threadIdx.x;
+    constexpr long T = (long)kPB * kPT;
+    const int t = blockIdx.x * kPT + threadIdx.x;
+    const int nk = (t < n) ? (int)((n - 1 - t) / T) + 1 : 0;   // chunks of lane t inside the vector
+    // Wave 0 runs the grid barrier, whose atomics return in order behind any
+    // load of its own; the other waves load the next basis vector while the
+    // blocks meet, so a pass costs about max(load, barrier) rather than the
+    // sum.  Two basis-vector arrays alternate: at pass i one holds v_{i-1}
+    // (for the update w -= h v_{i-1}) and v_{i+1} is loaded into it after use.
+    const bool prefetch = threadIdx.x >= 64;
     // Lanes past the end hold +0.0: their products are +0.0 and adding +0.0
-    // to a lane sum that starts at +0.0 leaves it unchanged, so no branch is
-    // needed (loads are clamped in range and issued back to back).
-    double w[PER];
+    // to a lane sum that starts at +0.0 leaves it unchanged.
+    LaneVec<PER, LDSW> w;
+    w.l = s_w;
+    {
+        double x[PER];
+        load_lane<PER>(wsrc, t, nk, x);
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        long e = t + k * T;
-        double x = wsrc[e < n ? e : n - 1];
-        w[k] = (e < n) ? x : 0.0;
+        for (int k = 0; k < PER; ++k) w.set(k, x[k]);
     }
+    double A[PER], B[PER];
+    load_lane<PER>(V, t, nk, A);
     __shared__ double s_hcol[kMaxM + 1];
     int phase = 0;
-    for (int i = 0; i <= j; ++i) {
-        const double* v = V + (long)i * n;
-        double vv[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            long e = t + k * T;
-            double x = v[e < n ? e : n - 1];
-            vv[k] = (e < n) ? x : 0.0;
-        }
+    double h = 0.0;
+    bool failed = false;
+    // Pass i with cur = v_i and prev = v_{i-1}: w -= h_{i-1} prev (i > 0),
+    // h_i = <v_i, w>, then prev <- v_{i+1}.
+    auto pass = [&](int i, double (&cur)[PER], double (&prev)[PER]) {
+        if (i > 0 && !prefetch) load_lane<PER>(V + (long)i * n, t, nk, cur);
         double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) acc = acc + vv[k] * w[k];
-        double h;
-        if (!grid_sum(acc, part, phase, bar, s, &h)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                ints[1] = 1;
-                ints[2] |= ROK_FLAG_BARRIER;
+        for (int k = 0; k < PER; ++k) {
+            double wk = w.get(k);
+            if (i > 0) {
+                wk = wk - h * prev[k];
+                w.set(k, wk);
             }
+            acc = acc + cur[k] * wk;
+        }
+        publish(acc, part, phase, s);
+        if (i < j && prefetch) load_lane<PER>(V + (long)(i + 1) * n, t, nk, prev);
+        if (!collect(part, phase, bar, s, &h)) {
+            failed = true;
             return;
         }
         phase ^= 1;
         if (threadIdx.x == 0) s_hcol[i] = h;
         if (blockIdx.x == 0 && threadIdx.x == 0) H[i * M + j] = h;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) w[k] = w[k] - h * vv[k];
+    };
+    int i = 0;
+    for (;;) {
+        pass(i, A, B);
+        if (failed || i == j) break;
+        ++i;
+        pass(i, B, A);
+        if (failed || i == j) break;
+        ++i;
     }
-    if (j + 1 >= M) return;
+    if (failed) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ints[1] = 1;
+            ints[2] |= ROK_FLAG_BARRIER;
+        }
+        return;
+    }
+    // last update w -= h_j v_j (v_j is A after an even number of passes, else B)
+    const bool inA = (j % 2) == 0;
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) acc = acc + w[k] * w[k];
+    for (int k = 0; k < PER; ++k) {
+        const double wk = w.get(k) - h * (inA ? A[k] : B[k]);
+        w.set(k, wk);
+        acc = acc + wk * wk;
+    }
+    if (j + 1 >= M) return;
+    publish(acc, part, phase, s);
     double nn;
-    if (!grid_sum(acc, part, phase, bar, s, &nn)) {
+    if (!collect(part, phase, bar, s, &nn)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             ints[1] = 1;
             ints[2] |= ROK_FLAG_BARRIER;
@@ -172,7 +247,7 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
     }
     const double hn = sqrt(nn);
     double c = 0.0;
-    for (int i = 0; i <= j; ++i) c = c + s_hcol[i] * s_hcol[i];
+    for (int q = 0; q <= j; ++q) c = c + s_hcol[q] * s_hcol[q];
     c = c + hn * hn;
     const bool brk = hn <= kBreakdownTolR * sqrt(c);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -186,10 +261,8 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
     }
     if (brk) return;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        long e = t + k * T;
-        if (e < n) vnext[e] = w[k] / hn;
-    }
+    for (int k = 0; k < PER; ++k)
+        if (k < nk) vnext[t + k * T] = w.get(k) / hn;
 }
 
 template <int PER>
