@@ -6,9 +6,11 @@ ROK4 with Krylov dimension M = 16 and finite-difference Jacobian-vector
 products, fixed step at CFL 10.  Inputs are synthetic (seeded) and resident
 in HBM before the timed region starts.
 
-Prints one JSON line with the step rate, a roofline entry for the FD
-Jacobian-vector product kernel (timed live with HIP events on the launch
-stream) and the CPU oracle's rate on a bounded sample of the same workload.
+Prints one JSON line with the step rate, a roofline entry for the dominant
+kernel of the step (the modified Gram-Schmidt Arnoldi column) and one for the
+FD Jacobian-vector product kernel (both timed live with HIP events on the
+launch stream), and the CPU oracle's rate on a bounded sample of the same
+workload.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -39,19 +41,23 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the roofline kernel loop and a calibration copy (for counter runs)")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_fd_jvp_vortex1024_muscl.json"),
-                    help="JSON file with HBM bytes per launch of the roofline kernel (from counter runs)")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_vortex1024_muscl.json"),
+                    help="JSON file with HBM bytes per launch of the roofline kernels (from counter runs)")
     ap.add_argument("--chain", action="store_true",
                     help="time a trajectory (each step starts from the previous result) instead of K passes "
                          "over the seeded input state")
     return ap.parse_args()
 
 
-def _residual_source_hash():
+RESIDUAL_SOURCES = ("rok_residual.hip", "rok_flux.hpp", "rok_device.hpp")
+MGS_SOURCES = ("rok_mgs.hip", "rok_kernels.hpp", "rok_device.hpp")
+
+
+def _source_hash(names):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1607_06834_amd", "csrc")
     data = b""
-    for name in ("rok_residual.hip", "rok_device.hpp"):
+    for name in names:
         with open(os.path.join(csrc, name), "rb") as fh:
             data += fh.read()
     return hashlib.sha256(data).hexdigest()[:16]
@@ -91,43 +97,104 @@ def gpu_leg(args, pb, y0, w, tab, h):
     flags, meff = g.last_status() if steps else (0, 0)
     finite = bool(torch.isfinite(yb if not args.chain else ya).all()) if steps else True
 
-    # dominant-kernel roofline: FD Jacobian-vector product kernel, one launch per call
-    N = g.N
-    F = g.residual(ya) if w["precision"] == "fp64" else None
-    v = torch.randn(N, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
-    v /= torch.linalg.vector_norm(v)
-    out = torch.empty(N, dtype=torch.float64, device=dev)
-    kern = "FD Jacobian-vector product (MUSCL residual at y + eps v, minus f(y), over eps)"
-    eps = 1.0e-7
-    for _ in range(3):
-        g.jvp(ya, v, "fd", fy=F, eps=eps, out=out)
-    torch.cuda.synchronize()
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    for _ in range(args.kernel_reps):
-        g.jvp(ya, v, "fd", fy=F, eps=eps, out=out)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    k_ms = k0.elapsed_time(k1) / args.kernel_reps
     # calibration kernel for the HBM counters: a plain copy of one state vector (8 N bytes read, 8 N written)
     calib = torch.empty_like(ya)
     calib.copy_(ya)
     torch.cuda.synchronize()
-    alg_bytes = 4 * 8 * N  # reads y, v, f(y); writes w
-    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic) and args.workload == "vortex1024_muscl":
-        with open(args.traffic) as fh:
-            rec = json.load(fh)
-        # counters are only valid for the kernel source they were taken on
-        if rec.get("source_sha256_16") == _residual_source_hash():
-            traffic = rec.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kern, "avg_launch_ms": round(k_ms, 5), "alg_bytes_per_launch": alg_bytes}
+    mgs = _mgs_roofline(args, g, ya, M, mode, stream)
+    jvp = _jvp_roofline(args, g, ya, w, stream)
     return {"ms_per_step": ev_ms / max(steps, 1), "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite,
-            "roofline": roofline}
+            "roofline": mgs, "roofline_jvp": jvp}
+
+
+def _timed(stream, launches):
+    """Average milliseconds per launch: each callable in `launches` enqueues one
+    kernel, bracketed by its own pair of HIP events on `stream`, so host-side
+    gaps between launches are not counted."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in launches]
+    for (a, b), fn in zip(ev, launches):
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+
+
+def _traffic(path, sources, key):
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get(key)
+    # counters are only valid for the kernel source they were taken on
+    if not ent or ent.get("source_sha256_16") != _source_hash(sources):
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def _mgs_roofline(args, g, y, M, mode, stream):
+    """Dominant kernel of the step: one modified Gram-Schmidt column (Arnoldi, a4).
+
+    The basis of the step's Arnoldi process at y and the products w_j = J v_j
+    are prepared first; the timed loop then runs the M columns j = 0..M-1 as
+    the step does (one kernel launch per column).  Algorithmic bytes of column
+    j: w and v_0..v_j read, v_{j+1} written (when j + 1 < M)."""
+    import torch
+    N = g.N
+    F = g.residual(y).to(torch.float64)
+    V, H, m = g.arnoldi(y, F, M, mode)
+    V = V.contiguous()
+    Ws = torch.stack([g.jvp(y, V[j], mode="fd" if mode == "fd" else "tangent", fy=F, eps=1e-7).to(torch.float64)
+                      for j in range(m)])
+    Hs = torch.zeros(m + 1, m, dtype=torch.float64, device=y.device)
+    ws = g.mgs_workspace(m)
+
+    def column(j):
+        return lambda: g.mgs_column(V, j, Ws[j], Hs, ws, vnext=V[j + 1] if j + 1 < m else None)
+
+    for j in range(m):
+        column(j)()
+    torch.cuda.synchronize()
+    reps = max(1, args.kernel_reps // 4)
+    ms = _timed(stream, [column(j) for _ in range(reps) for j in range(m)])
+    alg = sum((j + 2) * 8 * N + (8 * N if j + 1 < m else 0) for j in range(m)) / m
+    achieved = alg / (ms * 1e-3) / 1e9
+    traffic = None
+    if args.workload == "vortex1024_muscl":
+        traffic = _traffic(args.traffic, MGS_SOURCES, "mgs_column")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"modified Gram-Schmidt Arnoldi column (k_mgs_resident), average over the {m} columns of a step",
+            "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": int(alg)}
+
+
+def _jvp_roofline(args, g, y, w, stream):
+    """The FD Jacobian-vector product kernel: reads y, v, f(y), writes w (32 B per element)."""
+    import torch
+    if w["precision"] != "fp64":
+        return None
+    N = g.N
+    dev = y.device
+    F = g.residual(y)
+    v = torch.randn(N, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+    v /= torch.linalg.vector_norm(v)
+    out = torch.empty(N, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        g.jvp(y, v, "fd", fy=F, eps=1e-7, out=out)
+    torch.cuda.synchronize()
+    ms = _timed(stream, [lambda: g.jvp(y, v, "fd", fy=F, eps=1e-7, out=out)] * args.kernel_reps)
+    alg = 4 * 8 * N
+    achieved = alg / (ms * 1e-3) / 1e9
+    traffic = None
+    if args.workload == "vortex1024_muscl":
+        traffic = _traffic(args.traffic, RESIDUAL_SOURCES, "fd_jvp")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "FD Jacobian-vector product (residual at y + eps v, minus f(y), over eps)",
+            "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": alg}
+
+
 
 
 def cpu_leg(args, pb, y0, w, tab, h):
@@ -190,6 +257,7 @@ def main():
                                    "over many steps)")},
         "status": {"flags": res["flags"], "M_eff": res["M_eff"], "finite": res["finite"]},
         "roofline": res["roofline"],
+        "roofline_jvp": res["roofline_jvp"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -171,6 +171,35 @@ rok_status rok_arnoldi(rok_ctx* ctx, const double* y, const double* fy, int M, i
                        double* V, double* H, int* M_eff, void* work, size_t work_bytes, void* stream);
 
 /*
+ * One column of modified Arnoldi (Sec. 2.2.2): orthogonalise w = J v_j
+ * against v_0..v_j by modified Gram-Schmidt, h_ij = <v_i, w>, w <- w - h_ij v_i
+ * (i = 0..j, in order), then, when j + 1 < M, h_{j+1,j} = ||w|| and
+ * v_{j+1} = w / h_{j+1,j} unless the breakdown test of rok_arnoldi holds.
+ * Sums are taken in the library's fixed order, so a sequence of calls
+ * j = 0..M-1 reproduces rok_arnoldi's V and H bit for bit.
+ *   V:      N x M doubles, column c at V + c*N; columns 0..j are read
+ *   M, j:   1 <= M <= min(ROK_MAX_M, N), 0 <= j < M
+ *   w:      N doubles holding J v_j; its contents are undefined on return
+ *   H:      (M + 1) x M doubles, row-major: writes H[i*M + j] (i <= j) and
+ *           H[(j+1)*M + j] when j + 1 < M
+ *   vnext:  N doubles (may be V + (j+1)*N), written when j + 1 < M and the
+ *           column did not break down
+ *   work:   rok_workspace_bytes(ctx, M, 0) bytes prepared by
+ *           rok_workspace_init(ctx, work, bytes, M, 0, stream); a breakdown
+ *           sets M_eff = j + 1 and ROK_FLAG_BREAKDOWN in its status header
+ *           (rok_read_meff / rok_read_status), after which later columns
+ *           are skipped until the workspace is initialised again.
+ * All pointers are device memory.
+ */
+rok_status rok_mgs_column(rok_ctx* ctx, const double* V, int M, int j, double* w, double* H, double* vnext,
+                          void* work, size_t work_bytes, void* stream);
+
+/* Prepare a workspace of rok_workspace_bytes(ctx, M, s) bytes for the
+ * column-level calls (status header cleared, M_eff = M).  The other entry
+ * points prepare their workspace themselves. */
+rok_status rok_workspace_init(rok_ctx* ctx, void* work, size_t work_bytes, int M, int s, void* stream);
+
+/*
  * One ROK step (Sec. 2.2.2, eq. 9): F_i = f(y_n + sum_j alpha_ij k_j),
  * phi_i = V^T F_i, lambda_i = (I - h gamma H)^{-1} (h phi_i + h H sum_j
  * gamma_ij lambda_j), k_i = V lambda_i + h (F_i - V phi_i),

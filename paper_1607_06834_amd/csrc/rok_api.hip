@@ -362,6 +362,38 @@ rok_status rok_step_vjp(rok_ctx* c, const rok_tableau* tab, int M, double h, con
     return ROK_OK;
 }
 
+rok_status rok_workspace_init(rok_ctx* c, void* work, size_t wbytes, int M, int s, void* stream) {
+    if (!c || !work || !aligned(work, 256) || M < 0 || M > ROK_MAX_M || s < 0 || s > ROK_MAX_STAGES)
+        return ROK_EINVAL;
+    if ((long)M > c->G.N) M = (int)c->G.N;
+    if (wbytes < rok::work_bytes(c->G.N, M, s, s > 0)) return ROK_EINVAL;
+    rok::Work W = rok::carve(work, c->G.N, M, s, s > 0);
+    ROK_TRY(rok::launch_init(W, M, s, (hipStream_t)stream));
+    return ROK_OK;
+}
+
+rok_status rok_mgs_column(rok_ctx* c, const double* V, int M, int j, double* w, double* H, double* vnext, void* work,
+                          size_t wbytes, void* stream) {
+    if (!c || !V || !w || !H || !work || !aligned(V, 8) || !aligned(w, 8) || !aligned(H, 8) || !aligned(work, 256))
+        return ROK_EINVAL;
+    if (M < 1 || M > ROK_MAX_M || (long)M > c->G.N || j < 0 || j >= M) return ROK_EINVAL;
+    if (j + 1 < M && (!vnext || !aligned(vnext, 8))) return ROK_EINVAL;
+    if (wbytes < rok::work_bytes(c->G.N, M, 0, false)) return ROK_EINVAL;
+    const long N = c->G.N;
+    rok::Work W = rok::carve(work, N, M, 0, false);
+    W.H = H;
+    hipStream_t st = (hipStream_t)stream;
+    const bool resident =
+        c->mgs_path != ROK_MGS_PER_PASS && rok::mgs_resident_per(N) > 0 && rok::mgs_resident_available();
+    if (c->mgs_path == ROK_MGS_RESIDENT && !resident) return ROK_EUNSUPPORTED;
+    double* vn = (j + 1 < M) ? vnext : nullptr;
+    if (resident)
+        ROK_TRY(rok::launch_mgs_resident(W, w, V, N, M, j, vn, st));
+    else
+        ROK_TRY(rok::launch_mgs_column(W, w, V, N, M, j, vn, st));
+    return ROK_OK;
+}
+
 rok_status rok_residual_vjp(rok_ctx* c, const double* y, const double* wbar, double* ybar, int accumulate,
                             void* stream) {
     if (!c || !y || !wbar || !ybar || !aligned(y, 8) || !aligned(wbar, 8) || !aligned(ybar, 8)) return ROK_EINVAL;

@@ -238,7 +238,7 @@ struct GamRow {
 
 // phi_i = V^T F_i finished from the projection partials (all columns at once,
 // canonical order per column), then
-// lambda_i = LU^{-1} (h phi_i + h H sum_{j<i} gamma_ij lambda_j) on one thread.
+// lambda_i = LU^{-1} (h phi_i + h H sum_{j<i} gamma_ij lambda_j) on the same block.
 __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const double* LU, const int* perm, int M,
                                                        int i, GamRow gr, double h, const double* partials,
                                                        double* phi, double* lam, int* ints) {
@@ -262,27 +262,45 @@ __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const d
         if (tid < nc) sphi[c0 + tid] = s[tid][0];
         __syncthreads();
     }
-    if (tid != 0) return;
-    __shared__ double g[kMaxM], x[kMaxM], y[kMaxM];
-    for (int c = 0; c < m; ++c) {
-        phi[i * M + c] = sphi[c];
-        g[c] = 0.0;
+    // The reduced solve.  H, LU, the pivots and the earlier lambdas are staged
+    // in LDS; the right-hand side is formed row-parallel and the forward
+    // substitution column-parallel (each entry still sees its updates in
+    // increasing column order); the back substitution, whose entries each
+    // need the next one first, runs on one lane from LDS.
+    __shared__ double sLU[kMaxM * kMaxM], sH[kMaxM * kMaxM];
+    __shared__ double g[kMaxM], y[kMaxM];
+    __shared__ int sperm[kMaxM];
+    for (int e = tid; e < m * m; e += kRedThreads) {
+        const int r = e / m, c = e % m;
+        sLU[r * kMaxM + c] = LU[r * M + c];
+        sH[r * kMaxM + c] = H[r * M + c];
     }
-    for (int j = 0; j < i; ++j) {
-        if (gr.g[j] != 0.0)
-            for (int c = 0; c < m; ++c) g[c] = g[c] + gr.g[j] * lam[j * M + c];
+    if (tid < m) {
+        sperm[tid] = perm[tid];
+        double a = 0.0;
+        for (int j = 0; j < i; ++j)
+            if (gr.g[j] != 0.0) a = a + gr.g[j] * lam[j * M + tid];
+        g[tid] = a;
+        phi[i * M + tid] = sphi[tid];
     }
-    for (int r = 0; r < m; ++r) {
+    __syncthreads();
+    if (tid < m) {   // x_r = h phi_r + h (H g)_r, placed at its pivoted position
         double hg = 0.0;
-        for (int c = 0; c < m; ++c) hg = hg + H[r * M + c] * g[c];
-        x[r] = h * sphi[r] + h * hg;
+        for (int c = 0; c < m; ++c) hg = hg + sH[tid * kMaxM + c] * g[c];
+        s[0][tid] = h * sphi[tid] + h * hg;
     }
-    for (int r = 0; r < m; ++r) y[r] = x[perm[r]];
-    for (int r = 0; r < m; ++r)
-        for (int c = 0; c < r; ++c) y[r] = y[r] - LU[r * M + c] * y[c];
+    __syncthreads();
+    if (tid < m) y[tid] = s[0][sperm[tid]];
+    __syncthreads();
+    for (int c = 0; c + 1 < m; ++c) {   // forward substitution with the unit lower factor
+        if (tid > c && tid < m) y[tid] = y[tid] - sLU[tid * kMaxM + c] * y[c];
+        __syncthreads();
+    }
+    if (tid != 0) return;
     for (int r = m - 1; r >= 0; --r) {
-        for (int c = r + 1; c < m; ++c) y[r] = y[r] - LU[r * M + c] * y[c];
-        y[r] = y[r] / LU[r * M + r];
+        double a = y[r];
+        for (int c = r + 1; c < m; ++c) a = a - sLU[r * kMaxM + c] * y[c];
+        y[r] = a / sLU[r * kMaxM + r];
     }
     bool bad = false;
     for (int r = 0; r < m; ++r) {

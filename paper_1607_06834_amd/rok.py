@@ -26,7 +26,7 @@ MAX_STAGES, MAX_M = 8, 64
 
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual",
            "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
-           "rok_step_vjp_workspace_bytes", "rok_read_status", "rok_read_meff", "rok_strerror"]
+           "rok_step_vjp_workspace_bytes", "rok_mgs_column", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
 MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
@@ -85,6 +85,10 @@ def load_library(path: str = LIB_PATH):
     lib.rok_step_vjp.restype = i
     lib.rok_step_vjp_workspace_bytes.argtypes = [vp, i, i]
     lib.rok_step_vjp_workspace_bytes.restype = sz
+    lib.rok_mgs_column.argtypes = [vp, vp, i, i, vp, vp, vp, vp, sz, vp]
+    lib.rok_mgs_column.restype = i
+    lib.rok_workspace_init.argtypes = [vp, vp, sz, i, i, vp]
+    lib.rok_workspace_init.restype = i
     lib.rok_read_status.argtypes = [vp, vp, ctypes.POINTER(i), vp]
     lib.rok_read_status.restype = i
     lib.rok_read_meff.argtypes = [vp, vp, ctypes.POINTER(i), vp]
@@ -265,6 +269,27 @@ class Rok:
         _check(_lib.rok_step_vjp(self._ctx, ctypes.byref(tab), int(M), float(h), _ptr(y), _ptr(ybar_next), _ptr(yb),
                                  _ptr(y_next_out), _ptr(ws), ws.numel(), _stream()), "rok_step_vjp")
         return yb
+
+    def mgs_workspace(self, M: int) -> torch.Tensor:
+        """A workspace for column-level calls, prepared for Krylov dimension M."""
+        ws = self.workspace(M, 0)
+        _check(_lib.rok_workspace_init(self._ctx, _ptr(ws), ws.numel(), int(M), 0, _stream()), "rok_workspace_init")
+        self._last_step_ws = ws
+        return ws
+
+    def mgs_column(self, V: torch.Tensor, j: int, w: torch.Tensor, H: torch.Tensor, ws: torch.Tensor,
+                   vnext: torch.Tensor | None = None):
+        """One modified Gram-Schmidt column: V is (M, N) with rows as basis vectors, H is (M + 1, M)."""
+        M = V.shape[0]
+        if not (V.is_cuda and V.dtype == torch.float64 and V.is_contiguous() and V.shape[1] == self.N):
+            raise ValueError("V: expected a contiguous (M, N) float64 CUDA tensor")
+        if not (H.is_cuda and H.dtype == torch.float64 and H.is_contiguous() and tuple(H.shape) == (M + 1, M)):
+            raise ValueError("H: expected a contiguous (M + 1, M) float64 CUDA tensor")
+        self._vec(w, "w")
+        if vnext is not None:
+            self._vec(vnext, "vnext")
+        _check(_lib.rok_mgs_column(self._ctx, _ptr(V), int(M), int(j), _ptr(w), _ptr(H), _ptr(vnext), _ptr(ws),
+                                   ws.numel(), _stream()), "rok_mgs_column")
 
     def last_status(self) -> tuple[int, int]:
         """(flags, M_eff) of the last step (synchronises the stream)."""

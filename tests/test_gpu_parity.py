@@ -162,6 +162,56 @@ def test_arnoldi_parity(dev, mode, mgs):
     assert relerr(Vg.cpu().T, V) <= 1e-12
 
 
+@pytest.mark.parametrize("mgs", MGS)
+@pytest.mark.parametrize("shape", [(37, 21), (70, 33)])
+def test_mgs_column_bitwise(dev, mgs, shape):
+    """One modified Gram-Schmidt column against the oracle's canonical dots, and
+    the column sequence against rok_arnoldi, bit for bit."""
+    say("mgs column", mgs, shape)
+    pb = VARIANTS["euler_muscl"](shape)
+    N = ri.size(pb)
+    M = 6
+    rng = np.random.default_rng(7)
+    # an orthonormal-ish basis from the oracle's own Arnoldi on a smooth state
+    P = oracle_problem(pb)
+    y = t64(_state(pb, 2))
+    F = fv.residual(P, y)
+    V, H, m = krylov.arnoldi(lambda v: fv.jvp_exact(P, y, v), F, M)
+    assert m == M
+    w = t64(rng.standard_normal(N))
+    j = M - 2
+    # oracle column j: h_ij = <v_i, w>, w -= h_ij v_i, then the norm and v_{j+1}
+    wr = w.clone()
+    href = []
+    for i in range(j + 1):
+        hij = krylov.dot(V[:, i], wr)
+        href.append(hij)
+        wr = wr - hij * V[:, i]
+    hn = float(np.sqrt(krylov.dot(wr, wr)))
+    vref = wr / hn
+    g = gpu(pb, mgs=mgs)
+    Vd = V.T.contiguous().to(dev)
+    Hd = torch.zeros(M + 1, M, dtype=torch.float64, device=dev)
+    vn = torch.empty(N, dtype=torch.float64, device=dev)
+    ws = g.mgs_workspace(M)
+    g.mgs_column(Vd, j, w.to(dev), Hd, ws, vnext=vn)
+    Hc = Hd.cpu()
+    assert [float(Hc[i, j]) for i in range(j + 1)] == href
+    assert float(Hc[j + 1, j]) == hn
+    assert torch.equal(vn.cpu(), vref)
+    # the columns j = 0..M-1 with w = J v_j reproduce rok_arnoldi bit for bit
+    Vg, Hg, mg = g.arnoldi(y.to(dev), F.to(dev), M, "exact")
+    Vc = torch.zeros(M, N, dtype=torch.float64, device=dev)
+    Vc[0] = Vg[0]
+    Hs = torch.zeros(M + 1, M, dtype=torch.float64, device=dev)
+    ws = g.mgs_workspace(M)
+    for jj in range(M):
+        wj = g.jvp(y.to(dev), Vc[jj], mode="tangent")
+        g.mgs_column(Vc, jj, wj, Hs, ws, vnext=Vc[jj + 1] if jj + 1 < M else None)
+    assert torch.equal(Vc, Vg)
+    assert torch.equal(Hs[:M], Hg)
+
+
 def test_arnoldi_zero_rhs_and_breakdown(dev):
     say("arnoldi breakdown")
     pb = ri.vortex_problem(8, "muscl")
