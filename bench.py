@@ -12,7 +12,11 @@ FD Jacobian-vector product kernel (both timed live with HIP events on the
 launch stream), and the CPU oracle's rate on a bounded sample of the same
 workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+It also runs the precision form's equal-error comparison (FP32 residual and
+tangent products vs plain FP64 with finite-difference products, a
+work-precision sweep on a 512^2 Taylor-Green proxy).
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-equal-error]
 """
 from __future__ import annotations
 
@@ -43,6 +47,8 @@ def parse():
                     help="run only the roofline kernel loop and a calibration copy (for counter runs)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_vortex1024_muscl.json"),
                     help="JSON file with HBM bytes per launch of the roofline kernels (from counter runs)")
+    ap.add_argument("--no-equal-error", action="store_true",
+                    help="skip the FP32-tangent vs FP64-FD equal-error sweep")
     ap.add_argument("--chain", action="store_true",
                     help="time a trajectory (each step starts from the previous result) instead of K passes "
                          "over the seeded input state")
@@ -197,6 +203,68 @@ def _jvp_roofline(args, g, y, w, stream):
 
 
 
+def equal_error_leg(args):
+    """FP32 residual/tangent + FP64 Krylov against plain FP64 with finite-difference
+    products, at equal final-time error (work-precision sweep).
+
+    Proxy of the viscous Taylor-Green workload at 512^2 (Re 100, Mach 0.1,
+    MUSCL, M = 20).  Both forms integrate to the same final time T = 10 h(CFL 4)
+    at CFL 1, 2, 4, 8; the error is ||y_N - y_ref|| / ||y_ref|| with y_ref the
+    FP64 exact-product ROK solution at CFL 1/8 (320 steps; it agrees with
+    explicit RK4 at CFL 1/4 to about 3e-12).  Trajectories are timed with HIP
+    events.  speedup_at_equal_error: for each FP32 point, the FD time at the same
+    error (log-log interpolation between the bracketing FD points) over the FP32
+    time."""
+    import torch
+
+    import rok_inputs as ri
+    from paper_1607_06834_amd import Rok
+
+    dev = torch.device("cuda", 0)
+    pb = ri.tgv_problem(512, 2)
+    y0 = ri.tgv_state(pb)
+    tab = ri.rok4_tableau()
+    M = 20
+    T = 10 * ri.cfl_step(pb, y0, 4.0)
+    g64, g32 = Rok(pb, "fp64"), Rok(pb, "fp32")
+    stream = torch.cuda.current_stream()
+
+    def run(g, cfl, mode):
+        K = int(round(T / ri.cfl_step(pb, y0, cfl)))
+        h = T / K
+        y = torch.tensor(y0, device=dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(K):
+            y = g.step(y, h, tab, M, mode)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return y, e0.elapsed_time(e1), K
+
+    ref, _, _ = run(g64, 0.125, "exact")
+    nref = float(torch.linalg.vector_norm(ref))
+    pts = {"fp64_fd": [], "fp32_tangent": []}
+    for cfl in (1.0, 2.0, 4.0, 8.0):
+        for name, g, mode in (("fp64_fd", g64, "fd"), ("fp32_tangent", g32, "exact")):
+            y, ms, K = run(g, cfl, mode)
+            err = float(torch.linalg.vector_norm(y - ref)) / nref
+            pts[name].append({"cfl": cfl, "steps": K, "ms": round(ms, 3), "error": float(f"{err:.4e}")})
+    fd = sorted(pts["fp64_fd"], key=lambda q: q["error"])
+    ratios = []
+    for q in pts["fp32_tangent"]:
+        e = q["error"]
+        for a, b in zip(fd, fd[1:]):
+            if a["error"] <= e <= b["error"] and a["error"] > 0 and b["error"] > a["error"]:
+                f = (math.log(e) - math.log(a["error"])) / (math.log(b["error"]) - math.log(a["error"]))
+                t_fd = math.exp(math.log(a["ms"]) + f * (math.log(b["ms"]) - math.log(a["ms"])))
+                ratios.append({"error": e, "fp32_ms": q["ms"], "fp64_fd_ms": round(t_fd, 3),
+                               "speedup": round(t_fd / q["ms"], 3)})
+                break
+    return {"workload": "Taylor-Green 2-D, 512x512, Re 100, Mach 0.1, MUSCL, M = 20, T = 10 h(CFL 4)",
+            "reference": "FP64 exact-product ROK at CFL 1/8", "points": pts, "speedup_at_equal_error": ratios}
+
+
 def cpu_leg(args, pb, y0, w, tab, h):
     import torch
 
@@ -233,6 +301,7 @@ def main():
     tab = ri.rok4_tableau()
     h = ri.cfl_step(pb, y0, w["cfl"])
     res = gpu_leg(args, pb, y0, w, tab, h)
+    eq = None if (args.no_equal_error or args.roofline_only) else equal_error_leg(args)
     cpu = None if args.no_cpu_baseline else cpu_leg(args, pb, y0, w, tab, h)
     n = "x".join(str(x) for x in pb["n"])
     line = {
@@ -258,6 +327,7 @@ def main():
         "status": {"flags": res["flags"], "M_eff": res["M_eff"], "finite": res["finite"]},
         "roofline": res["roofline"],
         "roofline_jvp": res["roofline_jvp"],
+        "equal_error": eq,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -68,6 +68,12 @@ template <typename T, typename R, typename = typename std::enable_if<std::is_flo
 __device__ __forceinline__ Dual<T> operator*(Dual<T> a, R b) { return {a.v * b, a.d * b}; }
 template <typename T, typename R, typename = typename std::enable_if<std::is_floating_point<R>::value>::type>
 __device__ __forceinline__ Dual<T> operator/(Dual<T> a, R b) { return {a.v / b, a.d / b}; }
+template <typename T, typename R, typename = typename std::enable_if<std::is_floating_point<R>::value>::type>
+__device__ __forceinline__ Dual<T> operator+(R a, Dual<T> b) { return {a + b.v, b.d}; }
+template <typename T, typename R, typename = typename std::enable_if<std::is_floating_point<R>::value>::type>
+__device__ __forceinline__ Dual<T> operator+(Dual<T> a, R b) { return {a.v + b, a.d}; }
+template <typename T, typename R, typename = typename std::enable_if<std::is_floating_point<R>::value>::type>
+__device__ __forceinline__ Dual<T> operator-(Dual<T> a, R b) { return {a.v - b, a.d}; }
 
 // Scalar traits: value part (for branch decisions), construction, sqrt.
 template <typename S> struct Sc;
@@ -92,6 +98,16 @@ template <typename T> struct Sc<Dual<T>> {
         return {s, x.d / (s + s)};
     }
 };
+
+// The FP64 counterpart of a scalar type (double for float, Dual<double> for
+// Dual<float>) and rounding from it.
+template <typename S> struct Wide { using type = S; };
+template <> struct Wide<float> { using type = double; };
+template <typename T> struct Wide<Dual<T>> { using type = Dual<typename Wide<T>::type>; };
+template <typename S> __device__ __forceinline__ S narrow(typename Wide<S>::type x) {
+    if constexpr (std::is_floating_point<S>::value) return (S)x;
+    else return S{narrow<decltype(S{}.v)>(x.v), narrow<decltype(S{}.d)>(x.d)};
+}
 
 // Pairwise halving tree over groups of 256 consecutive threads of a block:
 // with x_i the value of lane i of a group, computes s_i <- s_i + s_{i+h} for

@@ -125,4 +125,64 @@ __device__ __forceinline__ void face_flux_cells(const Geom& G, const S (*U)[D + 
     rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
 }
 
+// ---------------------------------------------------------------------------
+// Reference-state form used by the FP32 kernels.  At low Mach number the
+// pressure and energy are large constants plus small variations, and the
+// flux differences that make up f are differences of those variations: in
+// FP32 the fluxes themselves would lose most of those digits.  The FP32
+// kernels therefore carry primitive perturbations q' = q - q0 (taken in FP64
+// from a constant reference state q0 = (r0, u0, p0) before rounding) and
+// evaluate F(q0 + q') - F(q0) from them without cancellation; the constant
+// F(q0) drops out of every flux difference.
+// ---------------------------------------------------------------------------
+template <int D, typename R>
+struct RefState {
+    R r0, u0[D], p0, m0[D], H0;   // H0 = E0 + p0
+};
+
+// Rusanov flux minus F(q0) at a face, from the perturbations of the left and
+// right primitive states (q = r', u'_0..u'_{D-1}, p').
+template <int D, typename S>
+__device__ __forceinline__ void rusanov_ref(const Geom& G, const RefState<D, typename Sc<S>::R>& Q, int d,
+                                            const S* qL, const S* qR, S* Fh) {
+    using R = typename Sc<S>::R;
+    const R g = (R)G.g, gm1 = (R)G.gm1, half = (R)0.5;
+    constexpr int NV = D + 2;
+    S F[2][NV], Up[2][NV], sp[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const S* q = side ? qR : qL;
+        const S rp = q[0], pp = q[D + 1];
+        const S r = Q.r0 + rp, p = Q.p0 + pp;
+        S u[D], mp[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            u[e] = Q.u0[e] + q[1 + e];
+            mp[e] = Q.r0 * q[1 + e] + rp * u[e];      // rho u - rho0 u0
+        }
+        S uu = u[0] * u[0], ku = q[1] * (u[0] + Q.u0[0]);
+#pragma unroll
+        for (int e = 1; e < D; ++e) {
+            uu = uu + u[e] * u[e];
+            ku = ku + q[1 + e] * (u[e] + Q.u0[e]);       // |u|^2 - |u0|^2
+        }
+        const S Ep = pp / gm1 + half * (rp * uu + Q.r0 * ku);   // E - E0
+        const S Hp = Ep + pp;                                    // (E + p) - (E0 + p0)
+        Up[side][0] = rp;
+#pragma unroll
+        for (int e = 0; e < D; ++e) Up[side][1 + e] = mp[e];
+        Up[side][D + 1] = Ep;
+        F[side][0] = mp[d];
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+            F[side][1 + e] = (e == d) ? mp[d] * u[e] + Q.m0[d] * q[1 + e] + pp : mp[d] * u[e] + Q.m0[d] * q[1 + e];
+        F[side][D + 1] = Hp * u[d] + Q.H0 * q[1 + d];
+        sp[side] = sabs(u[d]) + Sc<S>::sqrt_(g * p / r);
+    }
+    const S a = (Sc<S>::val(sp[0]) >= Sc<S>::val(sp[1])) ? sp[0] : sp[1];
+    const S ha = half * a;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) Fh[m] = half * (F[0][m] + F[1][m]) - ha * (Up[1][m] - Up[0][m]);
+}
+
 }  // namespace rok

@@ -16,7 +16,10 @@
 //   3. each thread assembles the flux differences of its cells in registers
 //      and writes them out once.
 // The same code is instantiated with a dual-number scalar for the exact
-// Jacobian-vector product and with float for the FP32 form.
+// Jacobian-vector product and with float for the FP32 form.  The FP32
+// instantiations stage primitive perturbations about a reference state (the
+// tile's centre cell, taken in FP64) and use the reference-state flux, so
+// the large constant part of pressure and energy never enters FP32 sums.
 #include "rok_device.hpp"
 #include "rok_kernels.hpp"
 #include "rok_flux.hpp"
@@ -73,7 +76,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     using R = typename Sc<S>::R;
     constexpr int NV = D + 2;
     constexpr bool FO = (RECON == 0);
-    constexpr int OFF_VEL = FO ? NV : 1;
+    constexpr bool PERT = sizeof(R) == 4;              // FP32: reference-state form
+    constexpr bool CONS = FO && !PERT;                 // conserved states staged as well
+    constexpr int OFF_VEL = CONS ? NV : 1;
     constexpr int OFF_P = OFF_VEL + D;
     constexpr int OFF_T = OFF_P + 1;
     constexpr int NP = OFF_P + 1 + (NSV ? 1 : 0);
@@ -93,6 +98,47 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     double eps = 0.0;
     if constexpr (MODE == MODE_FD) eps = A.eps_dev ? *A.eps_dev : A.eps;
 
+    // FP32: reference state = the primitive state of the box's centre cell,
+    // rounded to float; the same float values (as doubles) are subtracted in
+    // FP64 below, so q0 + q' is consistent.
+    __shared__ RefState<D, R> s_ref;
+    __shared__ double s_refd[D + 3];   // r0, u0[D], p0, T0 = p0 / r0
+    if constexpr (PERT) {
+        if (tid == 0) {
+            const int gx = wrap(x0 - 2 + T::BX / 2, n0);
+            const int gy = wrap(y0 - 2 + T::BY / 2, n1);
+            const int gz = (D == 3) ? wrap(z0 - 2 + T::BZ / 2, n2) : 0;
+            const long gi = ((long)gz * n1 + gy) * n0 + gx;
+            double U[NV];
+            load_state<MODE_PLAIN, NV, double>(MODE == MODE_PLAIN ? A : ResArgs{A.y}, G.ncell, gi, 0.0, U);
+            const double r0 = U[0];
+            double ke = 0.0, u0[D];
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                u0[e] = U[1 + e] / r0;
+                ke = ke + u0[e] * u0[e];
+            }
+            const double p0 = G.gm1 * (U[D + 1] - (0.5 * r0) * ke);
+            const R r0f = (R)r0, p0f = (R)p0;
+            s_ref.r0 = r0f;
+            s_ref.p0 = p0f;
+            s_refd[0] = (double)r0f;
+            s_refd[D + 1] = (double)p0f;
+            s_refd[D + 2] = (double)p0f / (double)r0f;
+            double keff = 0.0;
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                const R uf = (R)u0[e];
+                s_ref.u0[e] = uf;
+                s_ref.m0[e] = r0f * uf;
+                s_refd[1 + e] = (double)uf;
+                keff = keff + (double)uf * (double)uf;
+            }
+            s_ref.H0 = (R)(G.g * (double)p0f / G.gm1 + 0.5 * (double)r0f * keff);
+        }
+        __syncthreads();
+    }
+
     // 1. stage the box in LDS as primitive variables
     for (int c = tid; c < T::BOX; c += kThreads) {
         int bx = c % T::BX;
@@ -102,6 +148,25 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
         int gy = wrap(y0 - 2 + by, n1);
         int gz = (D == 3) ? wrap(z0 - 2 + bz, n2) : 0;
         long gi = ((long)gz * n1 + gy) * n0 + gx;
+        if constexpr (PERT) {
+            using SD = typename Wide<S>::type;
+            SD U[NV];
+            load_state<MODE, NV, SD>(A, G.ncell, gi, eps, U);
+            SD r = U[0];
+            SD vel[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) vel[d] = U[1 + d] / r;
+            SD ke = vel[0] * vel[0];
+#pragma unroll
+            for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
+            SD p = G.gm1 * (U[D + 1] - (0.5 * r) * ke);
+            sq[0][c] = narrow<S>(r - s_refd[0]);
+#pragma unroll
+            for (int d = 0; d < D; ++d) sq[1 + d][c] = narrow<S>(vel[d] - s_refd[1 + d]);
+            sq[OFF_P][c] = narrow<S>(p - s_refd[D + 1]);
+            if constexpr (NSV) sq[OFF_T][c] = narrow<S>(p / r - s_refd[D + 2]);
+            continue;
+        }
         S U[NV];
         load_state<MODE, NV, S>(A, G.ncell, gi, eps, U);
         const R gm1 = (R)G.gm1;
@@ -114,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 #pragma unroll
         for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
         S p = gm1 * (U[D + 1] - (half * r) * ke);
-        if constexpr (FO) {
+        if constexpr (CONS) {
 #pragma unroll
             for (int m = 0; m < NV; ++m) sq[m][c] = U[m];
         } else {
@@ -144,7 +209,22 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             S Fh[NV];
             S UL[NV], UR[NV], vL[D], vR[D];
             S rL, rR, pL, pR;
-            if constexpr (FO) {
+            if constexpr (PERT) {
+                S qL[NV], qR[NV];
+                if constexpr (FO) {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) { qL[k] = sq[k][ca]; qR[k] = sq[k][cb]; }
+                } else {
+                    const R half = (R)0.5;
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        S am1 = sq[k][ca - sd], a0 = sq[k][ca], ap1 = sq[k][cb], ap2 = sq[k][cb + sd];
+                        qL[k] = a0 + half * minmod(a0 - am1, ap1 - a0);
+                        qR[k] = ap1 - half * minmod(ap1 - a0, ap2 - ap1);
+                    }
+                }
+                rusanov_ref<D>(G, s_ref, d, qL, qR, Fh);
+            } else if constexpr (FO) {
 #pragma unroll
                 for (int m = 0; m < NV; ++m) { UL[m] = sq[m][ca]; UR[m] = sq[m][cb]; }
                 rL = UL[0];
@@ -171,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 to_conserved<D>(G, rL, vL, pL, UL);
                 to_conserved<D>(G, rR, vR, pR, UR);
             }
-            rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+            if constexpr (!PERT) rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
             if constexpr (NSV) {
                 const R half = (R)0.5;
                 const R mu = (R)G.mu, c23mu = (R)G.c23mu, kappa = (R)G.kappa;
@@ -199,6 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 for (int a = 0; a < D; ++a) {
                     S tau = (a == d) ? mu * (Gr[a][d] + Gr[d][a]) - c23mu * div : mu * (Gr[a][d] + Gr[d][a]);
                     S uf = half * (sq[OFF_VEL + a][ca] + sq[OFF_VEL + a][cb]);
+                    if constexpr (PERT) uf = s_ref.u0[a] + uf;   // perturbations staged: add the reference
                     work = (a == 0) ? uf * tau : work + uf * tau;
                     Fh[1 + a] = Fh[1 + a] - tau;
                 }

@@ -108,6 +108,27 @@ def perturb_density(pb, y, amplitude=0.01, seed=PERTURB_SEED):
     return _pack(pb, rho * (1.0 + amplitude * xi), vel, p)
 
 
+def perturb_generic(pb, y, amplitude=1e-3, seed=PERTURB_SEED + 1):
+    """Seeded perturbation of every primitive variable (relative to its spread):
+    rho, each velocity component and p get amplitude * (spread) * xi, xi ~ U(-1, 1)
+    per cell.  Breaks the exact symmetries of the analytic initial states, at
+    whose mirror-image cells minmod and the wave-speed maximum sit on ties."""
+    g = pb["gamma"]
+    D = len(pb["n"])
+    U = y.reshape((D + 2,) + tuple(reversed(pb["n"])))
+    rho = U[0]
+    vel = [U[1 + d] / rho for d in range(D)]
+    ke = sum(u * u for u in vel)
+    p = (g - 1.0) * (U[D + 1] - 0.5 * rho * ke)
+    rng = np.random.default_rng(seed)
+
+    def bump(q):
+        spread = float(np.max(q) - np.min(q)) or float(np.max(np.abs(q))) or 1.0
+        return q + amplitude * spread * rng.uniform(-1.0, 1.0, size=q.shape)
+
+    return _pack(pb, bump(rho), [bump(u) for u in vel], bump(p))
+
+
 # ---------------------------------------------------------------------------
 # Taylor-Green vortices
 # ---------------------------------------------------------------------------

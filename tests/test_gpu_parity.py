@@ -4,8 +4,9 @@ Tolerances (normwise relative, ||gpu - oracle|| / ||oracle||):
 * FP64 residual and FD product with a given eps: bitwise (same operation
   order, no contraction, correctly rounded / and sqrt on both sides);
 * FP64 exact (tangent) products, Arnoldi (V, H) and ROK steps: 1e-12;
-* FP32 residual / tangent (precision form): error stated against the FP64
-  oracle, bounded by 1e-5 relative to the size of f's perturbation.
+* FP32 residual / tangent (precision form, reference-state form): error
+  stated against the FP64 oracle, bounded by 2e-6 on smooth states
+  (measured <= 4e-7).
 """
 import math
 import sys
@@ -137,7 +138,7 @@ def test_fp32_residual_and_tangent_error_vs_fp64_oracle(dev, name):
     wr = fv.jvp_exact(P, y, v)
     eF, ew = relerr(F, Fr), relerr(w, wr)
     say("fp32 errors", name, eF, ew)
-    assert eF <= 2e-5 and ew <= 2e-5
+    assert eF <= 2e-6 and ew <= 2e-6
 
 
 def _arnoldi_case(mode, M=8, shape=(24, 20), recon="muscl"):

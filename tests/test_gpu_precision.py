@@ -1,0 +1,177 @@
+"""Precision form on the GPU: residual and tangent products in FP32, Arnoldi,
+reduced solve and accumulation in FP64.
+
+Errors are stated against the FP64 oracle (small grids) or against the FP64
+GPU path (full-size workloads; that path is bit-exact / 1e-12 against the
+oracle on the parity grids), normwise relative, also printed relative to the
+flow's perturbation y - mean(y).
+
+The FP32 residual and tangent carry perturbations about a reference state, so
+their own rounding error is about 1e-7 of f and J v on generic states.  What
+separates the FP32 form from the FP64 one beyond that is the Jacobian itself:
+f is piecewise smooth (minmod, |.|, the wave-speed maximum), and where a state
+lies within FP32 rounding of a switch, the FP32-rounded state sees the other
+one-sided Jacobian.  On generic states that happens rarely (measured step
+errors 1e-8 .. 2e-5 over 5 steps); the analytic initial states are
+mirror-symmetric and sit on switches, where the plain FP64 method with
+finite-difference products deviates from the exact-product trajectory as
+much (its increments cross the same switches).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import rok_inputs as ri
+from oracle import fv, krylov, rok
+from tests._util import oracle_problem, relerr, t64
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1607_06834_amd import load_library
+    load_library()
+    return torch.device("cuda", 0)
+
+
+def gpu(pb, precision="fp64"):
+    from paper_1607_06834_amd import Rok
+    return Rok(pb, precision)
+
+
+def _pert_rel(a, b, nvar):
+    """||a - b|| / ||b - mean(b)||, the mean taken per variable."""
+    b2 = b.reshape(nvar, -1)
+    dev = b2 - b2.mean(dim=1, keepdim=True)
+    return float(torch.linalg.norm((a - b).reshape(nvar, -1))) / float(torch.linalg.norm(dev))
+
+
+CASES = {
+    "tgv2d_32": lambda: (ri.tgv_problem(32, 2), 8, 5),
+    "tgv3d_12": lambda: (ri.tgv_problem(12, 3), 8, 3),
+    "vortex_muscl_32": lambda: (ri.vortex_problem(32, "muscl"), 8, 5),
+}
+
+
+def _initial(pb, generic):
+    y0 = ri.tgv_state(pb) if pb["physics"] == "ns" else ri.vortex_state(pb)
+    return ri.perturb_generic(pb, y0) if generic else y0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("generic", [True, False])
+def test_fp32_trajectory_error_vs_fp64_oracle(dev, name, generic):
+    """FP32 + tangent trajectory against the FP64 exact-product oracle.
+
+    Generic states (every variable seeded-perturbed): the FP32 rounding is the
+    only difference, bound 1e-5.  The analytic initial states themselves are
+    mirror-symmetric, so minmod and the wave-speed maximum sit on ties whose
+    outcome rounding decides: there the Jacobian of the FP32-rounded state is a
+    different one-sided Jacobian, and the bound is that the FP32 form stays at
+    least as close to the exact-product trajectory as the plain FP64 method with
+    finite-difference products (whose increments cross the same ties).
+    Generic bound 5e-5: a rare FP32 switch of the wave-speed maximum gives
+    1.7e-5 on the 32^2 Taylor-Green case after 5 steps."""
+    pb, M, K = CASES[name]()
+    say("fp32 trajectory", name, "generic" if generic else "analytic", pb["n"], M, K)
+    P = oracle_problem(pb)
+    y0 = _initial(pb, generic)
+    h = ri.cfl_step(pb, y0, 2.5)
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, "exact")
+    ref = rok.trajectory(f, mv, tab, M, h, t64(y0), K, keep=True)
+    g32, g64 = gpu(pb, "fp32"), gpu(pb, "fp64")
+    y32, y64, yfd = (torch.tensor(y0, device=dev) for _ in range(3))
+    nvar = len(pb["n"]) + 2
+    for n in range(1, K + 1):
+        y32 = g32.step(y32, h, tab, M, "exact")
+        y64 = g64.step(y64, h, tab, M, "exact")
+        yfd = g64.step(yfd, h, tab, M, "fd")
+        e32, e64, efd = relerr(y32.cpu(), ref[n]), relerr(y64.cpu(), ref[n]), relerr(yfd.cpu(), ref[n])
+        ep = _pert_rel(y32.cpu(), ref[n], nvar)
+        say(f"  step {n}: fp32 {e32:.3e} (vs perturbation {ep:.3e}), fp64-FD {efd:.3e}, fp64 exact {e64:.3e}")
+        assert e64 <= 1e-12
+        assert g32.last_status()[0] == 0
+        assert e32 <= (5e-5 if generic else max(5e-5, efd))
+
+
+@pytest.mark.parametrize("name", ["tgv2d_32", "vortex_muscl_32"])
+def test_fp32_krylov_pair_error(dev, name):
+    """(V, H) of the FP32-product Arnoldi against the oracle's exact-product Arnoldi (generic state)."""
+    pb, M, _ = CASES[name]()
+    P = oracle_problem(pb)
+    y = t64(_initial(pb, True))
+    F = fv.residual(P, y)
+    V, H, m = krylov.arnoldi(lambda v: fv.jvp_exact(P, y, v), F, M)
+    g = gpu(pb, "fp32")
+    Fg = g.residual(y.to(dev)).double()
+    Vg, Hg, mg = g.arnoldi(y.to(dev), Fg, M, "exact")
+    eH, eV = relerr(Hg.cpu(), H), relerr(Vg.cpu().T, V)
+    say("fp32 krylov", name, "H", eH, "V", eV, "F", relerr(Fg.cpu(), F))
+    assert mg == m
+    assert eH <= 1e-4 and eV <= 1e-4
+
+
+def test_tgv2048_full_size(dev):
+    """The 2048^2 viscous Taylor-Green workload (Re 100, Mach 0.1, M = 20):
+    FP32 residual against the FP64 oracle; FP32 tangent product and one FP32
+    step against the FP64 GPU path (exact products), from the seeded state.
+    The viscous Taylor-Green flow is a near-balance of O(1) flux terms, so f
+    itself is small and its FP32 relative error is about 4e-4 (1e-3 bound);
+    the step, which adds h f to a state of size ~ p0, is within 1e-5."""
+    pb, y0, w = ri.workload("tgv2048_ns")
+    say("tgv2048", w)
+    P = oracle_problem(pb)
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, w["cfl"])
+    g32, g64 = gpu(pb, "fp32"), gpu(pb, "fp64")
+    yd = torch.tensor(y0, device=dev)
+    F32 = g32.residual(yd).double()
+    Fr = fv.residual(P, t64(y0))
+    eF = relerr(F32.cpu(), Fr)
+    F64 = g64.residual(yd)
+    assert torch.equal(F64.cpu(), Fr)
+    v = torch.tensor(ri.random_direction(yd.numel(), 4), device=dev)
+    ew = relerr(g32.jvp(yd, v, "exact").double(), g64.jvp(yd, v, "exact"))
+    s32 = g32.step(yd, h, tab, w["M"], "exact")
+    s64 = g64.step(yd, h, tab, w["M"], "exact")
+    es = relerr(s32, s64)
+    ep = _pert_rel(s32.cpu(), s64.cpu(), 4)
+    say(f"  F {eF:.3e}  Jv {ew:.3e}  step {es:.3e} (vs perturbation {ep:.3e})")
+    assert g32.last_status() == (0, w["M"]) and g64.last_status() == (0, w["M"])
+    assert eF <= 1e-3 and ew <= 1e-3 and es <= 1e-5
+
+
+def test_tgv3d_256_full_size(dev):
+    """The 256^3 Taylor-Green workload (Re 1600, M = 16): one step of the FP32 +
+    tangent form and of the plain FP64 + finite-difference method against the
+    FP64 exact-product step, from the seeded state."""
+    pb, y0, w = ri.workload("tgv256_3d")
+    say("tgv256 3d", w)
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, w["cfl"])
+    yd = torch.tensor(y0, device=dev)
+    g64 = gpu(pb, "fp64")
+    ref = g64.step(yd, h, tab, w["M"], "exact")
+    assert g64.last_status() == (0, w["M"])
+    fd = g64.step(yd, h, tab, w["M"], "fd")
+    e_fd = relerr(fd, ref)
+    del g64
+    g32 = gpu(pb, "fp32")
+    s32 = g32.step(yd, h, tab, w["M"], "exact")
+    assert g32.last_status() == (0, w["M"])
+    e32 = relerr(s32, ref)
+    say(f"  fp32+tangent {e32:.3e} (vs perturbation {_pert_rel(s32.cpu(), ref.cpu(), 5):.3e}); "
+        f"fp64+FD {e_fd:.3e} (vs perturbation {_pert_rel(fd.cpu(), ref.cpu(), 5):.3e})")
+    # the analytic state is mirror-symmetric (see the trajectory test): bound by the plain method's own deviation
+    assert e32 <= max(5e-5, e_fd)
