@@ -39,49 +39,43 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 // the last arrival of a group bumps the top counter, the last arrival at the
 // top bumps the generation everyone waits on.  Counters sit on separate
 // 128-byte lines.  bar (unsigned): [g * 32] group g arrivals, [kBarTop] top
-// arrivals, [kBarGen] generation, [kBarErr] error.  Returns true (in every
-// thread of the block) if the barrier failed.
+// arrivals, [kBarGen] generation, [kBarErr] error.  Run by thread 0 only;
+// returns true if the barrier failed (spin limit).
 constexpr int kBarGroups = 16;
 constexpr int kBarTop = kBarGroups * 32;
 constexpr int kBarGen = kBarTop + 32;
 constexpr int kBarErr = kBarGen + 32;
 
-__device__ __forceinline__ bool grid_sync(unsigned* bar) {
-    __shared__ unsigned s_err;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned per_group = gridDim.x / kBarGroups;
-        const unsigned grp = blockIdx.x / per_group;
+__device__ __forceinline__ bool grid_arrive_wait(unsigned* bar) {
+    const unsigned per_group = gridDim.x / kBarGroups;
+    const unsigned grp = blockIdx.x / per_group;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    unsigned g = __hip_atomic_load(bar + kBarGen, __ATOMIC_RELAXED, AGENT);
+    unsigned a = __hip_atomic_fetch_add(bar + grp * 32, 1u, __ATOMIC_RELAXED, AGENT);
+    bool released = false;
+    if (a == per_group - 1) {
+        __hip_atomic_store(bar + grp * 32, 0u, __ATOMIC_RELAXED, AGENT);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        unsigned g = __hip_atomic_load(bar + kBarGen, __ATOMIC_RELAXED, AGENT);
-        unsigned a = __hip_atomic_fetch_add(bar + grp * 32, 1u, __ATOMIC_RELAXED, AGENT);
-        bool released = false;
-        if (a == per_group - 1) {
-            __hip_atomic_store(bar + grp * 32, 0u, __ATOMIC_RELAXED, AGENT);
+        unsigned t = __hip_atomic_fetch_add(bar + kBarTop, 1u, __ATOMIC_RELAXED, AGENT);
+        if (t == kBarGroups - 1) {
+            __hip_atomic_store(bar + kBarTop, 0u, __ATOMIC_RELAXED, AGENT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            unsigned t = __hip_atomic_fetch_add(bar + kBarTop, 1u, __ATOMIC_RELAXED, AGENT);
-            if (t == kBarGroups - 1) {
-                __hip_atomic_store(bar + kBarTop, 0u, __ATOMIC_RELAXED, AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __hip_atomic_fetch_add(bar + kBarGen, 1u, __ATOMIC_RELAXED, AGENT);
-                released = true;
-            }
+            __hip_atomic_fetch_add(bar + kBarGen, 1u, __ATOMIC_RELAXED, AGENT);
+            released = true;
         }
-        if (!released) {
-            long spins = 0;
-            while (__hip_atomic_load(bar + kBarGen, __ATOMIC_RELAXED, AGENT) == g) {
-                if (++spins > kSpinLimit) {
-                    __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        s_err = __hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, AGENT);
     }
-    __syncthreads();
-    return s_err != 0;
+    if (!released) {
+        long spins = 0;
+        while (__hip_atomic_load(bar + kBarGen, __ATOMIC_RELAXED, AGENT) == g) {
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return __hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, AGENT) != 0;
 }
 
 // Canonical sum of the lane values `acc` over the grid, in two halves so the
@@ -101,23 +95,46 @@ __device__ __forceinline__ void publish(double acc, double* part, int phase, dou
     }
 }
 
+// Wave 0 runs the barrier and then finishes the sum alone: lane l holds the
+// canonical lanes t = l + 64 m (m = 0..3), each the in-order sum of partials
+// t, t + 256, t + 512, t + 768; the first two levels of the halving tree
+// (t += t + 128, then t += t + 64) are additions within the lane and the last
+// six are shuffles, the same operations in the same order as the block tree.
+// Returns false (in every thread of the block) if the barrier failed.
 __device__ __forceinline__ bool collect(const double* part, int phase, unsigned* bar, double* s, double* out) {
     const int tid = threadIdx.x;
-    if (grid_sync(bar)) return false;
-    // all kRedBlocks partials fetched in parallel (one per thread), then lane t
-    // adds partials t, t+256, t+512, t+768 in order and the halving tree finishes
-    static_assert(kPT == kRedBlocks, "one partial per thread");
-    double pv = __hip_atomic_load(part + phase * kRedBlocks + tid, __ATOMIC_RELAXED, AGENT);
-    s[tid] = pv;
-    __syncthreads();
-    double a = 0.0;
-    if (tid < kRedThreads)
-        for (int b = tid; b < kRedBlocks; b += kRedThreads) a = a + s[b];
-    __syncthreads();
-    double r = tree256(a, s);
     __shared__ double s_out;
-    if (tid == 0) s_out = r;
+    __shared__ int s_err;
+    static_assert(kPT == kRedBlocks && kRedThreads == 256, "one partial per thread, 256-lane groups");
     __syncthreads();
+    if (tid < 64) {
+        int err = 0;
+        if (tid == 0) err = grid_arrive_wait(bar) ? 1 : 0;
+        err = __shfl(err, 0, 64);
+        if (tid == 0) s_err = err;
+        if (!err) {
+            const double* p = part + phase * kRedBlocks;
+            double pv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) pv[q] = __hip_atomic_load(p + tid + 64 * q, __ATOMIC_RELAXED, AGENT);
+            double a[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                double x = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x = x + pv[m + 4 * r];
+                a[m] = x;
+            }
+            a[0] = a[0] + a[2];
+            a[1] = a[1] + a[3];
+            double v = a[0] + a[1];
+#pragma unroll
+            for (int h = 32; h > 0; h >>= 1) v = v + __shfl_down(v, h, 64);
+            if (tid == 0) s_out = v;
+        }
+    }
+    __syncthreads();
+    if (s_err) return false;
     *out = s_out;
     return true;
 }
