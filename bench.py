@@ -47,6 +47,9 @@ def parse():
                     help="run only the roofline kernel loop and a calibration copy (for counter runs)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_vortex1024_muscl.json"),
                     help="JSON file with HBM bytes per launch of the roofline kernels (from counter runs)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the discrete adjoint of the step (rok_step_vjp; on by default for the "
+                         "differentiation workload)")
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the FP32-tangent vs FP64-FD equal-error sweep")
     ap.add_argument("--chain", action="store_true",
@@ -109,8 +112,42 @@ def gpu_leg(args, pb, y0, w, tab, h):
     torch.cuda.synchronize()
     mgs = _mgs_roofline(args, g, ya, M, mode, stream)
     jvp = _jvp_roofline(args, g, ya, w, stream)
+    adj = None
+    if (args.adjoint or args.workload == "vortex512_adjoint") and not args.roofline_only:
+        adj = _adjoint_leg(args, g, ya, h, tab, M, stream)
     return {"ms_per_step": ev_ms / max(steps, 1), "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite,
-            "roofline": mgs, "roofline_jvp": jvp}
+            "roofline": mgs, "roofline_jvp": jvp, "adjoint": adj}
+
+
+def _adjoint_leg(args, g, y, h, tab, M, stream):
+    """Discrete adjoint of one exact-product step (rok_step_vjp: recomputation of
+    the step from y_n plus the reverse sweep), K calls from the seeded state,
+    HIP events; next to the forward exact-product step for comparison."""
+    import torch
+    if g.precision != "fp64":
+        return None
+    yb = torch.ones_like(y) / math.sqrt(y.numel())
+    out = torch.empty_like(y)
+    for _ in range(2):
+        g.step_vjp(y, yb, h, tab, M, out=out)
+        g.step(y, h, tab, M, mode="tangent")
+    torch.cuda.synchronize()
+    K = max(1, args.steps // 2)
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(K):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    fwd = timed(lambda: g.step(y, h, tab, M, mode="tangent"))
+    bwd = timed(lambda: g.step_vjp(y, yb, h, tab, M, out=out))
+    return {"forward_exact_ms_per_step": round(fwd, 4), "step_vjp_ms_per_step": round(bwd, 4),
+            "ratio": round(bwd / fwd, 3), "steps": K}
 
 
 def _timed(stream, launches):
@@ -327,6 +364,7 @@ def main():
         "status": {"flags": res["flags"], "M_eff": res["M_eff"], "finite": res["finite"]},
         "roofline": res["roofline"],
         "roofline_jvp": res["roofline_jvp"],
+        "adjoint": res["adjoint"],
         "equal_error": eq,
         "cpu_baseline": cpu,
     }

@@ -9,10 +9,10 @@
 // cell c collects Fbar^T dFhat/dU_c from every face whose stencil contains c
 // (first order: faces c-1/2, c+1/2; MUSCL: the four faces c-3/2 .. c+3/2).
 // Each thread owns one cell and gathers its own contributions, so the result
-// is deterministic without atomics; dFhat/dU_c is taken by forward-mode dual
-// numbers seeded on one conserved variable of c at a time, on the same flux
-// code as the residual.  With a second dual level (y + t v) the same kernel
-// returns the second-order adjoint in the tangent part.
+// is deterministic without atomics; Fbar^T dFhat/dU_c comes from one reverse
+// sweep of the face flux (face_flux_vjp, the transpose of the tangent of the
+// residual's flux code).  With a dual scalar (y + t v) the same kernel returns
+// the second-order adjoint in the tangent part.
 #include "rok.h"
 #include "rok_device.hpp"
 #include "rok_flux.hpp"
@@ -27,8 +27,7 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
     constexpr int NV = D + 2;
     constexpr int NS = (RECON == 0) ? 2 : 4;   // stencil cells of a face
     constexpr int NF = (RECON == 0) ? 2 : 4;   // faces per direction whose stencil contains a cell
-    using T = typename std::conditional<SECOND, Dual<double>, double>::type;   // base: value (+ t-derivative)
-    using S = Dual<T>;                                                           // + derivative along e_{c,k}
+    using T = typename std::conditional<SECOND, Dual<double>, double>::type;   // value (+ t-derivative)
     const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
     const long ncell = G.ncell;
     const long stride = (long)gridDim.x * blockDim.x;
@@ -39,8 +38,10 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
         T acc[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) acc[k] = Sc<T>::make(0.0);
+#pragma unroll
         for (int d = 0; d < D; ++d) {
             const double inv = G.invdx[d];
+#pragma nounroll
             for (int f = 0; f < NF; ++f) {
                 // face between cells a and a+1 along d; stencil starts at s0
                 const int off_a = (RECON == 0) ? f - 1 : f - 2;      // a - c
@@ -58,10 +59,11 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
                 }
                 const long ca = cell[(RECON == 0) ? 0 : 1];
                 const long cb = cell[(RECON == 0) ? 1 : 2];
-                double fbar[NV];
+                T fbar[NV];
 #pragma unroll
-                for (int m = 0; m < NV; ++m) fbar[m] = (wbar[m * ncell + cb] - wbar[m * ncell + ca]) * inv;
-                T base[NS][NV];
+                for (int m = 0; m < NV; ++m)
+                    fbar[m] = Sc<T>::make((wbar[m * ncell + cb] - wbar[m * ncell + ca]) * inv);
+                T base[NS][NV], ub[NS][NV];
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
 #pragma unroll
@@ -69,19 +71,14 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
                         const long i = m * ncell + cell[q];
                         if constexpr (SECOND) base[q][m] = T{y[i], v[i]};
                         else base[q][m] = y[i];
+                        ub[q][m] = Sc<T>::make(0.0);
                     }
-                for (int k = 0; k < NV; ++k) {
-                    S U[NS][NV];
+                face_flux_vjp<D, RECON, T>(G, base, d, fbar, ub);
 #pragma unroll
-                    for (int q = 0; q < NS; ++q)
+                for (int q = 0; q < NS; ++q)
+                    if (q == kc)
 #pragma unroll
-                        for (int m = 0; m < NV; ++m)
-                            U[q][m] = S{base[q][m], Sc<T>::make((q == kc && m == k) ? 1.0 : 0.0)};
-                    S Fh[NV];
-                    face_flux_cells<D, RECON, S>(G, U, d, Fh);
-#pragma unroll
-                    for (int m = 0; m < NV; ++m) acc[k] = acc[k] + fbar[m] * Fh[m].d;
-                }
+                        for (int k = 0; k < NV; ++k) acc[k] = acc[k] + ub[q][k];
             }
         }
 #pragma unroll

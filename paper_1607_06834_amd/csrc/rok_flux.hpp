@@ -126,6 +126,230 @@ __device__ __forceinline__ void face_flux_cells(const Geom& G, const S (*U)[D + 
 }
 
 // ---------------------------------------------------------------------------
+// Reverse mode of face_flux_cells: given Fbar = dL/dFhat at one face, adds
+// Fbar^T dFhat/dU_q to Ubar[q] for every stencil cell q.  The branches
+// (|.|, the wave-speed maximum, minmod) are those the forward evaluation
+// takes, so this is the transpose of the tangent of face_flux_cells.  T may
+// itself be a dual number, which yields the derivative of the adjoint along
+// the dual direction (the second-order adjoint).
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+__device__ __forceinline__ void prim_rev(const Geom& G, const T* U, T rb, const T* vb_in, T pb, T* Ub) {
+    using R = typename Sc<T>::R;
+    const R gm1 = (R)G.gm1, half = (R)0.5;
+    const T r = U[0];
+    T vel[D], vb[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        vel[e] = U[1 + e] / r;
+        vb[e] = vb_in[e];
+    }
+    T ke = vel[0] * vel[0];
+#pragma unroll
+    for (int e = 1; e < D; ++e) ke = ke + vel[e] * vel[e];
+    // p = gm1 (E - (r/2) ke)
+    Ub[D + 1] = Ub[D + 1] + gm1 * pb;
+    const T tb = -(gm1 * pb);                 // adjoint of t = (r/2) ke
+    rb = rb + half * ke * tb;
+    const T keb = half * r * tb;
+#pragma unroll
+    for (int e = 0; e < D; ++e) vb[e] = vb[e] + (vel[e] + vel[e]) * keb;
+    // vel_e = U[1+e] / r
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        Ub[1 + e] = Ub[1 + e] + vb[e] / r;
+        rb = rb - vb[e] * vel[e] / r;
+    }
+    Ub[0] = Ub[0] + rb;
+}
+
+// Reverse of to_conserved (U = (r, r vel, p/gm1 + (r/2) ke)): adds to rb, vb, pb.
+template <int D, typename T>
+__device__ __forceinline__ void cons_rev(const Geom& G, T r, const T* vel, const T* Ub, T& rb, T* vb, T& pb) {
+    using R = typename Sc<T>::R;
+    const R gm1 = (R)G.gm1, half = (R)0.5;
+    T ke = vel[0] * vel[0];
+#pragma unroll
+    for (int e = 1; e < D; ++e) ke = ke + vel[e] * vel[e];
+    rb = rb + Ub[0] + half * ke * Ub[D + 1];
+    const T keb = half * r * Ub[D + 1];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        rb = rb + Ub[1 + e] * vel[e];
+        vb[e] = vb[e] + Ub[1 + e] * r + (vel[e] + vel[e]) * keb;
+    }
+    pb = pb + Ub[D + 1] / gm1;
+}
+
+// One side of the reverse of rusanov(): the Euler flux of that side carries
+// weight 1/2; when this side's wave speed is the maximum (taken), the
+// adjoint ab of the maximum flows into its |u_d| + sqrt(g p / r).
+template <int D, typename T>
+__device__ __forceinline__ void rusanov_side_rev(const Geom& G, int d, const T* U, T r, const T* v, T p, T c, T x,
+                                                 bool taken, T ab, const T* Fb, T* Ub, T& rb, T* vb, T& pb) {
+    using R = typename Sc<T>::R;
+    const R g = (R)G.g, half = (R)0.5;
+    const T un = v[d];
+    T unb = Sc<T>::make(0.0);
+    Ub[1 + d] = Ub[1 + d] + half * Fb[0];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        const T fb = half * Fb[1 + e];
+        Ub[1 + e] = Ub[1 + e] + fb * un;
+        unb = unb + fb * U[1 + e];
+        if (e == d) pb = pb + fb;
+    }
+    const T fe = half * Fb[D + 1];
+    Ub[D + 1] = Ub[D + 1] + fe * un;
+    pb = pb + fe * un;
+    unb = unb + fe * (U[D + 1] + p);
+    if (taken) {
+        unb = (Sc<T>::val(un) >= 0) ? unb + ab : unb - ab;
+        const T xb = ab / (c + c);
+        pb = pb + g * xb / r;
+        rb = rb - xb * x / r;
+    }
+    vb[d] = vb[d] + unb;
+}
+
+// Reverse of rusanov(): adds to the adjoints of both side states.
+template <int D, typename T>
+__device__ __forceinline__ void rusanov_rev(const Geom& G, int d, const T* UL, T rL, const T* vL, T pL, const T* UR,
+                                            T rR, const T* vR, T pR, const T* Fb, T* ULb, T& rLb, T* vLb, T& pLb,
+                                            T* URb, T& rRb, T* vRb, T& pRb) {
+    using R = typename Sc<T>::R;
+    const R g = (R)G.g, half = (R)0.5;
+    constexpr int NV = D + 2;
+    const T xL = g * pL / rL, xR = g * pR / rR;
+    const T cL = Sc<T>::sqrt_(xL), cR = Sc<T>::sqrt_(xR);
+    const T sL = sabs(vL[d]) + cL, sR = sabs(vR[d]) + cR;
+    const bool takeL = Sc<T>::val(sL) >= Sc<T>::val(sR);
+    const T ha = half * (takeL ? sL : sR);
+    // Fh = half (FL + FR) - ha (UR - UL)
+    T hab = Sc<T>::make(0.0);
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        hab = hab - Fb[m] * (UR[m] - UL[m]);
+        URb[m] = URb[m] - ha * Fb[m];
+        ULb[m] = ULb[m] + ha * Fb[m];
+    }
+    const T ab = half * hab;
+    rusanov_side_rev<D>(G, d, UL, rL, vL, pL, cL, xL, takeL, ab, Fb, ULb, rLb, vLb, pLb);
+    rusanov_side_rev<D>(G, d, UR, rR, vR, pR, cR, xR, !takeL, ab, Fb, URb, rRb, vRb, pRb);
+}
+
+// Ubar[q] += Fbar^T dFhat/dU_q for the stencil cells of one face (conserved
+// states U[q]; first order: 2 cells, MUSCL: 4).
+template <int D, int RECON, typename T>
+__device__ __forceinline__ void face_flux_vjp(const Geom& G, const T (*U)[D + 2], int d, const T* Fb,
+                                              T (*Ub)[D + 2]) {
+    using R = typename Sc<T>::R;
+    constexpr int NV = D + 2;
+    const T zero = Sc<T>::make(0.0);
+    T ULb[NV], URb[NV], vLb[D], vRb[D], rLb = zero, rRb = zero, pLb = zero, pRb = zero;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) ULb[m] = URb[m] = zero;
+#pragma unroll
+    for (int e = 0; e < D; ++e) vLb[e] = vRb[e] = zero;
+    if constexpr (RECON == 0) {
+        T rL, rR, pL, pR, vL[D], vR[D];
+        primitives<D>(G, U[0], rL, vL, pL);
+        primitives<D>(G, U[1], rR, vR, pR);
+        rusanov_rev<D>(G, d, U[0], rL, vL, pL, U[1], rR, vR, pR, Fb, ULb, rLb, vLb, pLb, URb, rRb, vRb, pRb);
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            Ub[0][m] = Ub[0][m] + ULb[m];
+            Ub[1][m] = Ub[1][m] + URb[m];
+        }
+        prim_rev<D>(G, U[0], rLb, vLb, pLb, Ub[0]);
+        prim_rev<D>(G, U[1], rRb, vRb, pRb, Ub[1]);
+    } else {
+        const R half = (R)0.5;
+        T q[4][NV];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            T rr, vv[D], pp;
+            primitives<D>(G, U[k], rr, vv, pp);
+            q[k][0] = rr;
+#pragma unroll
+            for (int e = 0; e < D; ++e) q[k][1 + e] = vv[e];
+            q[k][D + 1] = pp;
+        }
+        // reconstruction, remembering the minmod branch: 0 -> zero, 1 -> first slope, 2 -> second
+        T qL[NV], qR[NV];
+        int brL[NV], brR[NV];
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            const T am1 = q[0][m], a0 = q[1][m], ap1 = q[2][m], ap2 = q[3][m];
+            const T x1 = a0 - am1, y1 = ap1 - a0, x2 = ap1 - a0, y2 = ap2 - ap1;
+            brL[m] = (Sc<T>::val(x1) * Sc<T>::val(y1) <= (R)0) ? 0
+                     : ((Sc<T>::val(sabs(x1)) <= Sc<T>::val(sabs(y1))) ? 1 : 2);
+            brR[m] = (Sc<T>::val(x2) * Sc<T>::val(y2) <= (R)0) ? 0
+                     : ((Sc<T>::val(sabs(x2)) <= Sc<T>::val(sabs(y2))) ? 1 : 2);
+            qL[m] = a0 + half * minmod(x1, y1);
+            qR[m] = ap1 - half * minmod(x2, y2);
+        }
+        T UL[NV], UR[NV], vL[D], vR[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            vL[e] = qL[1 + e];
+            vR[e] = qR[1 + e];
+        }
+        to_conserved<D>(G, qL[0], vL, qL[D + 1], UL);
+        to_conserved<D>(G, qR[0], vR, qR[D + 1], UR);
+        rusanov_rev<D>(G, d, UL, qL[0], vL, qL[D + 1], UR, qR[0], vR, qR[D + 1], Fb, ULb, rLb, vLb, pLb, URb, rRb,
+                       vRb, pRb);
+        cons_rev<D>(G, qL[0], vL, ULb, rLb, vLb, pLb);
+        cons_rev<D>(G, qR[0], vR, URb, rRb, vRb, pRb);
+        T qLb[NV], qRb[NV];
+        qLb[0] = rLb;
+        qRb[0] = rRb;
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            qLb[1 + e] = vLb[e];
+            qRb[1 + e] = vRb[e];
+        }
+        qLb[D + 1] = pLb;
+        qRb[D + 1] = pRb;
+        T qb[4][NV];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int m = 0; m < NV; ++m) qb[k][m] = zero;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            // qL = a0 + half mm(a0 - am1, ap1 - a0)
+            qb[1][m] = qb[1][m] + qLb[m];
+            const T mL = half * qLb[m];
+            if (brL[m] == 1) {
+                qb[1][m] = qb[1][m] + mL;
+                qb[0][m] = qb[0][m] - mL;
+            } else if (brL[m] == 2) {
+                qb[2][m] = qb[2][m] + mL;
+                qb[1][m] = qb[1][m] - mL;
+            }
+            // qR = ap1 - half mm(ap1 - a0, ap2 - ap1)
+            qb[2][m] = qb[2][m] + qRb[m];
+            const T mR = -(half * qRb[m]);
+            if (brR[m] == 1) {
+                qb[2][m] = qb[2][m] + mR;
+                qb[1][m] = qb[1][m] - mR;
+            } else if (brR[m] == 2) {
+                qb[3][m] = qb[3][m] + mR;
+                qb[2][m] = qb[2][m] - mR;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            T vb[D];
+#pragma unroll
+            for (int e = 0; e < D; ++e) vb[e] = qb[k][1 + e];
+            prim_rev<D>(G, U[k], qb[k][0], vb, qb[k][D + 1], Ub[k]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Reference-state form used by the FP32 kernels.  At low Mach number the
 // pressure and energy are large constants plus small variations, and the
 // flux differences that make up f are differences of those variations: in

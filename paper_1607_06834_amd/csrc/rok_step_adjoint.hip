@@ -102,57 +102,68 @@ struct GRow {
 };
 
 // Reduced-space reverse of stage i on one block; P = V^T kbar_i from the
-// projection partials (column c at part + c kB).
+// projection partials (column c at part + c kB).  H, LU and the lambdas are
+// staged in LDS; the triangular solves run column by column across threads,
+// the rank-one updates of Abar and Hbar entry-parallel.
 __global__ __launch_bounds__(kT) void k_small_rev(const double* part, int M, int i, GRow gr, double h,
                                                  const double* H, const double* LU, const int* perm,
                                                  const double* lam, double* lambar, double* phibar, double* Abar,
                                                  double* Hbar, const int* ints) {
     __shared__ double s[kT];
-    __shared__ double P[kMaxM], r[kMaxM], z[kMaxM], g[kMaxM], Htr[kMaxM];
+    __shared__ double P[kMaxM], r[kMaxM], z[kMaxM], g[kMaxM], Htr[kMaxM], li[kMaxM];
+    __shared__ double sLU[kMaxM * kMaxM], sH[kMaxM * kMaxM];
     const int m = ints[0];
+    const int tid = threadIdx.x;
     for (int c = 0; c < m; ++c) {
         double t = finish(part + (long)c * kB, s);
-        if (threadIdx.x == 0) P[c] = t;
+        if (tid == 0) P[c] = t;
+    }
+    for (int e = tid; e < m * m; e += kT) {
+        const int a = e / m, b = e % m;
+        sLU[a * kMaxM + b] = LU[a * M + b];
+        sH[a * kMaxM + b] = H[a * M + b];
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
     double* lb = lambar + (long)i * M;
-    for (int c = 0; c < m; ++c) lb[c] = lb[c] + P[c];
-    // A = P^T L U (row permutation perm):  A^T r = lb  <=>  U^T z = lb, L^T u = z, r[perm[q]] = u[q]
-    for (int q = 0; q < m; ++q) {
-        double a = lb[q];
-        for (int c = 0; c < q; ++c) a = a - LU[c * M + q] * z[c];
-        z[q] = a / LU[q * M + q];
-    }
-    for (int q = m - 1; q >= 0; --q) {
-        double a = z[q];
-        for (int c = q + 1; c < m; ++c) a = a - LU[c * M + q] * z[c];
-        z[q] = a;
-    }
-    for (int q = 0; q < m; ++q) r[perm[q]] = z[q];
-    for (int c = 0; c < m; ++c) {
+    if (tid < m) {
+        const double v = lb[tid] + P[tid];
+        lb[tid] = v;
+        z[tid] = v;
+        li[tid] = lam[(long)i * M + tid];
         double a = 0.0;
         for (int j = 0; j < i; ++j)
-            if (gr.g[j] != 0.0) a = a + gr.g[j] * lam[j * M + c];
-        g[c] = a;
+            if (gr.g[j] != 0.0) a = a + gr.g[j] * lam[j * M + tid];
+        g[tid] = a;
     }
-    const double* li = lam + (long)i * M;
-    double* pb = phibar + (long)i * M;
-    for (int c = 0; c < m; ++c) pb[c] = -h * P[c] + h * r[c];
-    for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) {
-            Abar[a * M + b] = Abar[a * M + b] - r[a] * li[b];
-            Hbar[a * M + b] = Hbar[a * M + b] + h * r[a] * g[b];
-        }
-    for (int c = 0; c < m; ++c) {   // H^T r
-        double a = 0.0;
-        for (int q = 0; q < m; ++q) a = a + H[q * M + c] * r[q];
-        Htr[c] = a;
+    __syncthreads();
+    // A = P^T L U (row permutation perm):  A^T r = lb  <=>  U^T z = lb, L^T u = z, r[perm[q]] = u[q]
+    for (int q = 0; q < m; ++q) {          // U^T (lower triangular) forward, column-oriented
+        if (tid == 0) z[q] = z[q] / sLU[q * kMaxM + q];
+        __syncthreads();
+        if (tid > q && tid < m) z[tid] = z[tid] - sLU[q * kMaxM + tid] * z[q];
+        __syncthreads();
     }
-    for (int j = 0; j < i; ++j) {
-        if (gr.g[j] == 0.0) continue;
-        for (int c = 0; c < m; ++c) lambar[j * M + c] = lambar[j * M + c] + gr.g[j] * h * Htr[c];
+    for (int q = m - 1; q > 0; --q) {      // L^T (unit upper triangular) backward, column-oriented
+        if (tid < q) z[tid] = z[tid] - sLU[q * kMaxM + tid] * z[q];
+        __syncthreads();
     }
+    if (tid < m) r[perm[tid]] = z[tid];
+    __syncthreads();
+    if (tid < m) {
+        phibar[(long)i * M + tid] = -h * P[tid] + h * r[tid];
+        double a = 0.0;                     // (H^T r)_c
+        for (int q = 0; q < m; ++q) a = a + sH[q * kMaxM + tid] * r[q];
+        Htr[tid] = a;
+    }
+    for (int e = tid; e < m * m; e += kT) {
+        const int a = e / m, b = e % m;
+        Abar[a * M + b] = Abar[a * M + b] - r[a] * li[b];
+        Hbar[a * M + b] = Hbar[a * M + b] + h * r[a] * g[b];
+    }
+    __syncthreads();
+    if (tid < m)
+        for (int j = 0; j < i; ++j)
+            if (gr.g[j] != 0.0) lambar[j * M + tid] = lambar[j * M + tid] + gr.g[j] * h * Htr[tid];
 }
 
 // Vbar[:, c] += (lam_c - h phi_c) kbar + phibar_c F;  Fbar = h kbar + V phibar.
