@@ -80,34 +80,40 @@ __device__ __forceinline__ bool grid_arrive_wait(unsigned* bar) {
 
 // Canonical sum of the lane values `acc` over the grid, in two halves so the
 // caller can issue independent loads in between: publish() combines the
-// block's lanes and stores its partials, collect() waits for every block and
-// finishes the sum (every block obtains the same bits).
+// block's lanes into its four 256-lane group sums (left in LDS), collect()
+// stores them, waits for every block and finishes the sum (every block
+// obtains the same bits).  Only wave 0 touches global memory in collect(),
+// so the other waves may keep loads in flight across it.
 // part: 2 x kRedBlocks doubles, `phase` selects the half.
-__device__ __forceinline__ void publish(double acc, double* part, int phase, double* s) {
+__device__ __forceinline__ void publish(double acc, double* s, double* gs) {
     const int tid = threadIdx.x;
     const double g = tree256(acc, s);
-    if ((tid & (kRedThreads - 1)) == 0) {
-        __hip_atomic_store(part + phase * kRedBlocks + blockIdx.x * (kPT / kRedThreads) + tid / kRedThreads, g,
-                           __ATOMIC_RELAXED, AGENT);
-        // the partial must have reached the coherent level before this block
-        // can arrive at the grid barrier (the arrival is made by another wave)
-        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-    }
+    if ((tid & (kRedThreads - 1)) == 0) gs[tid / kRedThreads] = g;
 }
 
-// Wave 0 runs the barrier and then finishes the sum alone: lane l holds the
-// canonical lanes t = l + 64 m (m = 0..3), each the in-order sum of partials
-// t, t + 256, t + 512, t + 768; the first two levels of the halving tree
-// (t += t + 128, then t += t + 64) are additions within the lane and the last
-// six are shuffles, the same operations in the same order as the block tree.
+// Wave 0 stores the block's four partials, runs the barrier and then
+// finishes the sum alone: lane l holds the canonical lanes t = l + 64 m
+// (m = 0..3), each the in-order sum of partials t, t + 256, t + 512, t + 768;
+// the first two levels of the halving tree (t += t + 128, then t += t + 64)
+// are additions within the lane and the last six are shuffles, the same
+// operations in the same order as the block tree.  after_loads() runs in
+// wave 0 once the partial loads are issued (the caller's prefetch: loads
+// complete in order, so the sum does not wait for them).
 // Returns false (in every thread of the block) if the barrier failed.
-__device__ __forceinline__ bool collect(const double* part, int phase, unsigned* bar, double* s, double* out) {
+template <typename AfterLoads>
+__device__ __forceinline__ bool collect(double* part, int phase, unsigned* bar, const double* gs, double* out,
+                                        AfterLoads after_loads) {
     const int tid = threadIdx.x;
     __shared__ double s_out;
     __shared__ int s_err;
     static_assert(kPT == kRedBlocks && kRedThreads == 256, "one partial per thread, 256-lane groups");
     __syncthreads();
     if (tid < 64) {
+        if (tid < kPT / kRedThreads)
+            __hip_atomic_store(part + phase * kRedBlocks + blockIdx.x * (kPT / kRedThreads) + tid, gs[tid],
+                               __ATOMIC_RELAXED, AGENT);
+        // the partials must have reached the coherent level before the arrival
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         int err = 0;
         if (tid == 0) err = grid_arrive_wait(bar) ? 1 : 0;
         err = __shfl(err, 0, 64);
@@ -117,6 +123,7 @@ __device__ __forceinline__ bool collect(const double* part, int phase, unsigned*
             double pv[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) pv[q] = __hip_atomic_load(p + tid + 64 * q, __ATOMIC_RELAXED, AGENT);
+            after_loads();
             double a[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -139,18 +146,28 @@ __device__ __forceinline__ bool collect(const double* part, int phase, unsigned*
     return true;
 }
 
-// x[k] = src[t + k T] for the nk chunks of lane t that lie below n, +0.0
-// past the end.  Each chunk is addressed from a uniform base (one scalar base
-// per chunk, one offset register for all), so the loads of all chunks are
-// issued back to back.
+// Buffer descriptor word 3 for raw (untyped, unswizzled) loads on gfx9-class
+// devices: data format 32 (a zero format would make every access out of range).
+constexpr int kBufWord3 = 0x00020000;
+
+// x[k] = src[t + k T] for the chunks of lane t that lie below n, +0.0 past
+// the end.  Raw buffer loads with the range n * 8 bytes: an offset past the
+// range reads as zero without touching memory, so the loads need no per-lane
+// condition (no exec-masked branches, whose joins would make the compiler
+// wait for every outstanding load, prefetches included).  All offsets are in
+// the lane's offset register, which is what the range check covers.
 template <int PER>
-__device__ __forceinline__ void load_lane(const double* __restrict__ src, int t, int nk, double (&x)[PER]) {
-    constexpr long T = (long)kPB * kPT;
+__device__ __forceinline__ void load_lane(const double* __restrict__ src, long n, int t, double (&x)[PER]) {
+    constexpr int T = kPB * kPT;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(src), (short)0, (int)(n * 8), kBufWord3);
+    // an opaque base offset: the chunk offsets are formed next to each load
+    // instead of being held in registers across the whole kernel
+    int off = t * 8;
+    asm volatile("" : "+v"(off));
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const double* base = src + k * T;
-        x[k] = (k < nk) ? base[t] : 0.0;
-    }
+    for (int k = 0; k < PER; ++k)
+        x[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off + k * T * 8, 0, 0));
 }
 
 // Work vector storage of one lane: registers, or (PER = 16, where three
@@ -181,11 +198,13 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
     constexpr long T = (long)kPB * kPT;
     const int t = blockIdx.x * kPT + threadIdx.x;
     const int nk = (t < n) ? (int)((n - 1 - t) / T) + 1 : 0;   // chunks of lane t inside the vector
-    // Wave 0 runs the grid barrier, whose atomics return in order behind any
-    // load of its own; the other waves load the next basis vector while the
-    // blocks meet, so a pass costs about max(load, barrier) rather than the
-    // sum.  Two basis-vector arrays alternate: at pass i one holds v_{i-1}
-    // (for the update w -= h v_{i-1}) and v_{i+1} is loaded into it after use.
+    // Wave 0 runs the grid barrier; the other waves issue the loads of the
+    // next basis vector as soon as its register array is free (right after
+    // the pass's update), so they stay in flight across the block tree and
+    // the exchange, and wave 0 issues its own behind the loads of the
+    // partials.  A pass then costs about max(load, tree + exchange).  Two
+    // basis-vector arrays alternate: at pass i one holds v_{i-1} (for the
+    // update w -= h v_{i-1}) and v_{i+1} is loaded into it after use.
     const bool prefetch = threadIdx.x >= 64;
     // Lanes past the end hold +0.0: their products are +0.0 and adding +0.0
     // to a lane sum that starts at +0.0 leaves it unchanged.
@@ -193,20 +212,21 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
     w.l = s_w;
     {
         double x[PER];
-        load_lane<PER>(wsrc, t, nk, x);
+        load_lane<PER>(wsrc, n, t, x);
 #pragma unroll
         for (int k = 0; k < PER; ++k) w.set(k, x[k]);
     }
     double A[PER], B[PER];
-    load_lane<PER>(V, t, nk, A);
+    load_lane<PER>(V, n, t, A);
     __shared__ double s_hcol[kMaxM + 1];
+    __shared__ double s_gs[kPT / kRedThreads];
     int phase = 0;
     double h = 0.0;
     bool failed = false;
+    auto none = [] {};
     // Pass i with cur = v_i and prev = v_{i-1}: w -= h_{i-1} prev (i > 0),
     // h_i = <v_i, w>, then prev <- v_{i+1}.
     auto pass = [&](int i, double (&cur)[PER], double (&prev)[PER]) {
-        if (i > 0 && !prefetch) load_lane<PER>(V + (long)i * n, t, nk, cur);
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
@@ -217,9 +237,17 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
             }
             acc = acc + cur[k] * wk;
         }
-        publish(acc, part, phase, s);
-        if (i < j && prefetch) load_lane<PER>(V + (long)(i + 1) * n, t, nk, prev);
-        if (!collect(part, phase, bar, s, &h)) {
+        // the sum is complete before the loads are issued: otherwise the
+        // products sink past the (conditional) loads and the merge after them
+        // waits for every outstanding load, the prefetch included
+        asm volatile("" : "+v"(acc) : : "memory");
+        const bool more = i < j;
+        if (more && prefetch) load_lane<PER>(V + (long)(i + 1) * n, n, t, prev);
+        publish(acc, s, s_gs);
+        // unconditional (v_j again after the last pass, 64 lanes' worth), so
+        // that the sum's waits count exactly these loads behind the partials
+        auto wave0_prefetch = [&] { load_lane<PER>(V + (long)(more ? i + 1 : j) * n, n, t, prev); };
+        if (!collect(part, phase, bar, s_gs, &h, wave0_prefetch)) {
             failed = true;
             return;
         }
@@ -253,9 +281,9 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
         acc = acc + wk * wk;
     }
     if (j + 1 >= M) return;
-    publish(acc, part, phase, s);
+    publish(acc, s, s_gs);
     double nn;
-    if (!collect(part, phase, bar, s, &nn)) {
+    if (!collect(part, phase, bar, s_gs, &nn, none)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             ints[1] = 1;
             ints[2] |= ROK_FLAG_BARRIER;

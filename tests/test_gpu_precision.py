@@ -175,3 +175,50 @@ def test_tgv3d_256_full_size(dev):
         f"fp64+FD {e_fd:.3e} (vs perturbation {_pert_rel(fd.cpu(), ref.cpu(), 5):.3e})")
     # the analytic state is mirror-symmetric (see the trajectory test): bound by the plain method's own deviation
     assert e32 <= max(5e-5, e_fd)
+
+
+def _ke(pb, y):
+    n = pb["n"]
+    U = y.reshape((len(n) + 2,) + tuple(reversed(n)))
+    dV = 1.0
+    for d in range(len(n)):
+        dV *= (pb["hi"][d] - pb["lo"][d]) / n[d]
+    return float((0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]).sum()) * dV
+
+
+def test_tgv2048_stability_by_cfl(dev):
+    """Stability of the 2048^2 viscous Taylor-Green workload over its 20
+    steps, CFL doubled from 5 (h = CFL / rho_est from the initial state).
+    ROK is only conditionally stable (Table 1): the stated CFL 50 blows up
+    within 4 steps in both precisions, CFL 20 within 20; CFL 5 and 10
+    integrate the 20 steps, the kinetic energy following exp(-4 nu t) and the
+    FP32 form within 1e-5 of the FP64 exact-product trajectory at every step.
+    (The FP64 exact-product GPU path is the oracle's arithmetic to 1e-12 on
+    the parity grids; the oracle itself is too slow for 2048^2 trajectories.)"""
+    import math
+    pb, y0, w = ri.workload("tgv2048_ns")
+    tab = ri.rok4_tableau()
+    yd = torch.tensor(y0, device=dev)
+    ke0, nu = _ke(pb, yd), pb["mu"]
+    g32, g64 = gpu(pb, "fp32"), gpu(pb, "fp64")
+    stable = {}
+    for cfl in (5.0, 10.0, 20.0, 50.0):
+        h = ri.cfl_step(pb, y0, cfl)
+        a, b = yd.clone(), yd.clone()
+        worst, k_fail = 0.0, None
+        for k in range(1, w["steps"] + 1):
+            a = g32.step(a, h, tab, w["M"], "exact")
+            b = g64.step(b, h, tab, w["M"], "exact")
+            fa, fb = g32.last_status()[0], g64.last_status()[0]
+            if fa or fb:
+                k_fail = k
+                break
+            worst = max(worst, relerr(a, b))
+        ratio = _ke(pb, b) / (ke0 * math.exp(-4 * nu * k * h)) if k_fail is None else float("nan")
+        say(f"  CFL {cfl}: h {h:.3e}, " + (f"stable 20 steps, fp32 vs fp64 worst {worst:.2e}, "
+                                            f"KE / (KE0 exp(-4 nu t)) {ratio:.6f}" if k_fail is None
+                                            else f"non-finite / non-physical flag at step {k_fail}"))
+        stable[cfl] = k_fail is None
+        if k_fail is None:
+            assert worst <= 1e-5 and abs(ratio - 1.0) <= 1e-3
+    assert stable == {5.0: True, 10.0: True, 20.0: False, 50.0: False}
