@@ -44,8 +44,10 @@ rok::ResArgs plain_args(const double* y, void* out) {
 
 // w = J(y) v into a double vector (internal use).  FD reads eps from eps_dev.
 hipError_t jvp_into(const rok_ctx* c, const double* y, const double* fy, const double* v, double* w, int mode,
-                    const double* eps_dev, double eps, hipStream_t st) {
+                    const double* eps_dev, double eps, hipStream_t st, const int* gate = nullptr, int gate_col = 0) {
     rok::ResArgs A{};
+    A.gate = gate;
+    A.gate_col = gate_col;
     A.y = y;
     A.v = v;
     A.f0 = fy;
@@ -183,7 +185,9 @@ hipError_t step_adjoint(const rok_ctx* c, const rok_tableau* tab, int M, double 
         if (e != hipSuccess) return e;
         for (int j = M - 1; j >= 0; --j) {
             const double* vj = W.V + (long)j * N;
-            e = jvp_into(c, y_n, nullptr, vj, W.w, ROK_JVP_TANGENT, nullptr, 0.0, st);
+            // J v_j is needed only where the final MGS iterate cannot be taken
+            // as h_{j+1,j} v_{j+1}: the basis' last column
+            e = jvp_into(c, y_n, nullptr, vj, W.w, ROK_JVP_TANGENT, nullptr, 0.0, st, W.ints, j);
             if (e != hipSuccess) return e;
             e = rok::launch_arnoldi_rev_col(W, A, M, j, N, st);
             if (e != hipSuccess) return e;

@@ -43,6 +43,10 @@ struct ResArgs {
     const double* xs[kMaxStages];
     double cs[kMaxStages];
     void* out;
+    // optional: skip the launch unless gate_col + 1 >= *gate (gate: a
+    // device-side basis size, e.g. M_eff of the Arnoldi process)
+    const int* gate;
+    int gate_col;
 };
 
 // ---------------------------------------------------------------------------

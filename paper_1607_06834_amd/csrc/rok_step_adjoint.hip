@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kT) void k_dot(const double* a, const double* b, lo
 }
 
 // Start of the reverse of Arnoldi column j (j < M_eff):
-//   w    = J v_j - sum_{i<=j} h_ij v_i   (the forward's last MGS iterate, in place; w holds J v_j on entry)
+//   w    = the forward's last MGS iterate: h_{j+1,j} v_{j+1} when j + 1 < M_eff (equal to it up to the
+//          rounding of v_{j+1} = w / h_{j+1,j}), else J v_j - sum_{i<=j} h_ij v_i (w holds J v_j on entry)
 //   wbar = adjoint of that iterate: from v_{j+1} = w / h_{j+1,j} when j + 1 < M_eff, else 0
 //   part = partials of <wbar, v_j>
 __global__ __launch_bounds__(kT) void k_col_start(double* w, const double* V, const double* H, int M, int j,
@@ -229,8 +230,13 @@ __global__ __launch_bounds__(kT) void k_col_start(double* w, const double* V, co
     const double* vbn = Vbar + (long)(j + 1) * n;
     double acc = 0.0;
     for (long e = (long)blockIdx.x * kT + threadIdx.x; e < n; e += (long)kB * kT) {
-        double wv = w[e];
-        for (int i = 0; i <= j; ++i) wv = wv - hc[i] * V[(long)i * n + e];
+        double wv;
+        if (nrm) {
+            wv = rho * vn[e];
+        } else {
+            wv = w[e];
+            for (int i = 0; i <= j; ++i) wv = wv - hc[i] * V[(long)i * n + e];
+        }
         w[e] = wv;
         const double wb = nrm ? vbn[e] / rho + coef * vn[e] : 0.0;
         wbar[e] = wb;
