@@ -183,13 +183,14 @@ hipError_t step_adjoint(const rok_ctx* c, const rok_tableau* tab, int M, double 
     if (M > 0) {
         e = rok::launch_abar_to_hbar(W, A, Mm, h * tab->gamma, st);
         if (e != hipSuccess) return e;
+        const bool resident = c->mgs_path != ROK_MGS_PER_PASS && rok::mgs_rev_resident_available(N);
         for (int j = M - 1; j >= 0; --j) {
             const double* vj = W.V + (long)j * N;
             // J v_j is needed only where the final MGS iterate cannot be taken
             // as h_{j+1,j} v_{j+1}: the basis' last column
             e = jvp_into(c, y_n, nullptr, vj, W.w, ROK_JVP_TANGENT, nullptr, 0.0, st, W.ints, j);
             if (e != hipSuccess) return e;
-            e = rok::launch_arnoldi_rev_col(W, A, M, j, N, st);
+            e = rok::launch_arnoldi_rev_col(W, A, M, j, N, resident, st);
             if (e != hipSuccess) return e;
             // w = J(y) v_j:  vbar_j += J^T wbar,  ybar += d/dt [J(y + t v_j)^T wbar]
             e = rok::launch_vjp(c->G, recon, y_n, vj, A.wbar, A.Vbar + (long)j * N, ybar_n, 1, st, W.ints, j);

@@ -99,7 +99,11 @@ hipError_t launch_small_rev(const Work& W, const AdjWork& A, int M, int i, const
 hipError_t launch_vbar_stage(const Work& W, const AdjWork& A, int M, int i, double h, double* Fbar, long n,
                              bool first, hipStream_t st);
 hipError_t launch_abar_to_hbar(const Work& W, const AdjWork& A, int M, double hg, hipStream_t st);
-hipError_t launch_arnoldi_rev_col(const Work& W, const AdjWork& A, int M, int j, long n, hipStream_t st);
+// resident: one cooperative kernel for the column (mgs_rev_resident_available(n)), else per-pass kernels
+hipError_t launch_arnoldi_rev_col(const Work& W, const AdjWork& A, int M, int j, long n, bool resident,
+                                  hipStream_t st);
+bool mgs_rev_resident_available(long n);
+hipError_t launch_mgs_rev_resident(const Work& W, const AdjWork& A, int M, int j, long n, hipStream_t st);
 hipError_t launch_beta_rev(const Work& W, const AdjWork& A, long n, hipStream_t st);
 
 }  // namespace rok

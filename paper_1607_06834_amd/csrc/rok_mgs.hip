@@ -170,6 +170,20 @@ __device__ __forceinline__ void load_lane(const double* __restrict__ src, long n
         x[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off + k * T * 8, 0, 0));
 }
 
+// dst[t + k T] = x[k] for the chunks of lane t below n (raw buffer stores
+// with the range n * 8 bytes: stores past it are dropped).
+template <int PER>
+__device__ __forceinline__ void store_lane(double* __restrict__ dst, long n, int t, const double (&x)[PER]) {
+    constexpr int T = kPB * kPT;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)(n * 8), kBufWord3);
+    using B64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    int off = t * 8;
+    asm volatile("" : "+v"(off));
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, x[k]), r, off + k * T * 8, 0, 0);
+}
+
 // Work vector storage of one lane: registers, or (PER = 16, where three
 // register arrays of 16 doubles would exceed the 128 registers a lane has at
 // 1024 threads per block) the lane's own LDS slots, used as private storage.
@@ -310,6 +324,132 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
         if (k < nk) vnext[t + k * T] = w.get(k) / hn;
 }
 
+// Reverse of one Arnoldi column (the discrete adjoint of its modified
+// Gram-Schmidt passes and of the normalisation v_{j+1} = w / h_{j+1,j}),
+// resident like the forward kernel: w (the forward iterates, rebuilt pass
+// by pass) and wbar stay in registers, so reverse pass i streams only
+// v_{i-1} (for the next dot) and reads and writes vbar_i.  Rules, with x'
+// the result of a forward operation:
+//   v = w / rho, rho = ||w||:  wbar = vbar / rho + (Hbar_rho - <vbar, v> / rho) v
+//   w' = w - h v, h = <v, w>:  hb = Hbar_h - <w'bar, v>, w = w' + h v,
+//                              vbar += hb w - h w'bar, wbar = w'bar + hb v
+// The final forward iterate is h_{j+1,j} v_{j+1} where v_{j+1} exists, else
+// (the basis' last column) J v_j - sum_i h_ij v_i with J v_j read from wsrc.
+// Every dot product is the canonical sum (the same lane order and finish as
+// the per-pass reverse kernels, whose results this reproduces bit for bit).
+// Nothing runs for j >= M_eff or after a failed in-kernel barrier.
+template <int PER>
+__global__ __launch_bounds__(kPT) void k_mgs_rev_resident(const double* wsrc, const double* V, double* Vbar,
+                                                         const double* H, const double* Hbar, long n, int M, int j,
+                                                         double* wbar_out, int* ints, double* part, unsigned* bar) {
+    __shared__ double s[kPT];
+    __shared__ double s_gs[kPT / kRedThreads];
+    __shared__ int s_m, s_bad;
+    __shared__ double s_h[kMaxM + 1], s_hb[kMaxM + 1];   // column j of H and Hbar
+    if (threadIdx.x == 0) {
+        s_m = ints[0];
+        s_bad = (ints[2] & ROK_FLAG_BARRIER) != 0;
+    }
+    if (threadIdx.x < M && threadIdx.x <= j + 1) {
+        s_h[threadIdx.x] = H[threadIdx.x * M + j];
+        s_hb[threadIdx.x] = Hbar[threadIdx.x * M + j];
+    }
+    __syncthreads();
+    const int m = s_m;
+    if (j >= m || s_bad) return;
+    const int t = blockIdx.x * kPT + threadIdx.x;
+    const bool prefetch = threadIdx.x >= 64;
+    const bool nrm = j + 1 < m;
+    double w[PER], wb[PER], A[PER], B[PER], vb[PER];
+    int phase = 0;
+    double d = 0.0;
+    bool failed = false;
+    // canonical sum of the lane values acc; loads(): the caller's prefetch,
+    // issued by waves 1.. before the block tree and by wave 0 behind the partials
+    auto exchange = [&](double acc, auto loads) {
+        asm volatile("" : "+v"(acc) : : "memory");
+        if (prefetch) loads();
+        publish(acc, s, s_gs);
+        if (!collect(part, phase, bar, s_gs, &d, loads)) failed = true;
+        phase ^= 1;
+    };
+    if (nrm) {
+        load_lane<PER>(V + (long)(j + 1) * n, n, t, A);      // v_{j+1}
+        load_lane<PER>(Vbar + (long)(j + 1) * n, n, t, vb);  // vbar_{j+1}
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) acc = acc + vb[k] * A[k];
+        exchange(acc, [&] { load_lane<PER>(V + (long)j * n, n, t, B); });
+        if (failed) goto fail;
+        const double rho = s_h[j + 1];
+        const double coef = s_hb[j + 1] - d / rho;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            w[k] = rho * A[k];
+            wb[k] = vb[k] / rho + coef * A[k];
+        }
+    } else {
+        load_lane<PER>(wsrc, n, t, w);
+        for (int i = 0; i <= j; ++i) {
+            load_lane<PER>(V + (long)i * n, n, t, B);
+            const double hij = s_h[i];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) w[k] = w[k] - hij * B[k];
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) wb[k] = 0.0;
+    }
+    {   // <wbar, v_j>; meanwhile v_{j-1} and vbar_j arrive
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) acc = acc + wb[k] * B[k];
+        exchange(acc, [&] {
+            load_lane<PER>(V + (long)(j > 0 ? j - 1 : 0) * n, n, t, A);
+            load_lane<PER>(Vbar + (long)j * n, n, t, vb);
+        });
+        if (failed) goto fail;
+    }
+    {
+        // reverse pass i with cur = v_i, prev = v_{i-1}, vb = vbar_i, d = <wbar, v_i>
+        auto rpass = [&](int i, double (&cur)[PER], double (&prev)[PER]) {
+            const double h = s_h[i];
+            const double hb = s_hb[i] - d;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const double v = cur[k];
+                const double wo = w[k] + h * v;
+                w[k] = wo;
+                const double b = wb[k];
+                vb[k] = vb[k] + hb * wo - h * b;
+                const double wn = b + hb * v;
+                wb[k] = wn;
+                acc = acc + wn * prev[k];
+            }
+            store_lane<PER>(Vbar + (long)i * n, n, t, vb);
+            if (i == 0) return;
+            exchange(acc, [&] {
+                load_lane<PER>(V + (long)(i > 1 ? i - 2 : 0) * n, n, t, cur);
+                load_lane<PER>(Vbar + (long)(i - 1) * n, n, t, vb);
+            });
+        };
+        int i = j;
+        for (;;) {
+            rpass(i, B, A);
+            if (failed || i == 0) break;
+            --i;
+            rpass(i, A, B);
+            if (failed || i == 0) break;
+            --i;
+        }
+        if (failed) goto fail;
+    }
+    store_lane<PER>(wbar_out, n, t, wb);
+    return;
+fail:
+    if (blockIdx.x == 0 && threadIdx.x == 0) ints[2] |= ROK_FLAG_BARRIER;
+}
+
 template <int PER>
 static hipError_t launch_res(const Work& W, const double* w, const double* V, long n, int M, int j, double* vnext,
                              hipStream_t st) {
@@ -361,6 +501,53 @@ hipError_t launch_mgs_resident(const Work& W, const double* w, const double* V, 
         case 4: return launch_res<4>(W, w, V, n, M, j, vnext, st);
         case 8: return launch_res<8>(W, w, V, n, M, j, vnext, st);
         case 16: return launch_res<16>(W, w, V, n, M, j, vnext, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PER>
+static hipError_t launch_rev(const Work& W, const AdjWork& A, long n, int M, int j, hipStream_t st) {
+    long nn = n;
+    int MM = M, jj = j;
+    const double* wsrc = W.w;
+    const double* V = W.V;
+    double* Vbar = A.Vbar;
+    const double* H = W.H;
+    const double* Hbar = A.Hbar;
+    double* wbar = A.wbar;
+    int* ints = W.ints;
+    double* part = W.gpart;
+    unsigned* bar = W.bar;
+    void* args[] = {(void*)&wsrc, (void*)&V,  (void*)&Vbar, (void*)&H,    (void*)&Hbar, (void*)&nn,
+                    (void*)&MM,   (void*)&jj, (void*)&wbar, (void*)&ints, (void*)&part, (void*)&bar};
+    return hipLaunchCooperativeKernel((const void*)k_mgs_rev_resident<PER>, dim3(kPB), dim3(kPT), args, 0, st);
+}
+
+static int g_rev_ok = -1;
+
+// The resident reverse keeps five lane vectors in registers: up to 8 elements per lane.
+bool mgs_rev_resident_available(long n) {
+    const int per = mgs_resident_per(n);
+    if (per == 0 || per > 8) return false;
+    if (g_rev_ok < 0) {
+        int dev = 0, coop = 0, cus = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_mgs_rev_resident<8>, kPT, 0) != hipSuccess)
+            g_rev_ok = 0;
+        else
+            g_rev_ok = (coop && (long)nb * cus >= kPB) ? 1 : 0;
+    }
+    return g_rev_ok == 1;
+}
+
+hipError_t launch_mgs_rev_resident(const Work& W, const AdjWork& A, int M, int j, long n, hipStream_t st) {
+    switch (mgs_resident_per(n)) {
+        case 1: return launch_rev<1>(W, A, n, M, j, st);
+        case 2: return launch_rev<2>(W, A, n, M, j, st);
+        case 4: return launch_rev<4>(W, A, n, M, j, st);
+        case 8: return launch_rev<8>(W, A, n, M, j, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -404,8 +404,10 @@ hipError_t launch_abar_to_hbar(const Work& W, const AdjWork& A, int M, double hg
 // Partial buffers: projection columns [0, M), then three for the MGS reverse.
 static double* ap(const AdjWork& A, int k) { return A.part + (size_t)(A.M + k) * kB; }
 
-hipError_t launch_arnoldi_rev_col(const Work& W, const AdjWork& A, int M, int j, long n, hipStream_t st) {
-    // W.w holds J v_j on entry.
+hipError_t launch_arnoldi_rev_col(const Work& W, const AdjWork& A, int M, int j, long n, bool resident,
+                                  hipStream_t st) {
+    // W.w holds J v_j on entry (where the column needs it).
+    if (resident) return launch_mgs_rev_resident(W, A, M, j, n, st);
     if (j + 1 < M)
         hipLaunchKernelGGL(k_dot, dim3(kB), dim3(kT), 0, st, A.Vbar + (long)(j + 1) * n, W.V + (long)(j + 1) * n, n,
                            ap(A, 0), W.ints, j + 1);

@@ -268,6 +268,7 @@ class Rok:
         ws = self.workspace(M, tab.s, adjoint=True)
         _check(_lib.rok_step_vjp(self._ctx, ctypes.byref(tab), int(M), float(h), _ptr(y), _ptr(ybar_next), _ptr(yb),
                                  _ptr(y_next_out), _ptr(ws), ws.numel(), _stream()), "rok_step_vjp")
+        self._last_step_ws = ws   # the status header leads the adjoint workspace too
         return yb
 
     def mgs_workspace(self, M: int) -> torch.Tensor:

@@ -205,6 +205,33 @@ def test_step_vjp_after_breakdown(dev):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("kind,n,M", [("fo", (33, 20), 12), ("fo", 300, 16), ("muscl", 400, 16), ("fo", 512, 16),
+                                      ("fo", 700, 16), ("fo", 2, 16)])
+def test_step_vjp_resident_reverse_bitwise(dev, kind, n, M):
+    """The resident reverse of the Arnoldi columns (one cooperative kernel per
+    column, 1..8 elements per lane: N = 2640, 360000, 640000, 1048576,
+    1960000 and the 2 x 2 breakdown case) gives the bits of the per-pass
+    reverse kernels: same operations, same canonical sums."""
+    if n == 2:
+        pb = ri.vortex_problem(2, "first")
+        y0 = ri.smooth_random_state(pb, seed=3)
+    else:
+        pb, y0 = _step_case(kind, n)
+    say("resident reverse", kind, n, M, "N", y0.size)
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, 2.0 if n != 2 else 1.0)
+    yd = torch.tensor(y0, device=dev)
+    cd = torch.tensor(ri.random_direction(y0.size, 5), device=dev)
+    a = gpu(pb, mgs="auto").step_vjp(yd, cd, h, tab, M)
+    Rp = gpu(pb, mgs="pass")
+    b = Rp.step_vjp(yd, cd, h, tab, M)
+    flags, meff = Rp.last_status()
+    say("  M_eff", meff, "flags", flags)
+    assert flags & 8 == 0
+    assert torch.isfinite(a).all()
+    assert torch.equal(a, b)
+
+
 def test_step_vjp_zero_rhs_is_the_explicit_adjoint(dev):
     """f(y) = 0 gives M_eff = 0: the adjoint equals that of the M = 0 (explicit) step, bit for bit."""
     pb = ri.vortex_problem(8, "first")
