@@ -213,6 +213,39 @@ def test_mgs_column_bitwise(dev, mgs, shape):
     assert torch.equal(Hs[:M], Hg)
 
 
+@pytest.mark.parametrize("mgs", MGS)
+@pytest.mark.parametrize("n", [300, 400, 700, 1000, 1024])
+def test_mgs_column_bitwise_large(dev, mgs, n):
+    """One MGS column (j = 4: five passes and the norm) at N = 4 n^2 = 360000 ...
+    4194304, i.e. 2, 4 (ragged), 8 (ragged), 16 (ragged) and 16 (full, the
+    largest the resident kernel takes) elements per lane, against the oracle's
+    canonical dots, bit for bit.  The basis need not be orthonormal for this."""
+    pb = ri.vortex_problem(n, "first")
+    N = ri.size(pb)
+    say("mgs column large", mgs, n, "N", N)
+    M, j = 6, 4
+    rng = np.random.default_rng(n)
+    V = t64(rng.standard_normal((M, N)) / np.sqrt(N))
+    w = t64(rng.standard_normal(N))
+    wr = w.clone()
+    href = []
+    for i in range(j + 1):
+        hij = krylov.dot(V[i], wr)
+        href.append(hij)
+        wr = wr - hij * V[i]
+    hn = float(np.sqrt(krylov.dot(wr, wr)))
+    vref = wr / hn
+    g = gpu(pb, mgs=mgs)
+    Vd = V.to(dev)
+    Hd = torch.zeros(M + 1, M, dtype=torch.float64, device=dev)
+    vn = torch.empty(N, dtype=torch.float64, device=dev)
+    g.mgs_column(Vd, j, w.to(dev), Hd, g.mgs_workspace(M), vnext=vn)
+    Hc = Hd.cpu()
+    assert [float(Hc[i, j]) for i in range(j + 1)] == href
+    assert float(Hc[j + 1, j]) == hn
+    assert torch.equal(vn.cpu(), vref)
+
+
 def test_arnoldi_zero_rhs_and_breakdown(dev):
     say("arnoldi breakdown")
     pb = ri.vortex_problem(8, "muscl")
