@@ -63,13 +63,19 @@ MGS_SOURCES = ("rok_mgs.hip", "rok_kernels.hpp", "rok_device.hpp")
 
 
 def _source_hash(names):
+    """sha256 (16 hex digits) of the kernel sources with comments and white space
+    removed: any change to the code invalidates stored counters, a comment does not."""
     import hashlib
+    import re
     csrc = os.path.join(ROOT, "paper_1607_06834_amd", "csrc")
-    data = b""
+    data = ""
     for name in names:
-        with open(os.path.join(csrc, name), "rb") as fh:
-            data += fh.read()
-    return hashlib.sha256(data).hexdigest()[:16]
+        with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        data += " ".join(text.split()) + "\n"
+    return hashlib.sha256(data.encode()).hexdigest()[:16]
 
 
 def gpu_leg(args, pb, y0, w, tab, h):

@@ -19,6 +19,10 @@
 // the barrier counters, all accessed with agent-scope atomics (coherent
 // across XCDs without an L2 write-back); every spin is bounded and reports a
 // status flag instead of hanging.
+//
+// The same machinery runs the reverse of a column for the discrete adjoint
+// of the step (k_mgs_rev_resident below): the normalisation and the passes
+// in reverse order, with the forward iterate and its adjoint resident.
 #include "rok.h"
 #include "rok_device.hpp"
 #include "rok_kernels.hpp"
