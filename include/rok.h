@@ -143,7 +143,7 @@ rok_status rok_residual(rok_ctx* ctx, const double* y, void* F, void* stream);
  * w = J(y) v, J = df/dy at y (Sec. 2.3).
  *   mode ROK_JVP_FD:      w = (f(y + eps v) - fy) / eps  (eq. 10); fy = f(y)
  *                         (N doubles); eps > 0 is used as given, eps <= 0
- *                         selects eps = sqrt(eps_mach) (1 + ||y||_2) / ||v||_2,
+ *                         selects eps = sqrt((1 + ||y||_2) eps_mach) / ||v||_2,
  *                         which needs `work` (rok_workspace_bytes(ctx, 0, 0)).
  *                         FP64 precision only (ROK_EUNSUPPORTED otherwise).
  *   mode ROK_JVP_TANGENT: the exact product (forward-mode derivative of f);
@@ -158,7 +158,7 @@ rok_status rok_jvp(rok_ctx* ctx, const double* y, const double* fy, const double
  * H = V^T J V (upper Hessenberg).
  *   y, fy:  N doubles (fy = f(y) as a double vector)
  *   M:      1..min(ROK_MAX_M, N) requested dimension
- *   mode:   ROK_JVP_FD (eps <= 0: sqrt(eps_mach) (1 + ||y||), unit vectors)
+ *   mode:   ROK_JVP_FD (eps <= 0: sqrt((1 + ||y||) eps_mach), unit vectors)
  *           or ROK_JVP_TANGENT
  *   V:      N x M doubles, column c at V + c*N (columns >= M_eff untouched)
  *   H:      M x M doubles, row-major, H[i*M + j] = h_ij (zero outside the
@@ -204,7 +204,7 @@ rok_status rok_workspace_init(rok_ctx* ctx, void* work, size_t work_bytes, int M
  * phi_i = V^T F_i, lambda_i = (I - h gamma H)^{-1} (h phi_i + h H sum_j
  * gamma_ij lambda_j), k_i = V lambda_i + h (F_i - V phi_i),
  * y_{n+1} = y_n + sum_i b_i k_i, with (V, H) from rok_arnoldi at y_n (FD
- * products use eps = sqrt(eps_mach) (1 + ||y_n||)).  M = 0 gives the explicit
+ * products use eps = sqrt((1 + ||y_n||) eps_mach)).  M = 0 gives the explicit
  * Runge-Kutta method (alpha, b).
  *   tab:    host tableau;  M: 0..ROK_MAX_M (clamped to N);  h: step size
  *   y_n, y_np1: N doubles each (may not alias)

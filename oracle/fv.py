@@ -251,20 +251,26 @@ def residual(P: Problem, y: torch.Tensor) -> torch.Tensor:
 # Jacobian-vector products (Sec. 2.3)
 # ---------------------------------------------------------------------------
 
-SQRT_EPS = math.sqrt(2.0 ** -52)
+EPS_MACH = 2.0 ** -52
 
 
 def fd_epsilon(y: torch.Tensor, v: torch.Tensor) -> float:
-    """Default finite-difference increment: sqrt(eps_mach) (1 + ||y||) / ||v||.
+    """Default finite-difference increment: sqrt((1 + ||y||) eps_mach) / ||v||.
 
-    The paper defers the choice of epsilon to the truncation/round-off balance
-    (Sec. 2.3); this is that balance for a per-entry perturbation of about
-    sqrt(eps_mach) times the size of y.
+    The paper defers the choice of epsilon to the literature on Jacobian-free
+    Newton-Krylov methods (Sec. 2.3).  Of the two usual rules, this one and
+    sqrt(eps_mach) (1 + ||y||) / ||v|| (a per-entry perturbation of about
+    sqrt(eps_mach) times the size of y), this one gives the smaller error
+    against the exact product on the seeded workloads at their sizes: f is
+    only piecewise smooth, and the larger perturbation crosses more switches
+    of minmod and of the wave-speed maximum.  Operation order: the sum, its
+    product with eps_mach (exact), a correctly rounded square root, then the
+    division.
     """
     from .krylov import dot
     ny = math.sqrt(dot(y, y))
     nv = math.sqrt(dot(v, v))
-    return SQRT_EPS * (1.0 + ny) / nv
+    return math.sqrt((1.0 + ny) * EPS_MACH) / nv
 
 
 def jvp_fd(P: Problem, y, fy, v, eps: float):

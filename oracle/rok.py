@@ -85,8 +85,9 @@ def rok_step(f, matvec_at, tab: dict, M: int, h: float, y: torch.Tensor, record:
 def fv_system(P: fv.Problem, mode: str = JVP_FD, eps: float | None = None):
     """(f, matvec_at) for the finite-volume right-hand side.
 
-    mode 'fd': finite-difference products with eps = sqrt(eps_mach) (1 + ||y_n||)
-    (unit Arnoldi vectors), or the given eps; mode 'exact': exact products.
+    mode 'fd': finite-difference products with eps = sqrt((1 + ||y_n||) eps_mach)
+    (fv.fd_epsilon for unit Arnoldi vectors), or the given eps; mode 'exact':
+    exact products.
     """
     def f(y):
         return fv.residual(P, y)
@@ -94,7 +95,7 @@ def fv_system(P: fv.Problem, mode: str = JVP_FD, eps: float | None = None):
     def matvec_at(y, fy):
         if mode == JVP_EXACT:
             return lambda v: fv.jvp_exact(P, y, v)
-        e = eps if eps is not None else fv.SQRT_EPS * (1.0 + math.sqrt(dot(y, y)))
+        e = eps if eps is not None else math.sqrt((1.0 + math.sqrt(dot(y, y))) * fv.EPS_MACH)
         return lambda v: fv.jvp_fd(P, y, fy, v, e)
 
     return f, matvec_at

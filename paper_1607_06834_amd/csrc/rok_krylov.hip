@@ -19,7 +19,7 @@
 namespace rok {
 
 constexpr double kBreakdownTol = 1e-13;
-constexpr double kSqrtEps = 1.4901161193847656e-08;  // sqrt(2^-52) = 2^-26
+constexpr double kEpsMach = 2.220446049250313e-16;   // 2^-52
 
 // Block of kRedThreads threads: the halving tree; every thread gets the sum.
 __device__ __forceinline__ double block_sum(double acc, double* s) {
@@ -115,10 +115,10 @@ __global__ __launch_bounds__(kRedThreads) void k_finish(const double* partials, 
             ints[2] |= ROK_FLAG_ZERO_RHS;
         }
         if (nonfinite(beta)) ints[2] |= ROK_FLAG_NONFINITE;
-    } else {  // FIN_EPS: eps = sqrt(u) (1 + ||y||) [/ ||v||]
+    } else {  // FIN_EPS: eps = sqrt((1 + ||y||) u) [/ ||v||]
         double ny = sqrt(tot);
         scal[0] = ny;
-        double e = kSqrtEps * (1.0 + ny);
+        double e = sqrt((1.0 + ny) * kEpsMach);
         if (has_v) e = e / scal[3];
         scal[1] = e;
     }

@@ -114,6 +114,37 @@ def test_fd_jvp_default_eps(dev):
     assert relerr(out, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["vortex1024_muscl", "tgv512", "tgv2048_ns"])
+def test_fd_increment_rules_full_size(dev, name):
+    """The default finite-difference increment sqrt((1 + ||y||) eps_mach) / ||v||
+    against sqrt(eps_mach) (1 + ||y||) / ||v||: error of the FD product against
+    the exact one over the first four Krylov vectors of the workload's seeded
+    state (generic: every variable perturbed, so no switch of f sits at y).
+    The default is the smaller at these sizes (reading of Sec. 2.3)."""
+    import math
+    if name == "tgv512":
+        pb = ri.tgv_problem(512, 2)
+        y0 = ri.tgv_state(pb)
+    else:
+        pb, y0, _ = ri.workload(name)
+    y0 = ri.perturb_generic(pb, y0)
+    R = gpu(pb)
+    y = torch.tensor(y0, device=dev)
+    F = R.residual(y)
+    V, H, m = R.arnoldi(y, F, 4, "exact")
+    ny = float(torch.linalg.norm(y))
+    errs = {"default": [], "sqrt_eps_scaled": []}
+    for j in range(m):
+        v = V[j].contiguous()
+        ex = R.jvp(y, v, "exact")
+        errs["default"].append(relerr(R.jvp(y, v, "fd", fy=F), ex))
+        e_other = math.sqrt(2.0 ** -52) * (1.0 + ny) / float(torch.linalg.norm(v))
+        errs["sqrt_eps_scaled"].append(relerr(R.jvp(y, v, "fd", fy=F, eps=e_other), ex))
+    mean = {k: sum(x) / len(x) for k, x in errs.items()}
+    say("  FD increment rules", name, "N", y.numel(), {k: f"{x:.2e}" for k, x in mean.items()})
+    assert mean["default"] < mean["sqrt_eps_scaled"]
+
+
 def test_3d_first_order_tangent_is_unsupported(dev):
     from paper_1607_06834_amd import RokError
     pb = VARIANTS["ns3d_fo"]((5, 4, 3))
