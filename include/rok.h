@@ -121,8 +121,11 @@ void rok_destroy(rok_ctx* ctx);
  * streamed through memory); ROK_MGS_RESIDENT runs one cooperative kernel per
  * Arnoldi column with the work vector held in registers (N up to 16 * 2^18 = 4194304);
  * ROK_MGS_AUTO (default) takes the resident kernel when the device and N
- * allow it.  Both produce bit-identical results.  Changes the context: not
- * to be called while other calls on the same context are being made.
+ * allow it.  Both produce bit-identical results.  The setting also selects
+ * the reverse of the Arnoldi columns in rok_step_vjp: one resident kernel per
+ * column for N up to 8 * 2^18 = 2097152 unless ROK_MGS_PER_PASS is set
+ * (per-pass kernels otherwise; bit-identical as well).  Changes the context:
+ * not to be called while other calls on the same context are being made.
  * ROK_EINVAL for an unknown path. */
 rok_status rok_set_mgs_path(rok_ctx* ctx, int path);
 
@@ -224,7 +227,10 @@ rok_status rok_step(rok_ctx* ctx, const rok_tableau* tab, int M, int mode, doubl
  * V and of H on y_n (modified Gram-Schmidt in reverse, the normalisation of
  * the first basis vector and the second-order residual adjoint of each
  * product J(y_n) v_j), so the result is the gradient of the computed step,
- * not of an idealised one.
+ * not of an idealised one (up to the rounding of the rebuilt MGS iterates:
+ * the last iterate of column j is taken as h_{j+1,j} v_{j+1} where v_{j+1}
+ * exists).  The workspace's status header reports the step (M_eff, flags)
+ * and ROK_FLAG_BARRIER if an in-kernel barrier of the reverse timed out.
  *   tab, M, h:  as rok_step
  *   y_n, ybar_np1, ybar_n, y_np1: N doubles each, device memory; ybar_n and
  *               y_np1 may not alias any other argument
