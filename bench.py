@@ -152,8 +152,12 @@ def _adjoint_leg(args, g, y, h, tab, M, stream):
 
     fwd = timed(lambda: g.step(y, h, tab, M, mode="tangent"))
     bwd = timed(lambda: g.step_vjp(y, yb, h, tab, M, out=out))
+    _, rec = g.step_keep(y, h, tab, M)         # the forward kept: reverse sweep only
+    g.step_vjp_stored(rec, yb, out=out)
+    stored = timed(lambda: g.step_vjp_stored(rec, yb, out=out))
     return {"forward_exact_ms_per_step": round(fwd, 4), "step_vjp_ms_per_step": round(bwd, 4),
-            "ratio": round(bwd / fwd, 3), "steps": K}
+            "ratio": round(bwd / fwd, 3), "step_vjp_stored_ms_per_step": round(stored, 4),
+            "ratio_stored": round(stored / fwd, 3), "steps": K}
 
 
 def _timed(stream, launches):

@@ -245,6 +245,32 @@ rok_status rok_step_vjp(rok_ctx* ctx, const rok_tableau* tab, int M, double h, c
 size_t rok_step_vjp_workspace_bytes(const rok_ctx* ctx, int M, int s);
 
 /*
+ * The reverse sweep of rok_step_vjp without recomputing the step: the same
+ * adjoint (Sec. 2.2.2, eq. 9; exact products), taken from the forward
+ * quantities (V, H, its LU factors, lambda_i, phi_i, F_i, k_i) that a call
+ * rok_step(ctx, tab, M, ROK_JVP_TANGENT, h, y_n, ...) left in `fwd_work`.
+ * It trades memory for time: a caller that keeps one forward workspace per
+ * step (rok_workspace_bytes(ctx, M, tab->s) bytes, about M + 2 s state
+ * vectors) reverses each step in about the time of the reverse sweep alone.
+ *   tab, M, h, y_n: exactly those of that rok_step call (not checked: any
+ *           other forward, an FD step included, gives a meaningless result)
+ *   ybar_np1, ybar_n: N doubles each; ybar_n may not alias y_n or ybar_np1
+ *   fwd_work: the forward workspace, device memory, rok_workspace_bytes(ctx,
+ *           M, tab->s) bytes; the call writes only its scratch words (work
+ *           vector, exchange and status words), so a forward may be reversed
+ *           several times
+ *   adj_work: rok_step_vjp_adjoint_bytes(ctx, M, tab->s) bytes, device memory
+ * Results are bitwise those of rok_step_vjp.  Euler physics and FP64
+ * precision only (ROK_EUNSUPPORTED otherwise).
+ */
+rok_status rok_step_vjp_stored(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
+                               const double* ybar_np1, double* ybar_n, void* fwd_work, size_t fwd_bytes,
+                               void* adj_work, size_t adj_bytes, void* stream);
+
+/* Bytes of adjoint workspace rok_step_vjp_stored needs (0 on invalid arguments). */
+size_t rok_step_vjp_adjoint_bytes(const rok_ctx* ctx, int M, int s);
+
+/*
  * Adjoint product of the residual (transposed Jacobian, Sec. 2.3 / eq. 11):
  *   ybar = J(y)^T wbar          (accumulate = 0)
  *   ybar = ybar + J(y)^T wbar   (accumulate = 1)

@@ -5,13 +5,16 @@ steps with exact (tangent) Jacobian-vector products and returns y_K as a
 tensor that torch can differentiate: the backward pass runs the discrete
 adjoint of every step (rok_step_vjp) in reverse order.
 
-Checkpointing: the forward keeps the states y_n with n a multiple of
+Checkpointing (default): the forward keeps the states y_n with n a multiple of
 `checkpoint_every` (all of them by default).  The backward walks the
 segments from last to first; each segment's intermediate states are
 recomputed from its checkpoint with rok_step, and every rok_step_vjp call
 recomputes the step's Krylov basis and stages from y_n itself.  Memory is
 therefore about (nsteps / checkpoint_every + checkpoint_every) state vectors
-plus one step's workspace.
+plus one step's workspace.  With store_forward=True every step keeps its
+state and forward workspace instead, and the backward runs only the reverse
+sweeps (rok_step_vjp_stored): the HBM of one GPU holds hundreds of steps at
+512^2.
 """
 from __future__ import annotations
 
@@ -52,9 +55,40 @@ class _RokTrajectory(torch.autograd.Function):
         return g, None, None, None, None, None, None
 
 
+class _RokTrajectoryStored(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y0, rok: Rok, h: float, tableau: dict, M: int, nsteps: int):
+        y = y0.detach().contiguous().clone()
+        recs = []
+        for _ in range(nsteps):
+            y1, rec = rok.step_keep(y, h, tableau, M)
+            recs.append(rec)
+            y = y1
+        ctx.rok, ctx.recs = rok, recs
+        return y
+
+    @staticmethod
+    def backward(ctx, gout):
+        g = gout.detach().contiguous().clone()
+        nxt = torch.empty_like(g)
+        for rec in reversed(ctx.recs):
+            ctx.rok.step_vjp_stored(rec, g, out=nxt)
+            g, nxt = nxt, g
+        ctx.recs = None
+        return g, None, None, None, None, None
+
+
 def rok_trajectory(rok: Rok, y0: torch.Tensor, h: float, tableau: dict, M: int, nsteps: int,
-                   checkpoint_every: int | None = None) -> torch.Tensor:
-    """y_K after nsteps exact-product ROK steps, differentiable with respect to y0."""
+                   checkpoint_every: int | None = None, store_forward: bool = False) -> torch.Tensor:
+    """y_K after nsteps exact-product ROK steps, differentiable with respect to y0.
+
+    store_forward=True keeps every step's state and forward workspace (about
+    M + 2 s + 1 state vectors per step) and reverses the steps from them
+    (Rok.step_vjp_stored) instead of recomputing: same bits, less time, more
+    memory.  Otherwise states are checkpointed every `checkpoint_every` steps.
+    """
+    if store_forward:
+        return _RokTrajectoryStored.apply(y0, rok, float(h), tableau, int(M), int(nsteps))
     every = 1 if checkpoint_every is None else int(checkpoint_every)
     if every < 1:
         raise ValueError("checkpoint_every must be >= 1")

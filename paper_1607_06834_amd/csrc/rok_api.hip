@@ -367,6 +367,33 @@ rok_status rok_step_vjp(rok_ctx* c, const rok_tableau* tab, int M, double h, con
     return ROK_OK;
 }
 
+size_t rok_step_vjp_adjoint_bytes(const rok_ctx* c, int M, int s) {
+    if (!c || M < 0 || s < 1 || s > ROK_MAX_STAGES) return 0;
+    int Mc = M > ROK_MAX_M ? ROK_MAX_M : M;
+    if ((long)Mc > c->G.N) Mc = (int)c->G.N;
+    return rok::adj_bytes(c->G.N, Mc, s);
+}
+
+rok_status rok_step_vjp_stored(rok_ctx* c, const rok_tableau* tab, int M, double h, const double* y_n,
+                               const double* ybar_np1, double* ybar_n, void* fwd_work, size_t fwd_bytes,
+                               void* adj_work, size_t adj_bytes, void* stream) {
+    if (!c || !tab || !y_n || !ybar_np1 || !ybar_n) return ROK_EINVAL;
+    if (!aligned(y_n, 8) || !aligned(ybar_np1, 8) || !aligned(ybar_n, 8)) return ROK_EINVAL;
+    if (ybar_n == y_n || ybar_n == ybar_np1) return ROK_EINVAL;
+    if (tab->s < 1 || tab->s > ROK_MAX_STAGES) return ROK_EINVAL;
+    if (M < 0 || M > ROK_MAX_M || !(h == h)) return ROK_EINVAL;
+    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    if ((long)M > c->G.N) M = (int)c->G.N;
+    const int s = tab->s;
+    const long N = c->G.N;
+    if (!fwd_work || !aligned(fwd_work, 256) || fwd_bytes < rok::work_bytes(N, M, s, true)) return ROK_EINVAL;
+    if (!adj_work || !aligned(adj_work, 256) || adj_bytes < rok::adj_bytes(N, M, s)) return ROK_EINVAL;
+    rok::Work W = rok::carve(fwd_work, N, M, s, true);
+    rok::AdjWork A = rok::adj_carve(adj_work, N, M, s);
+    ROK_TRY(step_adjoint(c, tab, M, h, y_n, ybar_np1, ybar_n, W, A, (hipStream_t)stream));
+    return ROK_OK;
+}
+
 rok_status rok_workspace_init(rok_ctx* c, void* work, size_t wbytes, int M, int s, void* stream) {
     if (!c || !work || !aligned(work, 256) || M < 0 || M > ROK_MAX_M || s < 0 || s > ROK_MAX_STAGES)
         return ROK_EINVAL;

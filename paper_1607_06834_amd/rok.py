@@ -26,7 +26,8 @@ MAX_STAGES, MAX_M = 8, 64
 
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual",
            "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
-           "rok_step_vjp_workspace_bytes", "rok_mgs_column", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
+           "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
+           "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
 MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
@@ -85,6 +86,10 @@ def load_library(path: str = LIB_PATH):
     lib.rok_step_vjp.restype = i
     lib.rok_step_vjp_workspace_bytes.argtypes = [vp, i, i]
     lib.rok_step_vjp_workspace_bytes.restype = sz
+    lib.rok_step_vjp_stored.argtypes = [vp, ctypes.POINTER(RokTableau), i, d, vp, vp, vp, vp, sz, vp, sz, vp]
+    lib.rok_step_vjp_stored.restype = i
+    lib.rok_step_vjp_adjoint_bytes.argtypes = [vp, i, i]
+    lib.rok_step_vjp_adjoint_bytes.restype = sz
     lib.rok_mgs_column.argtypes = [vp, vp, i, i, vp, vp, vp, vp, sz, vp]
     lib.rok_mgs_column.restype = i
     lib.rok_workspace_init.argtypes = [vp, vp, sz, i, i, vp]
@@ -130,6 +135,15 @@ def make_tableau(tab: dict) -> RokTableau:
     return t
 
 
+class ForwardRecord:
+    """An exact-product step kept for Rok.step_vjp_stored: the state y_n (held,
+    not copied: it must not change) and the step's own forward workspace."""
+    __slots__ = ("y", "h", "tableau", "M", "ws")
+
+    def __init__(self, y, h, tableau, M, ws):
+        self.y, self.h, self.tableau, self.M, self.ws = y, h, tableau, M, ws
+
+
 class Rok:
     """One problem (grid, physics, discretisation, precision) on the current GPU."""
 
@@ -163,14 +177,18 @@ class Rok:
             self._ctx = None
 
     # -- workspace ---------------------------------------------------------
-    def workspace(self, M: int, s: int, adjoint: bool = False) -> torch.Tensor:
-        if adjoint:
+    def workspace(self, M: int, s: int, adjoint: bool | str = False) -> torch.Tensor:
+        """Cached aligned workspace: rok_workspace_bytes (adjoint=False),
+        rok_step_vjp_workspace_bytes (True) or rok_step_vjp_adjoint_bytes ("only")."""
+        if adjoint == "only":
+            nb = int(_lib.rok_step_vjp_adjoint_bytes(self._ctx, int(M), int(s)))
+        elif adjoint:
             nb = int(_lib.rok_step_vjp_workspace_bytes(self._ctx, int(M), int(s)))
         else:
             nb = int(_lib.rok_workspace_bytes(self._ctx, int(M), int(s)))
         if nb == 0:
             raise ValueError(f"invalid workspace request M={M}, s={s}")
-        key = (int(M), int(s), bool(adjoint))
+        key = (int(M), int(s), adjoint if adjoint == "only" else bool(adjoint))
         w = self._work.get(key)
         if w is None or w.numel() < nb:
             w = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
@@ -269,6 +287,36 @@ class Rok:
         _check(_lib.rok_step_vjp(self._ctx, ctypes.byref(tab), int(M), float(h), _ptr(y), _ptr(ybar_next), _ptr(yb),
                                  _ptr(y_next_out), _ptr(ws), ws.numel(), _stream()), "rok_step_vjp")
         self._last_step_ws = ws   # the status header leads the adjoint workspace too
+        return yb
+
+    def step_keep(self, y, h: float, tableau: dict, M: int, out=None):
+        """Exact-product step in a workspace of its own, kept for step_vjp_stored:
+        returns (y_{n+1}, ForwardRecord).  Memory: one forward workspace (about
+        M + 2 s state vectors) per kept step."""
+        self._vec(y, "y")
+        y1 = out if out is not None else torch.empty_like(y)
+        tab = make_tableau(tableau)
+        nb = int(_lib.rok_workspace_bytes(self._ctx, int(M), tab.s))
+        buf = torch.empty(nb + 256, dtype=torch.uint8, device=y.device)
+        off = (-buf.data_ptr()) % 256
+        ws = buf[off:off + nb]
+        _check(_lib.rok_step(self._ctx, ctypes.byref(tab), int(M), JVP_TANGENT, float(h), _ptr(y), _ptr(y1),
+                             _ptr(ws), ws.numel(), _stream()), "rok_step")
+        self._last_step_ws = ws
+        return y1, ForwardRecord(y, float(h), tableau, int(M), ws)
+
+    def step_vjp_stored(self, rec: ForwardRecord, ybar_next, out=None):
+        """(d y_{n+1}/d y_n)^T ybar_next from a kept step, without recomputing it
+        (bitwise equal to step_vjp)."""
+        self._vec(ybar_next, "ybar_next")
+        yb = out if out is not None else torch.empty_like(ybar_next)
+        self._vec(yb, "out")
+        tab = make_tableau(rec.tableau)
+        aws = self.workspace(rec.M, tab.s, adjoint="only")
+        _check(_lib.rok_step_vjp_stored(self._ctx, ctypes.byref(tab), rec.M, rec.h, _ptr(rec.y), _ptr(ybar_next),
+                                        _ptr(yb), _ptr(rec.ws), rec.ws.numel(), _ptr(aws), aws.numel(), _stream()),
+               "rok_step_vjp_stored")
+        self._last_step_ws = rec.ws
         return yb
 
     def mgs_workspace(self, M: int) -> torch.Tensor:

@@ -232,6 +232,63 @@ def test_step_vjp_resident_reverse_bitwise(dev, kind, n, M):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("kind,n,M", [("fo", 8, 6), ("muscl", (12, 10), 8), ("fo", (33, 20), 12), ("fo", 512, 16),
+                                      ("fo", 8, 0)])
+def test_step_vjp_stored_bitwise(dev, kind, n, M):
+    """The reverse sweep from a kept exact-product step (rok_step_vjp_stored)
+    gives the bits of rok_step_vjp, also when the same forward is reversed
+    twice; the kept step's y_{n+1} is that of rok_step."""
+    pb, y0 = _step_case(kind, n)
+    say("stored reverse", kind, n, M)
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, 2.0 if M else 0.5)
+    R = gpu(pb)
+    yd = torch.tensor(y0, device=dev)
+    cd = torch.tensor(ri.random_direction(y0.size, 5), device=dev)
+    y1a = torch.empty_like(yd)
+    a = R.step_vjp(yd, cd, h, tab, M, y_next_out=y1a)
+    y1b, rec = R.step_keep(yd, h, tab, M)
+    b = R.step_vjp_stored(rec, cd)
+    c = R.step_vjp_stored(rec, cd)
+    assert R.last_status()[0] & 8 == 0
+    assert torch.equal(y1a, y1b)
+    assert torch.isfinite(b).all()
+    assert torch.equal(a, b) and torch.equal(b, c)
+
+
+def test_trajectory_store_forward_matches_checkpointing(dev):
+    """Gradient of a 5-step trajectory through kept forwards equals the
+    checkpointed one bit for bit."""
+    from paper_1607_06834_amd.autograd import rok_trajectory
+    pb, y0 = _step_case("muscl", (12, 10))
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, 2.0)
+    R = gpu(pb)
+    grads = []
+    for kw in ({"checkpoint_every": 2}, {"store_forward": True}):
+        yd = torch.tensor(y0, device=dev).requires_grad_(True)
+        yK = rok_trajectory(R, yd, h, tab, 8, 5, **kw)
+        (g,) = torch.autograd.grad(_ke_torch(pb, yK), yd)
+        grads.append(g)
+    assert torch.isfinite(grads[0]).all()
+    assert torch.equal(grads[0], grads[1])
+
+
+def test_step_vjp_stored_bad_arguments(dev):
+    from paper_1607_06834_amd import RokError
+    from paper_1607_06834_amd.rok import ForwardRecord
+    pb, y0 = _step_case("fo", 8)
+    R = gpu(pb)
+    tab = ri.rok4_tableau()
+    yd = torch.tensor(y0, device=dev)
+    _, rec = R.step_keep(yd, 0.01, tab, 6)
+    short = ForwardRecord(rec.y, rec.h, rec.tableau, rec.M, rec.ws[:256])
+    with pytest.raises(RokError):
+        R.step_vjp_stored(short, yd.clone())
+    with pytest.raises(RokError):
+        R.step_vjp_stored(rec, yd.clone(), out=rec.y)   # ybar_n may not alias y_n
+
+
 def test_step_vjp_zero_rhs_is_the_explicit_adjoint(dev):
     """f(y) = 0 gives M_eff = 0: the adjoint equals that of the M = 0 (explicit) step, bit for bit."""
     pb = ri.vortex_problem(8, "first")
@@ -326,6 +383,19 @@ def test_differentiation_workload_full_size(dev):
     say("  KE(y_K)", float(L), "forward s", round(t1 - t0, 3), "backward s", round(t2 - t1, 3))
     assert np.isfinite(float(L))
     assert torch.isfinite(g).all()
+    # the same gradient from kept forwards (no recomputation; ~10 GB of forward workspaces)
+    ys = torch.tensor(y0, device=dev).requires_grad_(True)
+    torch.cuda.synchronize()
+    t3 = time.time()
+    Ls = _ke_torch(pb, rok_trajectory(R, ys, h, tab, M, K, store_forward=True))
+    torch.cuda.synchronize()
+    t4 = time.time()
+    (gs,) = torch.autograd.grad(Ls, ys)
+    torch.cuda.synchronize()
+    t5 = time.time()
+    say("  kept forwards: forward s", round(t4 - t3, 3), "backward s", round(t5 - t4, 3))
+    assert torch.equal(gs, g)
+    del gs, Ls, ys
     y0d = torch.tensor(y0, device=dev)
     ny = torch.linalg.norm(y0d)
     gold = json.load(open(GOLDEN)) if os.path.exists(GOLDEN) else {}
