@@ -32,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles (16 lanes), 2.4 GHz
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4.0
 
 
 def parse():
@@ -174,7 +176,8 @@ def _timed(stream, launches):
     return sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
 
-def _traffic(path, sources, key):
+def _traffic(path, sources, key, field="hbm_bytes_per_launch"):
+    """A counter figure per launch (HBM bytes by default) stored for `key`, or None."""
     if not path or not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -183,7 +186,7 @@ def _traffic(path, sources, key):
     # counters are only valid for the kernel source they were taken on
     if not ent or ent.get("source_sha256_16") != _source_hash(sources):
         return None
-    return ent.get("hbm_bytes_per_launch")
+    return ent.get(field)
 
 
 def _mgs_roofline(args, g, y, M, mode, stream):
@@ -240,12 +243,21 @@ def _jvp_roofline(args, g, y, w, stream):
     alg = 4 * 8 * N
     achieved = alg / (ms * 1e-3) / 1e9
     traffic = None
+    valu = None
     if args.workload == "vortex1024_muscl":
         traffic = _traffic(args.traffic, RESIDUAL_SOURCES, "fd_jvp")
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "FD Jacobian-vector product (residual at y + eps v, minus f(y), over eps)",
-            "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": alg}
+        valu = _traffic(args.traffic, RESIDUAL_SOURCES, "fd_jvp", "valu_insts_per_launch")
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    common = {"kernel": "FD Jacobian-vector product (residual at y + eps v, minus f(y), over eps)",
+              "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": alg}
+    if valu is None:
+        return dict(hbm, **common)
+    # the binding roof: wave-level VALU instructions issued per second (SQ_INSTS_VALU per launch, counter run)
+    ginst = valu / (ms * 1e-3) / 1e9
+    return dict({"bound": "alu", "achieved": round(ginst, 1), "peak": VALU_PEAK_GINST,
+                 "unit": "G VALU wave-instructions/s", "frac": round(ginst / VALU_PEAK_GINST, 4),
+                 "valu_insts_per_launch": valu, "hbm": hbm}, **common)
 
 
 
