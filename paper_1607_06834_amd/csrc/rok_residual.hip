@@ -47,11 +47,14 @@ __device__ __forceinline__ void load_state(const ResArgs& A, long ncell, long gi
     }
 }
 
-// Tile shapes.  Box = tile + 2 halo cells on each side.
-template <int D, int TX, int TY, int TZ>
+// Tile shapes.  Box = tile + HW halo cells on each side: 2 for MUSCL (the
+// reconstruction reaches two cells past a face), 1 for first order (the face
+// and, for viscous terms, the tangential neighbours).
+template <int D, int TX, int TY, int TZ, int HW>
 struct Tile {
+    static constexpr int H = HW;
     static constexpr int TZe = (D == 3) ? TZ : 1;
-    static constexpr int BX = TX + 4, BY = TY + 4, BZ = (D == 3) ? TZ + 4 : 1;
+    static constexpr int BX = TX + 2 * HW, BY = TY + 2 * HW, BZ = (D == 3) ? TZ + 2 * HW : 1;
     static constexpr int BOX = BX * BY * BZ;
     static constexpr int CELLS = TX * TY * TZe;
     static constexpr int NF0 = (TX + 1) * TY * TZe;
@@ -72,7 +75,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt0, int nt1) {
-    using T = Tile<D, TX, TY, TZ>;
+    using T = Tile<D, TX, TY, TZ, (RECON == 0 ? 1 : 2)>;
     using R = typename Sc<S>::R;
     constexpr int NV = D + 2;
     constexpr bool FO = (RECON == 0);
@@ -106,9 +109,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     __shared__ double s_refd[D + 3];   // r0, u0[D], p0, T0 = p0 / r0
     if constexpr (PERT) {
         if (tid == 0) {
-            const int gx = wrap(x0 - 2 + T::BX / 2, n0);
-            const int gy = wrap(y0 - 2 + T::BY / 2, n1);
-            const int gz = (D == 3) ? wrap(z0 - 2 + T::BZ / 2, n2) : 0;
+            const int gx = wrap(x0 - T::H + T::BX / 2, n0);
+            const int gy = wrap(y0 - T::H + T::BY / 2, n1);
+            const int gz = (D == 3) ? wrap(z0 - T::H + T::BZ / 2, n2) : 0;
             const long gi = ((long)gz * n1 + gy) * n0 + gx;
             double U[NV];
             load_state<MODE_PLAIN, NV, double>(MODE == MODE_PLAIN ? A : ResArgs{A.y}, G.ncell, gi, 0.0, U);
@@ -145,9 +148,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
         int bx = c % T::BX;
         int by = (c / T::BX) % T::BY;
         int bz = c / (T::BX * T::BY);
-        int gx = wrap(x0 - 2 + bx, n0);
-        int gy = wrap(y0 - 2 + by, n1);
-        int gz = (D == 3) ? wrap(z0 - 2 + bz, n2) : 0;
+        int gx = wrap(x0 - T::H + bx, n0);
+        int gy = wrap(y0 - T::H + by, n1);
+        int gz = (D == 3) ? wrap(z0 - T::H + bz, n2) : 0;
         long gi = ((long)gz * n1 + gy) * n0 + gx;
         if constexpr (PERT) {
             using SD = typename Wide<S>::type;
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             int fx = f % FX;
             int fy = (f / FX) % FY;
             int fz = f / (FX * FY);
-            int cb = ((fz + ((D == 3) ? 2 : 0)) * T::BY + (fy + 2)) * T::BX + (fx + 2);
+            int cb = ((fz + ((D == 3) ? T::H : 0)) * T::BY + (fy + T::H)) * T::BX + (fx + T::H);
             int ca = cb - sd;
             S Fh[NV];
             S UL[NV], UR[NV], vL[D], vR[D];
@@ -358,9 +361,7 @@ static hipError_t launch_v(const Geom& G, const ResArgs& A, hipStream_t st) {
         if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 16, 1>(G, A, st);
         else return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 8, 1>(G, A, st);
     } else {
-        // first-order 3-D keeps conserved and primitive states in LDS: too large for dual numbers
-        if constexpr (RECON == 0 && sizeof(S) > 8) return hipErrorNotSupported;
-        else return launch_t<D, RECON, NSV, S, MODE, OUT, 16, 4, 4>(G, A, st);
+        return launch_t<D, RECON, NSV, S, MODE, OUT, 16, 4, 4>(G, A, st);
     }
 }
 

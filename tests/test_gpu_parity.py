@@ -54,6 +54,7 @@ VARIANTS = {
     "ns3d_muscl": lambda n: ri.problem(n, (0.0, 0.0, 0.0), (1.0, 0.9, 1.2), "ns", "muscl", mu=0.05),
     "euler3d_muscl": lambda n: ri.problem(n, (0.0, 0.0, 0.0), (1.0, 0.9, 1.2), "euler", "muscl"),
     "ns3d_fo": lambda n: ri.problem(n, (0.0, 0.0, 0.0), (1.0, 0.9, 1.2), "ns", "first", mu=0.05),
+    "euler3d_fo": lambda n: ri.problem(n, (0.0, 0.0, 0.0), (1.0, 0.9, 1.2), "euler", "first"),
 }
 SHAPES_2D = [(6, 5), (37, 21), (70, 33)]      # tiny (wraps inside a tile), ragged, several tiles
 SHAPES_3D = [(5, 4, 3), (19, 9, 7)]
@@ -90,7 +91,7 @@ def test_fd_jvp_bitwise_given_eps(dev, name, shape):
     assert torch.equal(out, ref), relerr(out, ref)
 
 
-@pytest.mark.parametrize("name,shape", [c for c in CASES if c[0] != "ns3d_fo"])
+@pytest.mark.parametrize("name,shape", CASES)
 def test_tangent_jvp(dev, name, shape):
     say("tangent jvp", name, shape)
     pb = VARIANTS[name](shape)
@@ -145,16 +146,7 @@ def test_fd_increment_rules_full_size(dev, name):
     assert mean["default"] < mean["sqrt_eps_scaled"]
 
 
-def test_3d_first_order_tangent_is_unsupported(dev):
-    from paper_1607_06834_amd import RokError
-    pb = VARIANTS["ns3d_fo"]((5, 4, 3))
-    r = gpu(pb)
-    y = torch.tensor(_state(pb, 1), device=dev)
-    with pytest.raises(RokError):
-        r.jvp(y, y, "exact")
-
-
-@pytest.mark.parametrize("name", ["euler_muscl", "ns_muscl", "ns3d_muscl"])
+@pytest.mark.parametrize("name", ["euler_muscl", "ns_muscl", "ns3d_muscl", "euler_fo", "ns3d_fo"])
 def test_fp32_residual_and_tangent_error_vs_fp64_oracle(dev, name):
     say("fp32", name)
     shape = (37, 21) if "3d" not in name else (19, 9, 7)
