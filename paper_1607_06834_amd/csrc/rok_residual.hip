@@ -87,6 +87,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     constexpr int NP = OFF_P + 1 + (NSV ? 1 : 0);
     constexpr int CPT = T::CELLS / kThreads;
     static_assert(T::CELLS % kThreads == 0, "tile must be a multiple of the block size");
+    constexpr int kFaceUnroll = (D == 2 && sizeof(S) == 8 && !PERT) ? 2 : 1;
 
     __shared__ S sq[NP][T::BOX];
     __shared__ S fb[NV][T::NFMAX];
@@ -143,7 +144,55 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
         __syncthreads();
     }
 
-    // 1. stage the box in LDS as primitive variables
+    // 1. stage the box in LDS as primitive variables.  All loads of this
+    // thread's box cells are issued first, then converted: the loads overlap
+    // instead of waiting one cell at a time.
+    if constexpr (!PERT) {
+        constexpr int NIT = (T::BOX + kThreads - 1) / kThreads;
+        S Ub[NIT][NV];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int c = tid + it * kThreads;
+            if (it + 1 < NIT || c < T::BOX) {
+                int bx = c % T::BX;
+                int by = (c / T::BX) % T::BY;
+                int bz = c / (T::BX * T::BY);
+                int gx = wrap(x0 - T::H + bx, n0);
+                int gy = wrap(y0 - T::H + by, n1);
+                int gz = (D == 3) ? wrap(z0 - T::H + bz, n2) : 0;
+                long gi = ((long)gz * n1 + gy) * n0 + gx;
+                load_state<MODE, NV, S>(A, G.ncell, gi, eps, Ub[it]);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int c = tid + it * kThreads;
+            if (it + 1 < NIT || c < T::BOX) {
+                S* U = Ub[it];
+                const R gm1 = (R)G.gm1;
+                const R half = (R)0.5;
+                S r = U[0];
+                S vel[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) vel[d] = U[1 + d] / r;
+                S ke = vel[0] * vel[0];
+#pragma unroll
+                for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
+                S p = gm1 * (U[D + 1] - (half * r) * ke);
+                if constexpr (CONS) {
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) sq[m][c] = U[m];
+                } else {
+                    sq[0][c] = r;
+                }
+#pragma unroll
+                for (int d = 0; d < D; ++d) sq[OFF_VEL + d][c] = vel[d];
+                sq[OFF_P][c] = p;
+                if constexpr (NSV) sq[OFF_T][c] = p / r;
+            }
+        }
+        __syncthreads();
+    } else {
     for (int c = tid; c < T::BOX; c += kThreads) {
         int bx = c % T::BX;
         int by = (c / T::BX) % T::BY;
@@ -196,6 +245,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     }
     __syncthreads();
 
+    }
+
     S res[CPT][NV];
 
 #pragma unroll
@@ -203,7 +254,10 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
         const int FX = TX + (d == 0), FY = TY + (d == 1);
         const int NF = (d == 0) ? T::NF0 : (d == 1 ? T::NF1 : T::NF2);
         const int sd = T::stride(d);
-        // 2. every face flux of the tile along d, once
+        // 2. every face flux of the tile along d, once (plain FP64: two faces
+        // interleaved per thread, which hides the latency of their long chains
+        // of divisions and square roots)
+#pragma unroll(kFaceUnroll)
         for (int f = tid; f < NF; f += kThreads) {
             int fx = f % FX;
             int fy = (f / FX) % FY;
@@ -358,7 +412,9 @@ template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT>
 static hipError_t launch_v(const Geom& G, const ResArgs& A, hipStream_t st) {
     constexpr bool wide = sizeof(S) <= 8;   // double or float (not a dual number)
     if constexpr (D == 2) {
-        if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 16, 1>(G, A, st);
+        if constexpr (RECON == 1 && sizeof(S) == 8 && sizeof(typename Sc<S>::R) == 8)
+            return launch_t<D, RECON, NSV, S, MODE, OUT, 16, 16, 1>(G, A, st);   // FP64 (measured best)
+        else if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 16, 1>(G, A, st);
         else return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 8, 1>(G, A, st);
     } else {
         return launch_t<D, RECON, NSV, S, MODE, OUT, 16, 4, 4>(G, A, st);
