@@ -120,11 +120,12 @@ def gpu_leg(args, pb, y0, w, tab, h):
     torch.cuda.synchronize()
     mgs = _mgs_roofline(args, g, ya, M, mode, stream)
     jvp = _jvp_roofline(args, g, ya, w, stream)
+    resid = _residual_roofline(args, g, ya, w, stream)
     adj = None
     if (args.adjoint or args.workload == "vortex512_adjoint") and not args.roofline_only:
         adj = _adjoint_leg(args, g, ya, h, tab, M, stream)
     return {"ms_per_step": ev_ms / max(steps, 1), "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite,
-            "roofline": mgs, "roofline_jvp": jvp, "adjoint": adj}
+            "roofline": mgs, "roofline_jvp": jvp, "roofline_residual": resid, "adjoint": adj}
 
 
 def _adjoint_leg(args, g, y, h, tab, M, stream):
@@ -223,6 +224,33 @@ def _mgs_roofline(args, g, y, M, mode, stream):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"modified Gram-Schmidt Arnoldi column (k_mgs_resident), average over the {m} columns of a step",
             "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": int(alg)}
+
+
+def _residual_roofline(args, g, y, w, stream):
+    """The residual kernel F = f(y): reads y, writes F (16 B per element in
+    FP64; 12 B when F is written in FP32)."""
+    import torch
+    N = g.N
+    out = torch.empty(N, dtype=torch.float64 if w["precision"] == "fp64" else torch.float32, device=y.device)
+    for _ in range(3):
+        g.residual(y, out=out)
+    torch.cuda.synchronize()
+    ms = _timed(stream, [lambda: g.residual(y, out=out)] * args.kernel_reps)
+    alg = (8 + out.element_size()) * N
+    achieved = alg / (ms * 1e-3) / 1e9
+    traffic = valu = None
+    if args.workload == "vortex1024_muscl":
+        traffic = _traffic(args.traffic, RESIDUAL_SOURCES, "residual")
+        valu = _traffic(args.traffic, RESIDUAL_SOURCES, "residual", "valu_insts_per_launch")
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    common = {"kernel": "finite-volume residual F = f(y)", "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": alg}
+    if valu is None:
+        return dict(hbm, **common)
+    ginst = valu / (ms * 1e-3) / 1e9
+    return dict({"bound": "alu", "achieved": round(ginst, 1), "peak": VALU_PEAK_GINST,
+                 "unit": "G VALU wave-instructions/s", "frac": round(ginst / VALU_PEAK_GINST, 4),
+                 "valu_insts_per_launch": valu, "hbm": hbm}, **common)
 
 
 def _jvp_roofline(args, g, y, w, stream):
@@ -386,6 +414,7 @@ def main():
         "status": {"flags": res["flags"], "M_eff": res["M_eff"], "finite": res["finite"]},
         "roofline": res["roofline"],
         "roofline_jvp": res["roofline_jvp"],
+        "roofline_residual": res["roofline_residual"],
         "adjoint": res["adjoint"],
         "equal_error": eq,
         "cpu_baseline": cpu,
