@@ -17,6 +17,7 @@ tangent products vs plain FP64 with finite-difference products, a
 work-precision sweep on a 512^2 Taylor-Green proxy).
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-equal-error]
+                    [--adjoint] [--krylov-sweep]
 """
 from __future__ import annotations
 
@@ -54,6 +55,8 @@ def parse():
                          "differentiation workload)")
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the FP32-tangent vs FP64-FD equal-error sweep")
+    ap.add_argument("--krylov-sweep", action="store_true",
+                    help="also run the Krylov-dimension sweep (M = 4..20: error and time at fixed final time)")
     ap.add_argument("--chain", action="store_true",
                     help="time a trajectory (each step starts from the previous result) instead of K passes "
                          "over the seeded input state")
@@ -352,6 +355,55 @@ def equal_error_leg(args):
             "reference": "FP64 exact-product ROK at CFL 1/8", "points": pts, "speedup_at_equal_error": ratios}
 
 
+def krylov_sweep_leg(args):
+    """Krylov dimension M in {4, 8, 12, 16, 20} (FP64, FD products): error at a
+    fixed final time T = 10 h(CFL 4) and its cost, at CFL 1, 2, 4, 8, on the
+    512^2 Taylor-Green proxy and the 1024^2 MUSCL vortex.  Error: ||y_N - y_ref||
+    / ||y_ref|| with y_ref the exact-product ROK solution at CFL 1/8 and M = 20;
+    trajectories timed with HIP events; null where the trajectory is not finite."""
+    import torch
+
+    import rok_inputs as ri
+    from paper_1607_06834_amd import Rok
+
+    dev = torch.device("cuda", 0)
+    tab = ri.rok4_tableau()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, (pb, y0) in (("taylor_green_512", (ri.tgv_problem(512, 2), None)),
+                           ("vortex_muscl_1024", (ri.vortex_problem(1024, "muscl"), None))):
+        y0 = ri.tgv_state(pb) if pb["physics"] == "ns" else ri.vortex_state(pb)
+        T = 10 * ri.cfl_step(pb, y0, 4.0)
+        g = Rok(pb, "fp64")
+
+        def run(cfl, M, mode):
+            K = int(round(T / ri.cfl_step(pb, y0, cfl)))
+            h = T / K
+            y = torch.tensor(y0, device=dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(K):
+                y = g.step(y, h, tab, M, mode)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return y, e0.elapsed_time(e1), K
+
+        ref, _, _ = run(0.125, 20, "exact")
+        nref = float(torch.linalg.vector_norm(ref))
+        rows = []
+        for M in (4, 8, 12, 16, 20):
+            for cfl in (1.0, 2.0, 4.0, 8.0):
+                y, ms, K = run(cfl, M, "fd")
+                fin = bool(torch.isfinite(y).all())
+                err = float(torch.linalg.vector_norm(y - ref)) / nref if fin else None
+                rows.append({"M": M, "cfl": cfl, "steps": K, "ms": round(ms, 3),
+                             "ms_per_step": round(ms / K, 4), "error": float(f"{err:.4e}") if err is not None else None})
+        out[name] = rows
+        del g
+    return out
+
+
 def cpu_leg(args, pb, y0, w, tab, h):
     import torch
 
@@ -379,7 +431,7 @@ def cpu_leg(args, pb, y0, w, tab, h):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the path has no multi-GPU form",
               file=sys.stderr)
         sys.exit(2)
     import rok_inputs as ri
@@ -389,6 +441,7 @@ def main():
     h = ri.cfl_step(pb, y0, w["cfl"])
     res = gpu_leg(args, pb, y0, w, tab, h)
     eq = None if (args.no_equal_error or args.roofline_only) else equal_error_leg(args)
+    ksw = krylov_sweep_leg(args) if (args.krylov_sweep and not args.roofline_only) else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, pb, y0, w, tab, h)
     n = "x".join(str(x) for x in pb["n"])
     line = {
@@ -417,6 +470,7 @@ def main():
         "roofline_residual": res["roofline_residual"],
         "adjoint": res["adjoint"],
         "equal_error": eq,
+        "krylov_sweep": ksw,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -282,7 +282,8 @@ def test_arnoldi_zero_rhs_and_breakdown(dev):
 
 @pytest.mark.parametrize("mgs", MGS)
 @pytest.mark.parametrize("mode,recon,M", [("fd", "muscl", 8), ("exact", "muscl", 8), ("fd", "first", 6),
-                                          ("exact", "first", 0), ("fd", "muscl", 20)])
+                                          ("exact", "first", 0), ("fd", "muscl", 20), ("fd", "muscl", 4),
+                                          ("exact", "muscl", 4), ("fd", "muscl", 12)])
 def test_rok_step_parity(dev, mode, recon, M, mgs):
     say("step", mode, recon, M, mgs)
     pb = ri.vortex_problem(24, recon)
