@@ -17,4 +17,5 @@ rok         one ROK step (Sec. 2.2.2, eq. 9) and trajectories
 rk          explicit Runge-Kutta (Sec. 2.1, eq. 2), used as an independent check
 lorenz96    the Lorenz-96 test problem of the Appendix
 conditions  order conditions used to derive and check ROK coefficient tables
+adaptive    step-size control by step doubling (Sec. 4.2 reading)
 """
