@@ -57,6 +57,8 @@ def parse():
                     help="skip the FP32-tangent vs FP64-FD equal-error sweep")
     ap.add_argument("--krylov-sweep", action="store_true",
                     help="also run the Krylov-dimension sweep (M = 4..20: error and time at fixed final time)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="also run the adaptive work-precision sweep (step doubling; ERK4 vs ROK4 M = 4, 8)")
     ap.add_argument("--chain", action="store_true",
                     help="time a trajectory (each step starts from the previous result) instead of K passes "
                          "over the seeded input state")
@@ -404,6 +406,68 @@ def krylov_sweep_leg(args):
     return out
 
 
+def adaptive_leg(args):
+    """Adaptive step-size control (step doubling, rok_integrate_adaptive):
+    explicit RK4 (M = 0) against ROK4 with M = 4 and 8 (FD products, FP64) at
+    rtol = atol in {1e-3, 1e-4, 1e-5, 1e-6}, from H0 = h(CFL 1) to T = 100
+    h(CFL 4) on the 512^2 Taylor-Green proxy (Mach 0.1: acoustic waves set the
+    explicit limit, the vortical flow the accuracy) and T = 40 h(CFL 4) on the
+    1024^2 MUSCL vortex.
+    Error: ||y_T - y_ref|| / ||y_ref|| with y_ref the exact-product ROK
+    solution at CFL 1/8 and M = 20.  Reported per run: accepted and rejected
+    macro steps, ROK steps taken (3 per attempt), wall time of the call (it
+    synchronises once per macro step), the mean accepted step in CFL units and
+    the error."""
+    import time
+
+    import torch
+
+    import rok_inputs as ri
+    from paper_1607_06834_amd import Rok
+
+    dev = torch.device("cuda", 0)
+    tab = ri.rok4_tableau()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, pb, span in (("taylor_green_512", ri.tgv_problem(512, 2), 100),
+                           ("vortex_muscl_1024", ri.vortex_problem(1024, "muscl"), 40)):
+        y0 = ri.tgv_state(pb) if pb["physics"] == "ns" else ri.vortex_state(pb)
+        h1 = ri.cfl_step(pb, y0, 1.0)
+        T = span * ri.cfl_step(pb, y0, 4.0)
+        g = Rok(pb, "fp64")
+        K = int(round(T / ri.cfl_step(pb, y0, 0.125)))
+        y = torch.tensor(y0, device=dev)
+        for _ in range(K):
+            y = g.step(y, T / K, tab, 20, "exact")
+        ref = y
+        nref = float(torch.linalg.vector_norm(ref))
+        yd = torch.tensor(y0, device=dev)
+        g.integrate_adaptive(yd, h1, h1, tab, 4, "fd")          # warm-up (workspace, code objects)
+        rows = []
+        for M in (0, 4, 8):
+            for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                try:
+                    yT, rec = g.integrate_adaptive(yd, T, h1, tab, M, "fd", order=4, rtol=tol, atol=tol,
+                                                   max_steps=1000, history_cap=0)
+                except Exception as exc:        # noqa: BLE001 - a run that does not reach T is reported
+                    rows.append({"M": M, "tol": tol, "error": None, "note": str(exc)[:120]})
+                    print(f"[adaptive] {name} {rows[-1]}", file=sys.stderr, flush=True)
+                    continue
+                ms = (time.perf_counter() - t0) * 1e3
+                fin = bool(torch.isfinite(yT).all())
+                err = float(torch.linalg.vector_norm(yT - ref)) / nref if fin else None
+                na, nr = rec["n_accepted"], rec["n_rejected"]
+                rows.append({"M": M, "tol": tol, "accepted": na, "rejected": nr, "rok_steps": 3 * (na + nr),
+                             "ms": round(ms, 2), "mean_cfl": round(T / na / h1, 3),
+                             "error": float(f"{err:.4e}") if err is not None else None})
+                print(f"[adaptive] {name} {rows[-1]}", file=sys.stderr, flush=True)
+        out[name] = {"T": T, "h_cfl1": h1, "rows": rows}
+        del g
+    return out
+
+
 def cpu_leg(args, pb, y0, w, tab, h):
     import torch
 
@@ -442,6 +506,7 @@ def main():
     res = gpu_leg(args, pb, y0, w, tab, h)
     eq = None if (args.no_equal_error or args.roofline_only) else equal_error_leg(args)
     ksw = krylov_sweep_leg(args) if (args.krylov_sweep and not args.roofline_only) else None
+    ada = adaptive_leg(args) if (args.adaptive and not args.roofline_only) else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, pb, y0, w, tab, h)
     n = "x".join(str(x) for x in pb["n"])
     line = {
@@ -471,6 +536,7 @@ def main():
         "adjoint": res["adjoint"],
         "equal_error": eq,
         "krylov_sweep": ksw,
+        "adaptive": ada,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -217,6 +217,71 @@ rok_status rok_step(rok_ctx* ctx, const rok_tableau* tab, int M, int mode, doubl
                     const double* y_n, double* y_np1, void* work, size_t work_bytes, void* stream);
 
 /*
+ * Weighted RMS norm of a local error estimate, for adaptive step-size control
+ * (Sec. 4.2 compares the adaptive step sizes of explicit Runge-Kutta and ROK;
+ * the estimator is not stated there, and the library's reading is step
+ * doubling, see rok_integrate_adaptive):
+ *   sc_i = atol + rtol * max(|y_n,i|, |y_a,i|)
+ *   q_i  = (y_a,i - y_b,i) / (scale * sc_i)
+ *   *err = sqrt( sum_i q_i^2 / N )
+ * with the sum taken in the library's fixed order (bitwise reproducible).
+ * A NaN in y_n or y_a propagates to *err.
+ *   y_n, y_a, y_b: N doubles each, device memory
+ *   rtol, atol:    >= 0, finite, not both zero;  scale: > 0, finite
+ *   err:           one double, device memory, written on `stream`
+ *   work:          rok_workspace_bytes(ctx, 0, 0) bytes (any larger workspace
+ *                  works); its status header and reduction scratch are
+ *                  overwritten, so a forward kept for rok_step_vjp_stored
+ *                  must not be passed
+ */
+rok_status rok_error_norm(rok_ctx* ctx, const double* y_n, const double* y_a, const double* y_b, double rtol,
+                          double atol, double scale, double* err, void* work, size_t work_bytes, void* stream);
+
+typedef struct {
+    double t;        /* time reached: T, unless max_steps attempts ran out first */
+    double h_next;   /* the controller's proposal for the next macro step       */
+    int accepted;    /* accepted macro steps                                    */
+    int rejected;    /* rejected macro steps                                    */
+    int recorded;    /* entries written to `history`                            */
+} rok_adaptive_stats;
+
+/*
+ * Integrates y' = f(y) from 0 to T with rok_step under adaptive step-size
+ * control by step doubling (reading of Sec. 4.2).  Each macro step of size H
+ * takes one step of H (y_full) and two of H/2 (y_half) from the accepted
+ * state y_n; err = rok_error_norm(y_n, y_half, y_full; rtol, atol,
+ * scale = 2^order - 1).  err <= 1 accepts the step and the integration
+ * continues from y_half; the next H is H * min(fmax, max(0.2, 0.9 *
+ * err^(-1/(order+1)))) with fmax = 4, or 1 right after a rejection (a
+ * non-finite err rejects with factor 0.2).  The last macro step is shortened
+ * to end at T.  The control decisions are taken on the host: each macro step
+ * synchronises `stream` once to read err.
+ *   tab, M, mode: as rok_step (M = 0: the explicit Runge-Kutta method)
+ *   order:   1..16, the order p of the method (sets the error scale and the
+ *            controller's exponent)
+ *   T >= 0, H0 > 0: end time and first attempted macro step
+ *   rtol, atol: as rok_error_norm
+ *   max_steps: attempts (accepted + rejected) after which the call returns
+ *            with stats->t < T
+ *   y:       N doubles, device memory: y(0) on entry, y(stats->t) on return
+ *   stats:   host memory, written on success
+ *   history: host memory for history_cap entries of 4 doubles (t, H, err,
+ *            accepted ? 1 : 0), one per attempted macro step in order;
+ *            attempts beyond history_cap are not recorded (may be null when
+ *            history_cap = 0)
+ *   work:    rok_adaptive_workspace_bytes(ctx, M, tab->s) bytes, device
+ *            memory (a step workspace and three state vectors)
+ * Returns when the work is complete (the stream is synchronised).
+ */
+rok_status rok_integrate_adaptive(rok_ctx* ctx, const rok_tableau* tab, int M, int mode, int order, double T,
+                                  double H0, double rtol, double atol, int max_steps, double* y,
+                                  rok_adaptive_stats* stats, double* history, int history_cap, void* work,
+                                  size_t work_bytes, void* stream);
+
+/* Bytes of device workspace rok_integrate_adaptive needs (0 on invalid arguments). */
+size_t rok_adaptive_workspace_bytes(const rok_ctx* ctx, int M, int s);
+
+/*
  * Discrete adjoint of one ROK step (Sec. 2.2.2, eq. 9) taken with exact
  * (tangent) Jacobian-vector products:
  *   ybar_n = (d y_{n+1} / d y_n)^T ybar_np1

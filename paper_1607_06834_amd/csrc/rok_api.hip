@@ -336,6 +336,125 @@ rok_status rok_step(rok_ctx* c, const rok_tableau* tab, int M, int mode, double 
     return ROK_OK;
 }
 
+rok_status rok_error_norm(rok_ctx* c, const double* y_n, const double* y_a, const double* y_b, double rtol,
+                          double atol, double scale, double* err, void* work, size_t wbytes, void* stream) {
+    if (!c || !y_n || !y_a || !y_b || !err) return ROK_EINVAL;
+    if (!aligned(y_n, 8) || !aligned(y_a, 8) || !aligned(y_b, 8) || !aligned(err, 8)) return ROK_EINVAL;
+    if (!(rtol >= 0.0) || !(atol >= 0.0) || !(rtol + atol > 0.0) || !isfinite(rtol) || !isfinite(atol))
+        return ROK_EINVAL;
+    if (!(scale > 0.0) || !isfinite(scale)) return ROK_EINVAL;
+    size_t need = rok::work_bytes(c->G.N, 0, 0, false);
+    if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
+    rok::Work W = rok::carve(work, c->G.N, 0, 0, false);
+    ROK_TRY(rok::launch_error_norm(W, y_n, y_a, y_b, c->G.N, rtol, atol, scale, err, (hipStream_t)stream));
+    return ROK_OK;
+}
+
+namespace {
+constexpr double kAdaptSafety = 0.9, kAdaptFmin = 0.2, kAdaptFmax = 4.0;
+
+size_t al256h(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The controller's next macro step (safety * err^(-1/(p+1)), clamped).
+double adapt_next(double H, double err, int order, bool after_reject) {
+    const double fmax = after_reject ? 1.0 : kAdaptFmax;
+    double fac;
+    if (err == 0.0) {
+        fac = fmax;
+    } else {
+        fac = kAdaptSafety * pow(err, -1.0 / (double)(order + 1));
+        if (fac < kAdaptFmin) fac = kAdaptFmin;
+        if (fac > fmax) fac = fmax;
+    }
+    return H * fac;
+}
+}  // namespace
+
+size_t rok_adaptive_workspace_bytes(const rok_ctx* c, int M, int s) {
+    if (!c || M < 0 || s < 1 || s > ROK_MAX_STAGES) return 0;
+    int Mc = M > ROK_MAX_M ? ROK_MAX_M : M;
+    if ((long)Mc > c->G.N) Mc = (int)c->G.N;
+    return al256h(rok::work_bytes(c->G.N, Mc, s, true)) + 3 * al256h(sizeof(double) * (size_t)c->G.N) + 256;
+}
+
+rok_status rok_integrate_adaptive(rok_ctx* c, const rok_tableau* tab, int M, int mode, int order, double T, double H0,
+                                  double rtol, double atol, int max_steps, double* y, rok_adaptive_stats* stats,
+                                  double* history, int history_cap, void* work, size_t wbytes, void* stream) {
+    if (!c || !tab || !y || !stats || !aligned(y, 8)) return ROK_EINVAL;
+    if (tab->s < 1 || tab->s > ROK_MAX_STAGES) return ROK_EINVAL;
+    if (mode != ROK_JVP_FD && mode != ROK_JVP_TANGENT) return ROK_EINVAL;
+    if (M < 0 || M > ROK_MAX_M || order < 1 || order > 16 || max_steps < 0) return ROK_EINVAL;
+    if (!(T >= 0.0) || !isfinite(T) || !(H0 > 0.0) || !isfinite(H0)) return ROK_EINVAL;
+    if (!(rtol >= 0.0) || !(atol >= 0.0) || !(rtol + atol > 0.0) || !isfinite(rtol) || !isfinite(atol))
+        return ROK_EINVAL;
+    if (history_cap < 0 || (history_cap > 0 && !history)) return ROK_EINVAL;
+    if ((long)M > c->G.N) M = (int)c->G.N;
+    if (M > 0 && mode == ROK_JVP_FD && fp32(c)) return ROK_EUNSUPPORTED;
+    const long N = c->G.N;
+    const size_t step_b = al256h(rok::work_bytes(N, M, tab->s, true));
+    const size_t vec = al256h(sizeof(double) * (size_t)N);
+    if (!work || !aligned(work, 256) || wbytes < step_b + 3 * vec + 256) return ROK_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    char* p = (char*)work;
+    rok::Work W = rok::carve(p, N, M, tab->s, true);
+    double* buf[3] = {(double*)(p + step_b), (double*)(p + step_b + vec), (double*)(p + step_b + 2 * vec)};
+    double* err_dev = (double*)(p + step_b + 3 * vec);
+    // cur (the accepted state) and the three trial states always occupy four distinct buffers
+    double* cur = y;
+    double* y_full = buf[0];
+    double* y_mid = buf[1];
+    double* y_half = buf[2];
+    const double c_scale = (double)((1L << order) - 1);
+    double t = 0.0, H = H0;
+    bool after_reject = false;
+    int acc = 0, rej = 0, rec = 0;
+    for (int it = 0; it < max_steps; ++it) {
+        if (t >= T) break;
+        const bool last = t + H >= T;
+        if (last) H = T - t;
+        ROK_TRY(step_core(c, tab, M, mode, H, cur, y_full, W, st));
+        ROK_TRY(step_core(c, tab, M, mode, 0.5 * H, cur, y_mid, W, st));
+        ROK_TRY(step_core(c, tab, M, mode, 0.5 * H, y_mid, y_half, W, st));
+        ROK_TRY(rok::launch_error_norm(W, cur, y_half, y_full, N, rtol, atol, c_scale, err_dev, st));
+        double err = 0.0;
+        ROK_TRY(hipMemcpyAsync(&err, err_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+        ROK_TRY(hipStreamSynchronize(st));
+        if (!isfinite(err)) err = INFINITY;
+        const bool ok = err <= 1.0;
+        if (rec < history_cap) {
+            history[4 * rec + 0] = t;
+            history[4 * rec + 1] = H;
+            history[4 * rec + 2] = err;
+            history[4 * rec + 3] = ok ? 1.0 : 0.0;
+            ++rec;
+        }
+        double H_next;
+        if (ok) {
+            ++acc;
+            t = last ? T : t + H;
+            // the two-half-step result becomes the state; the old state's buffer takes its role
+            double* old = cur;
+            cur = y_half;
+            y_half = old;
+            H_next = adapt_next(H, err, order, after_reject);
+            after_reject = false;
+        } else {
+            ++rej;
+            H_next = isfinite(err) ? adapt_next(H, err, order, true) : H * kAdaptFmin;
+            after_reject = true;
+        }
+        H = H_next;
+    }
+    if (cur != y) ROK_TRY(hipMemcpyAsync(y, cur, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, st));
+    ROK_TRY(hipStreamSynchronize(st));
+    stats->t = t;
+    stats->h_next = H;
+    stats->accepted = acc;
+    stats->rejected = rej;
+    stats->recorded = rec;
+    return ROK_OK;
+}
+
 size_t rok_step_vjp_workspace_bytes(const rok_ctx* c, int M, int s) {
     if (!c || M < 0 || s < 1 || s > ROK_MAX_STAGES) return 0;
     int Mc = M > ROK_MAX_M ? ROK_MAX_M : M;

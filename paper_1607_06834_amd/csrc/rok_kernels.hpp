@@ -49,6 +49,9 @@ Work carve(void* base, long N, int M, int s, bool step);
 hipError_t launch_init(const Work& W, int M, int s, hipStream_t st);
 // scal[0] = ||y||, scal[1] = sqrt((1 + ||y||) u) / (v ? ||v|| : 1)  (scal[3] = ||v||)
 hipError_t launch_norm_eps(const Work& W, const double* y, const double* v, long n, hipStream_t st);
+// *out = sqrt(sum_i q_i^2 / n), q_i = (a_i - b_i) / (c (atol + rtol max(|y_i|, |a_i|)))
+hipError_t launch_error_norm(const Work& W, const double* y, const double* a, const double* b, long n, double rtol,
+                             double atol, double c, double* out, hipStream_t st);
 hipError_t launch_start_basis(const Work& W, const double* f, long n, double* v0, hipStream_t st);
 hipError_t launch_mgs_column(const Work& W, double* w, const double* V, long n, int M, int j, double* vnext,
                              hipStream_t st);

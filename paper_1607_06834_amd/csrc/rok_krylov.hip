@@ -474,6 +474,33 @@ static inline unsigned grid_for(long n, int threads) {
     return (unsigned)g;
 }
 
+// Weighted RMS norm of a step-doubling error estimate: lane sums of q_i^2 in
+// the canonical order, q_i = (a_i - b_i) / (c (atol + rtol max(|y_i|, |a_i|))).
+// The maximum propagates a NaN of either operand.
+__global__ __launch_bounds__(kRedThreads) void k_err_partials(const double* y, const double* a, const double* b,
+                                                             long n, double rtol, double atol, double c,
+                                                             double* partials) {
+    __shared__ double s[kRedThreads];
+    double acc = 0.0;
+    const long stride = (long)kRedBlocks * kRedThreads;
+    for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
+        const double ay = fabs(y[e]), aa = fabs(a[e]);
+        const double m = (ay != ay || ay > aa) ? ay : aa;
+        const double sc = atol + rtol * m;
+        const double q = (a[e] - b[e]) / (c * sc);
+        acc = acc + q * q;
+    }
+    double bs = block_sum(acc, s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// *out = sqrt(sum / n) from the partials.
+__global__ __launch_bounds__(kRedThreads) void k_err_finish(const double* partials, double n, double* out) {
+    __shared__ double s[kRedThreads];
+    double tot = final_sum(partials, s);
+    if (threadIdx.x == 0) *out = sqrt(tot / n);
+}
+
 #define ROK_RED(UPD, SELF, ...) \
     hipLaunchKernelGGL((k_red<UPD, SELF>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, __VA_ARGS__)
 
@@ -494,6 +521,14 @@ hipError_t launch_norm_eps(const Work& W, const double* y, const double* v, long
     ROK_RED(false, true, (double*)y, nullptr, nullptr, nullptr, nullptr, n, nullptr, mgs_part(W, 0));
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedThreads), 0, st, mgs_part(W, 0), (int)FIN_EPS, nullptr, W.scal,
                        W.ints, v ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_error_norm(const Work& W, const double* y, const double* a, const double* b, long n, double rtol,
+                             double atol, double c, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_err_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, st, y, a, b, n, rtol, atol, c,
+                       mgs_part(W, 0));
+    hipLaunchKernelGGL(k_err_finish, dim3(1), dim3(kRedThreads), 0, st, mgs_part(W, 0), (double)n, out);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ MAX_STAGES, MAX_M = 8, 64
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual",
            "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
            "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
-           "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
+           "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
 MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
@@ -42,6 +42,11 @@ class RokTableau(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int), ("alpha", ctypes.c_double * (MAX_STAGES * MAX_STAGES)),
                 ("gam", ctypes.c_double * (MAX_STAGES * MAX_STAGES)), ("gamma", ctypes.c_double),
                 ("b", ctypes.c_double * MAX_STAGES)]
+
+
+class RokAdaptiveStats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h_next", ctypes.c_double), ("accepted", ctypes.c_int),
+                ("rejected", ctypes.c_int), ("recorded", ctypes.c_int)]
 
 
 class RokError(RuntimeError):
@@ -90,6 +95,13 @@ def load_library(path: str = LIB_PATH):
     lib.rok_step_vjp_stored.restype = i
     lib.rok_step_vjp_adjoint_bytes.argtypes = [vp, i, i]
     lib.rok_step_vjp_adjoint_bytes.restype = sz
+    lib.rok_error_norm.argtypes = [vp, vp, vp, vp, d, d, d, vp, vp, sz, vp]
+    lib.rok_error_norm.restype = i
+    lib.rok_integrate_adaptive.argtypes = [vp, ctypes.POINTER(RokTableau), i, i, i, d, d, d, d, i, vp,
+                                           ctypes.POINTER(RokAdaptiveStats), ctypes.POINTER(d), i, vp, sz, vp]
+    lib.rok_integrate_adaptive.restype = i
+    lib.rok_adaptive_workspace_bytes.argtypes = [vp, i, i]
+    lib.rok_adaptive_workspace_bytes.restype = sz
     lib.rok_mgs_column.argtypes = [vp, vp, i, i, vp, vp, vp, vp, sz, vp]
     lib.rok_mgs_column.restype = i
     lib.rok_workspace_init.argtypes = [vp, vp, sz, i, i, vp]
@@ -179,16 +191,19 @@ class Rok:
     # -- workspace ---------------------------------------------------------
     def workspace(self, M: int, s: int, adjoint: bool | str = False) -> torch.Tensor:
         """Cached aligned workspace: rok_workspace_bytes (adjoint=False),
-        rok_step_vjp_workspace_bytes (True) or rok_step_vjp_adjoint_bytes ("only")."""
+        rok_step_vjp_workspace_bytes (True), rok_step_vjp_adjoint_bytes ("only")
+        or rok_adaptive_workspace_bytes ("adaptive")."""
         if adjoint == "only":
             nb = int(_lib.rok_step_vjp_adjoint_bytes(self._ctx, int(M), int(s)))
+        elif adjoint == "adaptive":
+            nb = int(_lib.rok_adaptive_workspace_bytes(self._ctx, int(M), int(s)))
         elif adjoint:
             nb = int(_lib.rok_step_vjp_workspace_bytes(self._ctx, int(M), int(s)))
         else:
             nb = int(_lib.rok_workspace_bytes(self._ctx, int(M), int(s)))
         if nb == 0:
             raise ValueError(f"invalid workspace request M={M}, s={s}")
-        key = (int(M), int(s), adjoint if adjoint == "only" else bool(adjoint))
+        key = (int(M), int(s), adjoint if isinstance(adjoint, str) else bool(adjoint))
         w = self._work.get(key)
         if w is None or w.numel() < nb:
             w = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
@@ -250,6 +265,45 @@ class Rok:
                              ws.numel(), _stream()), "rok_step")
         self._last_step_ws = ws
         return y1
+
+    def error_norm(self, y_n, y_a, y_b, rtol: float, atol: float, scale: float, out=None) -> torch.Tensor:
+        """sqrt(sum_i q_i^2 / N), q_i = (y_a - y_b)_i / (scale (atol + rtol max(|y_n|, |y_a|)_i)),
+        as a one-element device tensor."""
+        for t, nm in ((y_n, "y_n"), (y_a, "y_a"), (y_b, "y_b")):
+            self._vec(t, nm)
+        e = out if out is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        ws = self.workspace(0, 0)
+        _check(_lib.rok_error_norm(self._ctx, _ptr(y_n), _ptr(y_a), _ptr(y_b), float(rtol), float(atol),
+                                   float(scale), _ptr(e), _ptr(ws), ws.numel(), _stream()), "rok_error_norm")
+        return e
+
+    def integrate_adaptive(self, y0, T: float, H0: float, tableau: dict, M: int, mode: str = "fd", order: int = 4,
+                           rtol: float = 1e-6, atol: float = 1e-6, max_steps: int = 100000,
+                           history_cap: int = 4096):
+        """Integrate from y0 to T under step-doubling control (rok_integrate_adaptive).
+
+        Returns (y_T, record) with record = {"accepted": [(t, H, err)], "rejected": [(t, H, err)],
+        "t": time reached, "h_next": next proposed step}; raises if T was not reached.
+        """
+        self._vec(y0, "y0")
+        y = y0.clone()
+        tab = make_tableau(tableau)
+        ws = self.workspace(M, tab.s, adjoint="adaptive")
+        st = RokAdaptiveStats()
+        hist = (ctypes.c_double * (4 * max(1, history_cap)))()
+        m = JVP_FD if mode == "fd" else JVP_TANGENT
+        _check(_lib.rok_integrate_adaptive(self._ctx, ctypes.byref(tab), int(M), m, int(order), float(T), float(H0),
+                                           float(rtol), float(atol), int(max_steps), _ptr(y), ctypes.byref(st),
+                                           hist, int(history_cap), _ptr(ws), ws.numel(), _stream()),
+               "rok_integrate_adaptive")
+        rec = {"accepted": [], "rejected": [], "t": st.t, "h_next": st.h_next,
+               "n_accepted": st.accepted, "n_rejected": st.rejected}
+        for k in range(st.recorded):
+            e = (hist[4 * k], hist[4 * k + 1], hist[4 * k + 2])
+            rec["accepted" if hist[4 * k + 3] == 1.0 else "rejected"].append(e)
+        if st.t < T:
+            raise RokError(f"rok_integrate_adaptive stopped at t = {st.t} < T = {T} after {max_steps} attempts")
+        return y, rec
 
     def vjp(self, y, wbar, v=None, accumulate_into=None, accumulate_into2=None):
         """J(y)^T wbar; with v also d/dt [J(y + t v)^T wbar] (returned as a pair).
