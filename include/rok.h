@@ -262,7 +262,9 @@ typedef struct {
  *   T >= 0, H0 > 0: end time and first attempted macro step
  *   rtol, atol: as rok_error_norm
  *   max_steps: attempts (accepted + rejected) after which the call returns
- *            with stats->t < T
+ *            with stats->t < T; it also returns early, with stats->t < T,
+ *            when rejections have shrunk H until t + H == t (every attempt
+ *            failed, e.g. on a non-physical state)
  *   y:       N doubles, device memory: y(0) on entry, y(stats->t) on return
  *   stats:   host memory, written on success
  *   history: host memory for history_cap entries of 4 doubles (t, H, err,

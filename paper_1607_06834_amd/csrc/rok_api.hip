@@ -409,7 +409,7 @@ rok_status rok_integrate_adaptive(rok_ctx* c, const rok_tableau* tab, int M, int
     bool after_reject = false;
     int acc = 0, rej = 0, rec = 0;
     for (int it = 0; it < max_steps; ++it) {
-        if (t >= T) break;
+        if (t >= T || !(t + H > t)) break;   // done, or the step no longer advances t
         const bool last = t + H >= T;
         if (last) H = T - t;
         ROK_TRY(step_core(c, tab, M, mode, H, cur, y_full, W, st));

@@ -302,7 +302,9 @@ class Rok:
             e = (hist[4 * k], hist[4 * k + 1], hist[4 * k + 2])
             rec["accepted" if hist[4 * k + 3] == 1.0 else "rejected"].append(e)
         if st.t < T:
-            raise RokError(f"rok_integrate_adaptive stopped at t = {st.t} < T = {T} after {max_steps} attempts")
+            why = "max_steps attempts" if st.accepted + st.rejected >= max_steps else "step size underflow"
+            raise RokError(f"rok_integrate_adaptive stopped at t = {st.t} < T = {T} ({why}: "
+                           f"{st.accepted} accepted, {st.rejected} rejected)")
         return y, rec
 
     def vjp(self, y, wbar, v=None, accumulate_into=None, accumulate_into2=None):

@@ -132,3 +132,22 @@ def test_accepted_steps_cover_the_interval():
         assert t0 == t and err <= 1.0
         t = t0 + H
     assert abs(t - 0.3) < 1e-15 and all(e > 1.0 for _, _, e in rec["rejected"])
+
+
+def test_rok4_has_no_embedded_order3_weights():
+    """Why step doubling: the four order-3 conditions (the first four rows of
+    the ROK conditions) are linear in the weights; for the four-stage ROK4
+    tableau their matrix is nonsingular, so the only order-3 weights are b
+    itself and an embedded pair would estimate zero."""
+    tab = ri.rok4_tableau()
+    s = tab["s"]
+    al = np.array(tab["alpha"], dtype=np.float64).reshape(s, s)
+    ga = np.array(tab["gam"], dtype=np.float64).reshape(s, s)
+    g = float(tab["gamma"])
+    be = al + ga
+    a, bp = al.sum(axis=1), be.sum(axis=1)
+    A = np.stack([np.ones(s), bp, a ** 2, be @ bp])
+    rhs = np.array([1.0, 0.5 - g, 1.0 / 3.0, 1.0 / 6.0 - g + g * g])
+    assert np.linalg.cond(A) < 1e6
+    bhat = np.linalg.solve(A, rhs)
+    assert np.allclose(bhat, np.array(tab["b"], dtype=np.float64), rtol=0, atol=1e-12)
