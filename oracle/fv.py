@@ -18,7 +18,9 @@ the paper leaves open:
   q_L = q_i + mm(q_i - q_{i-1}, q_{i+1} - q_i)/2,
   q_R = q_{i+1} - mm(q_{i+1} - q_i, q_{i+2} - q_{i+1})/2,
   mm(a, b) = 0 if a*b <= 0, a if |a| <= |b|, else b;
-* Rusanov flux with wave speed a = max(|u_n,L| + c_L, |u_n,R| + c_R);
+* Rusanov flux with wave speed a = max(|u_n,L| + c_L, |u_n,R| + c_R), or
+  Roe's flux (the paper's solver offers Roe and Van Leer fluxes, Sec. 3.2)
+  with Harten's entropy fix on the acoustic waves (`_roe`);
 * viscous terms: Stokes hypothesis and q = -k grad T (eq. 11) with constant mu,
   k = mu*gamma/((gamma-1) Pr); the energy equation is read in its standard form
   dE/dt + div((E+p)u) = div(tau.u) - div(q) (the printed line repeats k and mu);
@@ -45,6 +47,8 @@ EULER = "euler"
 NS = "ns"
 FIRST_ORDER = "first"
 MUSCL = "muscl"
+RUSANOV = "rusanov"
+ROE = "roe"
 
 
 @dataclass
@@ -59,6 +63,7 @@ class Problem:
     gamma: float = 1.4
     mu: float = 0.0
     prandtl: float = 0.72
+    flux: str = RUSANOV
     dtype: torch.dtype = field(default=torch.float64)
 
     @property
@@ -170,6 +175,90 @@ def _rusanov(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, d):
     return [0.5 * (FL[m] + FR[m]) - 0.5 * a * (UR[m] - UL[m]) for m in range(P.nvar)]
 
 
+ROE_ENTROPY_FIX = 0.125
+
+
+def _roe(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, d):
+    """Roe's approximate Riemann flux (Roe 1981) along direction d:
+    Fhat = (F_L + F_R)/2 - (sum_k |lambda_k| alpha_k r_k)/2 with the
+    density-weighted averages, written in primitive differences.
+
+    Waves (n = e_d): lambda = u_n - c, u_n (entropy and D-1 shear waves),
+    u_n + c; strengths alpha_1,3 = (dp -+ rho c du_n)/(2 c^2),
+    alpha_2 = drho - dp/c^2, shear alpha_e = rho du_e (e != d); right
+    eigenvectors (1, u - c n, H - u_n c), (1, u, |u|^2/2), (0, e_e, u_e),
+    (1, u + c n, H + u_n c).  Harten's entropy fix on the two acoustic waves:
+    |lambda| < delta -> (lambda^2 + delta^2) / (2 delta), delta = c / 8.
+    """
+    D = P.ndim
+    gm1 = P.gamma - 1.0
+    FL = _euler_flux(P, UL, vL, pL, d)
+    FR = _euler_flux(P, UR, vR, pR, d)
+    sL = _sqrt(rL)
+    sR = _sqrt(rR)
+    den = sL + sR
+    wL = sL / den
+    wR = sR / den
+    u = [wL * vL[e] + wR * vR[e] for e in range(D)]
+    HL = (UL[D + 1] + pL) / rL
+    HR = (UR[D + 1] + pR) / rR
+    H = wL * HL + wR * HR
+    rho = sL * sR
+    ke = u[0] * u[0]
+    for e in range(1, D):
+        ke = ke + u[e] * u[e]
+    hke = 0.5 * ke
+    c2 = gm1 * (H - hke)
+    c = _sqrt(c2)
+    un = u[d]
+    dr = rR - rL
+    dp = pR - pL
+    dun = vR[d] - vL[d]
+    rc = rho * c
+    cc = c2 + c2
+    a1 = (dp - rc * dun) / cc
+    a3 = (dp + rc * dun) / cc
+    a2 = dr - dp / c2
+    delta = ROE_ENTROPY_FIX * c
+
+    def fixed(lam):
+        l = _absw(lam)
+        return torch.where(l < delta, (l * l + delta * delta) / (delta + delta), l)
+
+    l1 = fixed(un - c)
+    l2 = _absw(un)
+    l3 = fixed(un + c)
+    w1 = l1 * a1
+    w2 = l2 * a2
+    w3 = l3 * a3
+    wt = [None] * D
+    for e in range(D):
+        if e != d:
+            wt[e] = l2 * (rho * (vR[e] - vL[e]))
+    Dv = [w1 + w2 + w3]
+    for e in range(D):
+        if e == d:
+            Dv.append(w1 * (u[e] - c) + w2 * u[e] + w3 * (u[e] + c))
+        else:
+            Dv.append(w1 * u[e] + w2 * u[e] + w3 * u[e] + wt[e])
+    unc = un * c
+    en = w1 * (H - unc) + w2 * hke + w3 * (H + unc)
+    for e in range(D):
+        if e != d:
+            en = en + wt[e] * u[e]
+    Dv.append(en)
+    return [0.5 * (FL[m] + FR[m]) - 0.5 * Dv[m] for m in range(P.nvar)]
+
+
+def face_flux(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, d):
+    """The inviscid numerical flux selected by P.flux."""
+    if P.flux == RUSANOV:
+        return _rusanov(P, UL, rL, vL, pL, UR, rR, vR, pR, d)
+    if P.flux == ROE:
+        return _roe(P, UL, rL, vL, pL, UR, rR, vR, pR, d)
+    raise ValueError(f"unknown flux {P.flux!r}")
+
+
 def _face_states(P: Problem, U, r, vel, p, d):
     """Left/right states at the face c+1/2 along d, for every cell c."""
     D = P.ndim
@@ -235,7 +324,7 @@ def residual(P: Problem, y: torch.Tensor) -> torch.Tensor:
     out = None
     for d in range(P.ndim):
         (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, d)
-        Fh = _rusanov(P, UL, rL, vL, pL, UR, rR, vR, pR, d)
+        Fh = face_flux(P, UL, rL, vL, pL, UR, rR, vR, pR, d)
         if P.physics == NS:
             Fv = _viscous_flux(P, r, vel, p, d)
             Fh = [Fh[m] - Fv[m] for m in range(P.nvar)]

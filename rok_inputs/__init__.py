@@ -28,11 +28,11 @@ GAMMA = 1.4
 PERTURB_SEED = 20160726
 
 
-def problem(n, lo, hi, physics="euler", recon="first", gamma=GAMMA, mu=0.0, prandtl=0.72):
+def problem(n, lo, hi, physics="euler", recon="first", gamma=GAMMA, mu=0.0, prandtl=0.72, flux="rusanov"):
     """Plain description of f: grid, physics and discretisation."""
     return {"n": tuple(int(x) for x in n), "lo": tuple(float(x) for x in lo),
             "hi": tuple(float(x) for x in hi), "physics": physics, "recon": recon,
-            "gamma": float(gamma), "mu": float(mu), "prandtl": float(prandtl)}
+            "gamma": float(gamma), "mu": float(mu), "prandtl": float(prandtl), "flux": flux}
 
 
 def size(pb) -> int:

@@ -7,7 +7,8 @@ from oracle import fv
 
 def oracle_problem(pb):
     return fv.Problem(n=tuple(pb["n"]), lo=tuple(pb["lo"]), hi=tuple(pb["hi"]), physics=pb["physics"],
-                      recon=pb["recon"], gamma=pb["gamma"], mu=pb["mu"], prandtl=pb["prandtl"])
+                      recon=pb["recon"], gamma=pb["gamma"], mu=pb["mu"], prandtl=pb["prandtl"],
+                      flux=pb.get("flux", "rusanov"))
 
 
 def t64(a):
