@@ -52,7 +52,7 @@ enum {
 
 enum { ROK_EULER = 0, ROK_NS = 1 };                  /* physics                     */
 enum { ROK_FIRST_ORDER = 0, ROK_MUSCL_MINMOD = 1 };  /* reconstruction              */
-enum { ROK_RUSANOV = 0 };                            /* inviscid flux               */
+enum { ROK_RUSANOV = 0, ROK_ROE = 1 };               /* inviscid flux               */
 enum { ROK_FP64 = 0, ROK_FP32_RESIDUAL = 1 };        /* precision of f and J v      */
 enum { ROK_JVP_FD = 0, ROK_JVP_TANGENT = 1 };        /* Jacobian-vector product     */
 
@@ -76,7 +76,10 @@ enum { ROK_MGS_AUTO = 0, ROK_MGS_PER_PASS = 1, ROK_MGS_RESIDENT = 2 };
  * Sec. 3.2, eq. (11), finite volumes on a periodic cell-centred Cartesian
  * box [lo, hi] with n cells per direction (ndim = 2: n[2] and lo/hi[2] are
  * ignored), first-order or MUSCL (minmod limiter, primitive variables)
- * reconstruction, Rusanov flux, constant viscosity mu, Prandtl number
+ * reconstruction, Rusanov or Roe flux (ROK_ROE: Roe's linearisation with
+ * density-weighted averages and Harten's entropy fix, half-width c/8, on the
+ * acoustic waves; the paper's residual offers Roe and Van Leer fluxes,
+ * Sec. 3.2), constant viscosity mu, Prandtl number
  * `prandtl`, ratio of specific heats `gamma`.  With precision =
  * ROK_FP32_RESIDUAL the residual and tangent kernels compute in float while
  * Arnoldi, the reduced solve and all state accumulation stay in double.
@@ -302,7 +305,8 @@ size_t rok_adaptive_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *   y_n, ybar_np1, ybar_n, y_np1: N doubles each, device memory; ybar_n and
  *               y_np1 may not alias any other argument
  *   work:       rok_step_vjp_workspace_bytes(ctx, M, tab->s) bytes
- * Euler physics and FP64 precision only (ROK_EUNSUPPORTED otherwise).
+ * Euler physics, Rusanov flux and FP64 precision only (ROK_EUNSUPPORTED
+ * otherwise).
  */
 rok_status rok_step_vjp(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
                         const double* ybar_np1, double* ybar_n, double* y_np1, void* work, size_t work_bytes,
@@ -327,7 +331,7 @@ size_t rok_step_vjp_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *           vector, exchange and status words), so a forward may be reversed
  *           several times
  *   adj_work: rok_step_vjp_adjoint_bytes(ctx, M, tab->s) bytes, device memory
- * Results are bitwise those of rok_step_vjp.  Euler physics and FP64
+ * Results are bitwise those of rok_step_vjp.  Euler physics, Rusanov flux and FP64
  * precision only (ROK_EUNSUPPORTED otherwise).
  */
 rok_status rok_step_vjp_stored(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
@@ -341,8 +345,8 @@ size_t rok_step_vjp_adjoint_bytes(const rok_ctx* ctx, int M, int s);
  * Adjoint product of the residual (transposed Jacobian, Sec. 2.3 / eq. 11):
  *   ybar = J(y)^T wbar          (accumulate = 0)
  *   ybar = ybar + J(y)^T wbar   (accumulate = 1)
- * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  Euler physics and
- * FP64 precision only (ROK_EUNSUPPORTED otherwise).  Deterministic: each cell
+ * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  Euler physics,
+ * Rusanov flux and FP64 precision only (ROK_EUNSUPPORTED otherwise).  Deterministic: each cell
  * gathers its own contributions.
  */
 rok_status rok_residual_vjp(rok_ctx* ctx, const double* y, const double* wbar, double* ybar, int accumulate,

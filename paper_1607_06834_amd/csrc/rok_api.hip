@@ -35,6 +35,11 @@ rok_status hip_status(hipError_t e) {
 
 bool fp32(const rok_ctx* c) { return c->pb.precision == ROK_FP32_RESIDUAL; }
 
+// The adjoint kernels cover Euler physics with Rusanov's flux in FP64.
+bool adjoint_supported(const rok_ctx* c) {
+    return c->pb.physics == ROK_EULER && c->pb.flux == ROK_RUSANOV && !fp32(c);
+}
+
 rok::ResArgs plain_args(const double* y, void* out) {
     rok::ResArgs A{};
     A.y = y;
@@ -219,7 +224,7 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
     }
     if (p->physics != ROK_EULER && p->physics != ROK_NS) return ROK_EINVAL;
     if (p->recon != ROK_FIRST_ORDER && p->recon != ROK_MUSCL_MINMOD) return ROK_EINVAL;
-    if (p->flux != ROK_RUSANOV) return ROK_EINVAL;
+    if (p->flux != ROK_RUSANOV && p->flux != ROK_ROE) return ROK_EINVAL;
     if (p->precision != ROK_FP64 && p->precision != ROK_FP32_RESIDUAL) return ROK_EINVAL;
     if (!(p->gamma > 1.0) || !(p->mu >= 0.0) || !(p->prandtl > 0.0)) return ROK_EINVAL;
     rok_ctx* c = new (std::nothrow) rok_ctx;
@@ -243,6 +248,7 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
     G.mu = p->physics == ROK_NS ? p->mu : 0.0;
     G.c23mu = (2.0 / 3.0) * G.mu;
     G.kappa = G.mu * p->gamma / ((p->gamma - 1.0) * p->prandtl);
+    G.flux = p->flux;
     *out = c;
     return ROK_OK;
 }
@@ -472,7 +478,7 @@ rok_status rok_step_vjp(rok_ctx* c, const rok_tableau* tab, int M, double h, con
         return ROK_EINVAL;
     if (tab->s < 1 || tab->s > ROK_MAX_STAGES) return ROK_EINVAL;
     if (M < 0 || M > ROK_MAX_M || !(h == h)) return ROK_EINVAL;
-    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    if (!adjoint_supported(c)) return ROK_EUNSUPPORTED;
     if ((long)M > c->G.N) M = (int)c->G.N;
     const int s = tab->s;
     const long N = c->G.N;
@@ -501,7 +507,7 @@ rok_status rok_step_vjp_stored(rok_ctx* c, const rok_tableau* tab, int M, double
     if (ybar_n == y_n || ybar_n == ybar_np1) return ROK_EINVAL;
     if (tab->s < 1 || tab->s > ROK_MAX_STAGES) return ROK_EINVAL;
     if (M < 0 || M > ROK_MAX_M || !(h == h)) return ROK_EINVAL;
-    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    if (!adjoint_supported(c)) return ROK_EUNSUPPORTED;
     if ((long)M > c->G.N) M = (int)c->G.N;
     const int s = tab->s;
     const long N = c->G.N;
@@ -549,7 +555,7 @@ rok_status rok_residual_vjp(rok_ctx* c, const double* y, const double* wbar, dou
                             void* stream) {
     if (!c || !y || !wbar || !ybar || !aligned(y, 8) || !aligned(wbar, 8) || !aligned(ybar, 8)) return ROK_EINVAL;
     if (ybar == y || ybar == wbar) return ROK_EINVAL;
-    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    if (!adjoint_supported(c)) return ROK_EUNSUPPORTED;
     ROK_TRY(rok::launch_vjp(c->G, c->pb.recon, y, nullptr, wbar, ybar, nullptr, accumulate ? 1 : 0,
                             (hipStream_t)stream));
     return ROK_OK;
@@ -562,7 +568,7 @@ rok_status rok_residual_vjp2(rok_ctx* c, const double* y, const double* v, const
         return ROK_EINVAL;
     if (ybar == ybar2 || ybar == y || ybar == wbar || ybar == v || ybar2 == y || ybar2 == wbar || ybar2 == v)
         return ROK_EINVAL;
-    if (c->pb.physics != ROK_EULER || fp32(c)) return ROK_EUNSUPPORTED;
+    if (!adjoint_supported(c)) return ROK_EUNSUPPORTED;
     ROK_TRY(rok::launch_vjp(c->G, c->pb.recon, y, v, wbar, ybar, ybar2, accumulate ? 1 : 0, (hipStream_t)stream));
     return ROK_OK;
 }

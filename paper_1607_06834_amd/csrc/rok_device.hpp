@@ -29,6 +29,7 @@ struct Geom {
     double hinv[3];   // 0.5 / dx (central differences)
     double g, gm1;    // gamma, gamma - 1
     double mu, c23mu, kappa;  // mu, (2/3) mu, mu gamma / ((gamma-1) Pr)
+    int flux;                 // inviscid flux: 0 Rusanov, 1 Roe
 };
 
 // Residual-kernel inputs: the stage state Y = y + sum_t cs[t] xs[t]

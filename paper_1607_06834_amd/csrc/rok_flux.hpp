@@ -1,7 +1,7 @@
 // Pointwise pieces of the finite-volume right-hand side f (Sec. 3.2, eq. 11),
 // templated on the scalar type (double, float, or dual numbers for exact
 // derivatives): |.| and minmod with the branch rules of the reconstruction,
-// the physical Euler flux, Rusanov's flux, primitive <-> conserved variables
+// the physical Euler flux, Rusanov's and Roe's fluxes, primitive <-> conserved variables
 // and the flux of one face from the conserved states of its stencil cells.
 // Every formula keeps one fixed, left-to-right operation order.
 #pragma once
@@ -44,6 +44,99 @@ __device__ __forceinline__ void rusanov(const Geom& G, int d, const S* UL, S rL,
     S ha = half * a;
 #pragma unroll
     for (int m = 0; m < D + 2; ++m) Fh[m] = half * (FL[m] + FR[m]) - ha * (UR[m] - UL[m]);
+}
+
+// Roe's approximate Riemann flux along d (Roe 1981): the central flux minus
+// half the sum over waves of |lambda_k| alpha_k r_k, with density-weighted
+// averages of the two states.  Waves: u_n - c, u_n (entropy and D-1 shear
+// waves), u_n + c; strengths alpha_1,3 = (dp -+ rho c du_n) / (2 c^2),
+// alpha_2 = drho - dp / c^2, shear alpha_e = rho du_e; eigenvectors
+// (1, u - c n, H - u_n c), (1, u, |u|^2 / 2), (0, e_e, u_e),
+// (1, u + c n, H + u_n c).  Harten's entropy fix on the acoustic waves:
+// |lambda| < delta -> (lambda^2 + delta^2) / (2 delta), delta = c / 8.
+constexpr double kRoeFix = 0.125;
+
+template <typename S>
+__device__ __forceinline__ S roe_fixed(S lam, S delta) {
+    S l = sabs(lam);
+    if (Sc<S>::val(l) < Sc<S>::val(delta)) l = (l * l + delta * delta) / (delta + delta);
+    return l;
+}
+
+// The dissipation vector sum_k |lambda_k| alpha_k r_k from the averaged state
+// (u, H, rho, c2) and the primitive jumps (dr, du, dp) across the face.
+template <int D, typename S>
+__device__ __forceinline__ void roe_dissipation(const Geom& G, int d, const S* u, S H, S rho, S ke, S dr,
+                                                const S* du, S dp, S* Dv) {
+    using R = typename Sc<S>::R;
+    const R gm1 = (R)G.gm1, half = (R)0.5;
+    const S hke = half * ke;
+    const S c2 = gm1 * (H - hke);
+    const S c = Sc<S>::sqrt_(c2);
+    const S un = u[d];
+    const S rc = rho * c;
+    const S cc = c2 + c2;
+    const S a1 = (dp - rc * du[d]) / cc;
+    const S a3 = (dp + rc * du[d]) / cc;
+    const S a2 = dr - dp / c2;
+    const S delta = (R)kRoeFix * c;
+    const S l1 = roe_fixed(un - c, delta);
+    const S l2 = sabs(un);
+    const S l3 = roe_fixed(un + c, delta);
+    const S w1 = l1 * a1, w2 = l2 * a2, w3 = l3 * a3;
+    S wt[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) wt[e] = (e != d) ? l2 * (rho * du[e]) : Sc<S>::make(0.0);
+    Dv[0] = w1 + w2 + w3;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        if (e == d) Dv[1 + e] = w1 * (u[e] - c) + w2 * u[e] + w3 * (u[e] + c);
+        else Dv[1 + e] = w1 * u[e] + w2 * u[e] + w3 * u[e] + wt[e];
+    }
+    const S unc = un * c;
+    S en = w1 * (H - unc) + w2 * hke + w3 * (H + unc);
+#pragma unroll
+    for (int e = 0; e < D; ++e)
+        if (e != d) en = en + wt[e] * u[e];
+    Dv[D + 1] = en;
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void roe(const Geom& G, int d, const S* UL, S rL, const S* vL, S pL, const S* UR, S rR,
+                                    const S* vR, S pR, S* Fh) {
+    using R = typename Sc<S>::R;
+    const R half = (R)0.5;
+    S FL[D + 2], FR[D + 2];
+    euler_flux<D>(UL, vL, pL, d, FL);
+    euler_flux<D>(UR, vR, pR, d, FR);
+    const S sL = Sc<S>::sqrt_(rL), sR = Sc<S>::sqrt_(rR);
+    const S den = sL + sR;
+    const S wL = sL / den, wR = sR / den;
+    S u[D], du[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        u[e] = wL * vL[e] + wR * vR[e];
+        du[e] = vR[e] - vL[e];
+    }
+    const S HL = (UL[D + 1] + pL) / rL;
+    const S HR = (UR[D + 1] + pR) / rR;
+    const S H = wL * HL + wR * HR;
+    const S rho = sL * sR;
+    S ke = u[0] * u[0];
+#pragma unroll
+    for (int e = 1; e < D; ++e) ke = ke + u[e] * u[e];
+    S Dv[D + 2];
+    roe_dissipation<D>(G, d, u, H, rho, ke, rR - rL, du, pR - pL, Dv);
+#pragma unroll
+    for (int m = 0; m < D + 2; ++m) Fh[m] = half * (FL[m] + FR[m]) - half * Dv[m];
+}
+
+// The inviscid numerical flux selected at compile time (ROK_RUSANOV = 0, ROK_ROE = 1).
+template <int D, int FLUX, typename S>
+__device__ __forceinline__ void num_flux(const Geom& G, int d, const S* UL, S rL, const S* vL, S pL, const S* UR,
+                                         S rR, const S* vR, S pR, S* Fh) {
+    if constexpr (FLUX == 0) rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+    else roe<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
 }
 
 template <int D, typename S>
@@ -407,6 +500,74 @@ __device__ __forceinline__ void rusanov_ref(const Geom& G, const RefState<D, typ
     const S ha = half * a;
 #pragma unroll
     for (int m = 0; m < NV; ++m) Fh[m] = half * (F[0][m] + F[1][m]) - ha * (Up[1][m] - Up[0][m]);
+}
+
+// Roe flux minus F(q0) at a face in the reference-state form: the central part
+// from the flux perturbations (as in rusanov_ref), the dissipation from the
+// full averaged state and the jumps of the primitive perturbations (which are
+// the jumps of the primitives themselves).
+template <int D, typename S>
+__device__ __forceinline__ void roe_ref(const Geom& G, const RefState<D, typename Sc<S>::R>& Q, int d, const S* qL,
+                                        const S* qR, S* Fh) {
+    using R = typename Sc<S>::R;
+    const R gm1 = (R)G.gm1, half = (R)0.5;
+    constexpr int NV = D + 2;
+    S F[2][NV], Hs[2], rs[2], sq[2], us[2][D];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const S* q = side ? qR : qL;
+        const S rp = q[0], pp = q[D + 1];
+        const S r = Q.r0 + rp;
+        S u[D], mp[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            u[e] = Q.u0[e] + q[1 + e];
+            mp[e] = Q.r0 * q[1 + e] + rp * u[e];
+        }
+        S uu = u[0] * u[0], ku = q[1] * (u[0] + Q.u0[0]);
+#pragma unroll
+        for (int e = 1; e < D; ++e) {
+            uu = uu + u[e] * u[e];
+            ku = ku + q[1 + e] * (u[e] + Q.u0[e]);
+        }
+        const S Ep = pp / gm1 + half * (rp * uu + Q.r0 * ku);
+        const S Hp = Ep + pp;
+        F[side][0] = mp[d];
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+            F[side][1 + e] = (e == d) ? mp[d] * u[e] + Q.m0[d] * q[1 + e] + pp : mp[d] * u[e] + Q.m0[d] * q[1 + e];
+        F[side][D + 1] = Hp * u[d] + Q.H0 * q[1 + d];
+        rs[side] = r;
+        sq[side] = Sc<S>::sqrt_(r);
+        Hs[side] = (Q.H0 + Hp) / r;          // (E + p) / rho
+#pragma unroll
+        for (int e = 0; e < D; ++e) us[side][e] = u[e];
+    }
+    const S den = sq[0] + sq[1];
+    const S wL = sq[0] / den, wR = sq[1] / den;
+    S u[D], du[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        u[e] = wL * us[0][e] + wR * us[1][e];
+        du[e] = qR[1 + e] - qL[1 + e];
+    }
+    const S H = wL * Hs[0] + wR * Hs[1];
+    const S rho = sq[0] * sq[1];
+    S ke = u[0] * u[0];
+#pragma unroll
+    for (int e = 1; e < D; ++e) ke = ke + u[e] * u[e];
+    S Dv[NV];
+    roe_dissipation<D>(G, d, u, H, rho, ke, qR[0] - qL[0], du, qR[D + 1] - qL[D + 1], Dv);
+    (void)rs;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) Fh[m] = half * (F[0][m] + F[1][m]) - half * Dv[m];
+}
+
+template <int D, int FLUX, typename S>
+__device__ __forceinline__ void num_flux_ref(const Geom& G, const RefState<D, typename Sc<S>::R>& Q, int d,
+                                             const S* qL, const S* qR, S* Fh) {
+    if constexpr (FLUX == 0) rusanov_ref<D>(G, Q, d, qL, qR, Fh);
+    else roe_ref<D>(G, Q, d, qL, qR, Fh);
 }
 
 }  // namespace rok

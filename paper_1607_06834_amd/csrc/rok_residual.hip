@@ -3,7 +3,7 @@
 //
 // f is the semi-discrete compressible Euler / Navier-Stokes operator of
 // Sec. 3.2, eq. (11) on a periodic Cartesian grid: primitive variables per
-// cell, first-order or MUSCL-minmod face states, Rusanov flux, central
+// cell, first-order or MUSCL-minmod face states, Rusanov or Roe flux, central
 // viscous fluxes (Stokes stress, Fourier conduction), and the assembly
 // f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d.
 //
@@ -115,7 +115,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
+template <int D, int RECON, bool NSV, int FLUX, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt0, int nt1) {
     using T = Tile<D, TX, TY, TZ, (RECON == 0 ? 1 : 2)>;
     using R = typename Sc<S>::R;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     static_assert(T::CELLS % kThreads == 0, "tile must be a multiple of the block size");
     using ST = Stage<D, TX, TY, TZ, T::H, NSV>;
     const auto& cells = kStageCells<D, TX, TY, TZ, T::H, NSV>;
-    constexpr int kFaceUnroll = (D == 2 && sizeof(S) == 8 && !PERT) ? 2 : 1;
+    constexpr int kFaceUnroll = (D == 2 && sizeof(S) == 8 && !PERT && FLUX == 0) ? 2 : 1;
 
     __shared__ S sq[NP][T::BOX];
     __shared__ S fb[NV][T::NFMAX];
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                         qR[k] = ap1 - half * minmod(ap1 - a0, ap2 - ap1);
                     }
                 }
-                rusanov_ref<D>(G, s_ref, d, qL, qR, Fh);
+                num_flux_ref<D, FLUX>(G, s_ref, d, qL, qR, Fh);
             } else if constexpr (FO) {
 #pragma unroll
                 for (int m = 0; m < NV; ++m) { UL[m] = sq[m][ca]; UR[m] = sq[m][cb]; }
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 to_conserved<D>(G, rL, vL, pL, UL);
                 to_conserved<D>(G, rR, vR, pR, UR);
             }
-            if constexpr (!PERT) rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+            if constexpr (!PERT) num_flux<D, FLUX>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
             if constexpr (NSV) {
                 const R half = (R)0.5;
                 const R mu = (R)G.mu, c23mu = (R)G.c23mu, kappa = (R)G.kappa;
@@ -420,60 +420,66 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 // Launchers
 // ---------------------------------------------------------------------------
 
-template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
+template <int D, int RECON, bool NSV, int FLUX, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
 static hipError_t launch_t(const Geom& G, const ResArgs& A, hipStream_t st) {
     int nt0 = (G.n[0] + TX - 1) / TX;
     int nt1 = (G.n[1] + TY - 1) / TY;
     int nt2 = (D == 3) ? (G.n[2] + TZ - 1) / TZ : 1;
     long nb = (long)nt0 * nt1 * nt2;
     if (nb <= 0 || nb > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_residual<D, RECON, NSV, S, MODE, OUT, TX, TY, TZ>), dim3((unsigned)nb), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((k_residual<D, RECON, NSV, FLUX, S, MODE, OUT, TX, TY, TZ>), dim3((unsigned)nb), dim3(kThreads), 0, st,
                        G, A, nt0, nt1);
     return hipGetLastError();
 }
 
 // Tile shape per variant: bigger tiles where the LDS footprint allows.
-template <int D, int RECON, bool NSV, typename S, int MODE, typename OUT>
+template <int D, int RECON, bool NSV, int FLUX, typename S, int MODE, typename OUT>
 static hipError_t launch_v(const Geom& G, const ResArgs& A, hipStream_t st) {
     constexpr bool wide = sizeof(S) <= 8;   // double or float (not a dual number)
     if constexpr (D == 2) {
         if constexpr (RECON == 1 && sizeof(S) == 8 && sizeof(typename Sc<S>::R) == 8)
-            return launch_t<D, RECON, NSV, S, MODE, OUT, 16, 16, 1>(G, A, st);   // FP64 (measured best)
-        else if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 16, 1>(G, A, st);
-        else return launch_t<D, RECON, NSV, S, MODE, OUT, 32, 8, 1>(G, A, st);
+            return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 16, 16, 1>(G, A, st);   // FP64 (measured best)
+        else if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 32, 16, 1>(G, A, st);
+        else return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 32, 8, 1>(G, A, st);
     } else {
-        return launch_t<D, RECON, NSV, S, MODE, OUT, 16, 4, 4>(G, A, st);
+        return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 16, 4, 4>(G, A, st);
     }
 }
 
-template <int D, int RECON, bool NSV>
+template <int D, int RECON, bool NSV, int FLUX>
 static hipError_t dispatch_prec(const Geom& G, const ResArgs& A, int kind, bool fp32, bool out_double, hipStream_t st) {
     if (!fp32) {
-        if (kind == MODE_PLAIN) return launch_v<D, RECON, NSV, double, MODE_PLAIN, double>(G, A, st);
-        if (kind == MODE_FD) return launch_v<D, RECON, NSV, double, MODE_FD, double>(G, A, st);
-        return launch_v<D, RECON, NSV, Dual<double>, MODE_TAN, double>(G, A, st);
+        if (kind == MODE_PLAIN) return launch_v<D, RECON, NSV, FLUX, double, MODE_PLAIN, double>(G, A, st);
+        if (kind == MODE_FD) return launch_v<D, RECON, NSV, FLUX, double, MODE_FD, double>(G, A, st);
+        return launch_v<D, RECON, NSV, FLUX, Dual<double>, MODE_TAN, double>(G, A, st);
     }
     if (kind == MODE_FD) return hipErrorNotSupported;
     if (kind == MODE_PLAIN) {
-        if (out_double) return launch_v<D, RECON, NSV, float, MODE_PLAIN, double>(G, A, st);
-        return launch_v<D, RECON, NSV, float, MODE_PLAIN, float>(G, A, st);
+        if (out_double) return launch_v<D, RECON, NSV, FLUX, float, MODE_PLAIN, double>(G, A, st);
+        return launch_v<D, RECON, NSV, FLUX, float, MODE_PLAIN, float>(G, A, st);
     }
-    if (out_double) return launch_v<D, RECON, NSV, Dual<float>, MODE_TAN, double>(G, A, st);
-    return launch_v<D, RECON, NSV, Dual<float>, MODE_TAN, float>(G, A, st);
+    if (out_double) return launch_v<D, RECON, NSV, FLUX, Dual<float>, MODE_TAN, double>(G, A, st);
+    return launch_v<D, RECON, NSV, FLUX, Dual<float>, MODE_TAN, float>(G, A, st);
+}
+
+template <int D, int RECON, bool NSV>
+static hipError_t dispatch_flux(const Geom& G, const ResArgs& A, int kind, bool fp32, bool out_double, hipStream_t st) {
+    if (G.flux == 1) return dispatch_prec<D, RECON, NSV, 1>(G, A, kind, fp32, out_double, st);
+    return dispatch_prec<D, RECON, NSV, 0>(G, A, kind, fp32, out_double, st);
 }
 
 hipError_t launch_residual(const Geom& G, int recon, bool ns, bool fp32, int kind, bool out_double,
                            const ResArgs& A, hipStream_t st) {
     if (G.D == 2) {
-        if (recon == 0) return ns ? dispatch_prec<2, 0, true>(G, A, kind, fp32, out_double, st)
-                                  : dispatch_prec<2, 0, false>(G, A, kind, fp32, out_double, st);
-        return ns ? dispatch_prec<2, 1, true>(G, A, kind, fp32, out_double, st)
-                  : dispatch_prec<2, 1, false>(G, A, kind, fp32, out_double, st);
+        if (recon == 0) return ns ? dispatch_flux<2, 0, true>(G, A, kind, fp32, out_double, st)
+                                  : dispatch_flux<2, 0, false>(G, A, kind, fp32, out_double, st);
+        return ns ? dispatch_flux<2, 1, true>(G, A, kind, fp32, out_double, st)
+                  : dispatch_flux<2, 1, false>(G, A, kind, fp32, out_double, st);
     }
-    if (recon == 0) return ns ? dispatch_prec<3, 0, true>(G, A, kind, fp32, out_double, st)
-                              : dispatch_prec<3, 0, false>(G, A, kind, fp32, out_double, st);
-    return ns ? dispatch_prec<3, 1, true>(G, A, kind, fp32, out_double, st)
-              : dispatch_prec<3, 1, false>(G, A, kind, fp32, out_double, st);
+    if (recon == 0) return ns ? dispatch_flux<3, 0, true>(G, A, kind, fp32, out_double, st)
+                              : dispatch_flux<3, 0, false>(G, A, kind, fp32, out_double, st);
+    return ns ? dispatch_flux<3, 1, true>(G, A, kind, fp32, out_double, st)
+              : dispatch_flux<3, 1, false>(G, A, kind, fp32, out_double, st);
 }
 
 }  // namespace rok

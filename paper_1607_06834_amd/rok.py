@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librok.so")
 ROK_OK, ROK_EINVAL, ROK_EUNSUPPORTED, ROK_EHIP = 0, -1, -2, -3
 EULER, NS = 0, 1
 FIRST_ORDER, MUSCL_MINMOD = 0, 1
-RUSANOV = 0
+RUSANOV, ROE = 0, 1
 FP64, FP32_RESIDUAL = 0, 1
 JVP_FD, JVP_TANGENT = 0, 1
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER = 1, 2, 4, 8
@@ -170,7 +170,7 @@ class Rok:
             p.hi[d] = float(problem["hi"][d]) if d < D else 1.0
         p.physics = NS if problem["physics"] == "ns" else EULER
         p.recon = MUSCL_MINMOD if problem["recon"] == "muscl" else FIRST_ORDER
-        p.flux = RUSANOV
+        p.flux = {"rusanov": RUSANOV, "roe": ROE}[problem.get("flux", "rusanov")]
         p.gamma = float(problem["gamma"])
         p.mu = float(problem.get("mu", 0.0))
         p.prandtl = float(problem.get("prandtl", 0.72))
