@@ -22,6 +22,8 @@ the paper leaves open:
   Roe's flux (the paper's solver offers Roe and Van Leer fluxes, Sec. 3.2)
   with Harten's entropy fix on the acoustic waves (`_roe`);
 * viscous terms: Stokes hypothesis and q = -k grad T (eq. 11) with constant mu,
+  or Sutherland's law evaluated at the face temperature (T_a + T_b)/2 (the
+  paper's cylinder cases set Sutherland's coefficient, Sec. 4.2),
   k = mu*gamma/((gamma-1) Pr); the energy equation is read in its standard form
   dE/dt + div((E+p)u) = div(tau.u) - div(q) (the printed line repeats k and mu);
   face gradients: two-point difference along the face normal, the average of
@@ -64,6 +66,8 @@ class Problem:
     mu: float = 0.0
     prandtl: float = 0.72
     flux: str = RUSANOV
+    sutherland: float = 0.0   # S / T_ref of Sutherland's law; 0: constant viscosity mu
+    t_ref: float = 1.0        # temperature at which the viscosity is mu
     dtype: torch.dtype = field(default=torch.float64)
 
     @property
@@ -279,13 +283,24 @@ def _face_states(P: Problem, U, r, vel, p, d):
     return (conserved(P, rL, vL, pL), rL, vL, pL), (conserved(P, rR, vR, pR), rR, vR, pR)
 
 
+def sutherland_mu(P: Problem, T):
+    """Sutherland's law mu(T) = mu (T/T_ref)^(3/2) (T_ref + S) / (T + S), written
+    with theta = T / T_ref and s = S / T_ref as mu theta sqrt(theta) (1 + s) / (theta + s)."""
+    s = P.sutherland
+    th = T / P.t_ref
+    return P.mu * th * _sqrt(th) * (1.0 + s) / (th + s)
+
+
 def _viscous_flux(P: Problem, r, vel, p, d):
     """Viscous flux (tau row and energy term) at the face c+1/2 along d."""
     D = P.ndim
-    mu = P.mu
+    T = p / r
+    if P.sutherland > 0.0:
+        mu = sutherland_mu(P, 0.5 * (T + _at(T, 1, d)))   # at the face temperature
+    else:
+        mu = P.mu
     c23mu = (2.0 / 3.0) * mu
     kappa = mu * P.gamma / ((P.gamma - 1.0) * P.prandtl)
-    T = p / r
     inv = [P.invdx(b) for b in range(D)]
 
     def grad(a, b):

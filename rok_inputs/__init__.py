@@ -28,11 +28,14 @@ GAMMA = 1.4
 PERTURB_SEED = 20160726
 
 
-def problem(n, lo, hi, physics="euler", recon="first", gamma=GAMMA, mu=0.0, prandtl=0.72, flux="rusanov"):
-    """Plain description of f: grid, physics and discretisation."""
+def problem(n, lo, hi, physics="euler", recon="first", gamma=GAMMA, mu=0.0, prandtl=0.72, flux="rusanov",
+            sutherland=0.0, t_ref=1.0):
+    """Plain description of f: grid, physics and discretisation (sutherland = S / T_ref,
+    0 for a constant viscosity)."""
     return {"n": tuple(int(x) for x in n), "lo": tuple(float(x) for x in lo),
             "hi": tuple(float(x) for x in hi), "physics": physics, "recon": recon,
-            "gamma": float(gamma), "mu": float(mu), "prandtl": float(prandtl), "flux": flux}
+            "gamma": float(gamma), "mu": float(mu), "prandtl": float(prandtl), "flux": flux,
+            "sutherland": float(sutherland), "t_ref": float(t_ref)}
 
 
 def size(pb) -> int:

@@ -8,7 +8,8 @@ from oracle import fv
 def oracle_problem(pb):
     return fv.Problem(n=tuple(pb["n"]), lo=tuple(pb["lo"]), hi=tuple(pb["hi"]), physics=pb["physics"],
                       recon=pb["recon"], gamma=pb["gamma"], mu=pb["mu"], prandtl=pb["prandtl"],
-                      flux=pb.get("flux", "rusanov"))
+                      flux=pb.get("flux", "rusanov"), sutherland=pb.get("sutherland", 0.0),
+                      t_ref=pb.get("t_ref", 1.0))
 
 
 def t64(a):
