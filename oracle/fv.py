@@ -331,20 +331,28 @@ def _viscous_flux(P: Problem, r, vel, p, d):
     return [torch.zeros_like(r)] + tau + [energy]
 
 
-def residual(P: Problem, y: torch.Tensor) -> torch.Tensor:
-    """f(y) for a flat state vector y of length P.size (float64)."""
+def residual(P: Problem, y: torch.Tensor, part: str = "all") -> torch.Tensor:
+    """f(y) for a flat state vector y of length P.size (float64).
+
+    part = "inviscid" or "viscous" assembles f from that flux alone (the
+    split output of the residual: the two parts add up to f)."""
+    if part not in ("all", "inviscid", "viscous"):
+        raise ValueError(f"unknown part {part!r}")
     U = y.reshape(P.shape)
     U = [U[m] for m in range(P.nvar)]
     r, vel, p = primitives(P, U)
     out = None
     for d in range(P.ndim):
         (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, d)
-        Fh = face_flux(P, UL, rL, vL, pL, UR, rR, vR, pR, d)
-        if P.physics == NS:
+        if part == "viscous":
+            Fh = [torch.zeros_like(r) for _ in range(P.nvar)]
+        else:
+            Fh = face_flux(P, UL, rL, vL, pL, UR, rR, vR, pR, d)
+        if P.physics not in (EULER, NS):
+            raise ValueError(f"unknown physics {P.physics!r}")
+        if P.physics == NS and part != "inviscid":
             Fv = _viscous_flux(P, r, vel, p, d)
             Fh = [Fh[m] - Fv[m] for m in range(P.nvar)]
-        elif P.physics != EULER:
-            raise ValueError(f"unknown physics {P.physics!r}")
         inv = P.invdx(d)
         term = torch.stack([(_at(Fh[m], -1, d) - Fh[m]) * inv for m in range(P.nvar)])
         out = term if out is None else out + term
