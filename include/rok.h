@@ -79,7 +79,11 @@ enum { ROK_MGS_AUTO = 0, ROK_MGS_PER_PASS = 1, ROK_MGS_RESIDENT = 2 };
  * reconstruction, Rusanov or Roe flux (ROK_ROE: Roe's linearisation with
  * density-weighted averages and Harten's entropy fix, half-width c/8, on the
  * acoustic waves; the paper's residual offers Roe and Van Leer fluxes,
- * Sec. 3.2), constant viscosity mu, Prandtl number
+ * Sec. 3.2), viscosity mu, constant or by Sutherland's law
+ * mu(T) = mu theta^(3/2) (1 + s) / (theta + s), theta = T / t_ref,
+ * s = sutherland, at each face's temperature (T_a + T_b) / 2 with T = p / rho
+ * (the paper's cylinder cases set Sutherland's coefficient, Sec. 4.2),
+ * conductivity mu(T) gamma / ((gamma - 1) Pr), Prandtl number
  * `prandtl`, ratio of specific heats `gamma`.  With precision =
  * ROK_FP32_RESIDUAL the residual and tangent kernels compute in float while
  * Arnoldi, the reduced solve and all state accumulation stay in double.
@@ -96,6 +100,8 @@ typedef struct {
     double mu;
     double prandtl;
     int precision;
+    double sutherland;   /* S / T_ref of Sutherland's law (>= 0; 0: constant mu) */
+    double t_ref;        /* temperature p / rho at which the viscosity is mu (> 0 when sutherland > 0) */
 } rok_problem;
 
 /*
@@ -144,6 +150,19 @@ size_t rok_workspace_bytes(const rok_ctx* ctx, int M, int s);
  * or N floats when the context's precision is ROK_FP32_RESIDUAL.
  */
 rok_status rok_residual(rok_ctx* ctx, const double* y, void* F, void* stream);
+
+/*
+ * The residual split into its inviscid and viscous parts (eq. 11: the
+ * divergence of the inviscid flux and of the viscous stress / heat flux
+ * vectors), F_inv + F_visc = f(y) up to the rounding of that one addition:
+ *   F_inv  = -sum_d (Fhat_{c+1/2} - Fhat_{c-1/2}) / dx_d  (inviscid flux only)
+ *   F_visc =  sum_d (Fv_{c+1/2} - Fv_{c-1/2}) / dx_d      (viscous flux only;
+ *            zero for ROK_EULER)
+ * Each part is assembled as f is, with the other flux left out.
+ *   y: N doubles; F_inv, F_visc: N elements each (double, or float for
+ *   ROK_FP32_RESIDUAL), device memory, distinct.
+ */
+rok_status rok_residual_split(rok_ctx* ctx, const double* y, void* F_inv, void* F_visc, void* stream);
 
 /*
  * w = J(y) v, J = df/dy at y (Sec. 2.3).

@@ -227,6 +227,8 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
     if (p->flux != ROK_RUSANOV && p->flux != ROK_ROE) return ROK_EINVAL;
     if (p->precision != ROK_FP64 && p->precision != ROK_FP32_RESIDUAL) return ROK_EINVAL;
     if (!(p->gamma > 1.0) || !(p->mu >= 0.0) || !(p->prandtl > 0.0)) return ROK_EINVAL;
+    if (!(p->sutherland >= 0.0) || !isfinite(p->sutherland)) return ROK_EINVAL;
+    if (p->sutherland > 0.0 && (!(p->t_ref > 0.0) || !isfinite(p->t_ref))) return ROK_EINVAL;
     rok_ctx* c = new (std::nothrow) rok_ctx;
     if (!c) return ROK_EINVAL;
     c->pb = *p;
@@ -249,6 +251,11 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
     G.c23mu = (2.0 / 3.0) * G.mu;
     G.kappa = G.mu * p->gamma / ((p->gamma - 1.0) * p->prandtl);
     G.flux = p->flux;
+    G.suth = (p->physics == ROK_NS && p->sutherland > 0.0) ? 1 : 0;
+    G.suth_s = p->sutherland;
+    G.suth_one_s = 1.0 + p->sutherland;
+    G.t_ref = p->sutherland > 0.0 ? p->t_ref : 1.0;
+    G.kden = (p->gamma - 1.0) * p->prandtl;
     *out = c;
     return ROK_OK;
 }
@@ -275,6 +282,25 @@ rok_status rok_residual(rok_ctx* c, const double* y, void* F, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     rok::ResArgs A = plain_args(y, F);
     ROK_TRY(rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, fp32(c), 0, !fp32(c), A, st));
+    return ROK_OK;
+}
+
+rok_status rok_residual_split(rok_ctx* c, const double* y, void* F_inv, void* F_visc, void* stream) {
+    const size_t a = fp32(c) ? 4 : 8;
+    if (!c || !y || !F_inv || !F_visc || F_inv == F_visc || !aligned(y, 8) || !aligned(F_inv, a) ||
+        !aligned(F_visc, a))
+        return ROK_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    // inviscid part: the Euler kernel of the same discretisation
+    rok::ResArgs A = plain_args(y, F_inv);
+    ROK_TRY(rok::launch_residual(c->G, c->pb.recon, false, fp32(c), 0, !fp32(c), A, st));
+    if (c->pb.physics != ROK_NS) {
+        ROK_TRY(rok::launch_zero(F_visc, c->G.N * (long)a, st));
+        return ROK_OK;
+    }
+    A.out = F_visc;
+    A.viscous_only = 1;
+    ROK_TRY(rok::launch_residual(c->G, c->pb.recon, true, fp32(c), 0, !fp32(c), A, st));
     return ROK_OK;
 }
 

@@ -30,6 +30,8 @@ struct Geom {
     double g, gm1;    // gamma, gamma - 1
     double mu, c23mu, kappa;  // mu, (2/3) mu, mu gamma / ((gamma-1) Pr)
     int flux;                 // inviscid flux: 0 Rusanov, 1 Roe
+    int suth;                 // Sutherland's law (else constant mu)
+    double suth_s, suth_one_s, t_ref, kden;   // S / T_ref, 1 + S / T_ref, T_ref, (gamma - 1) Pr
 };
 
 // Residual-kernel inputs: the stage state Y = y + sum_t cs[t] xs[t]
@@ -48,6 +50,8 @@ struct ResArgs {
     // device-side basis size, e.g. M_eff of the Arnoldi process)
     const int* gate;
     int gate_col;
+    // Navier-Stokes kernels: assemble the viscous part of f only
+    int viscous_only;
 };
 
 // ---------------------------------------------------------------------------

@@ -8,6 +8,8 @@ namespace rok {
 // Residual family (rok_residual.hip).  kind: 0 = F = f(Y), 1 = FD product,
 // 2 = tangent product.  fp32: compute in float.  out_double: write doubles
 // even when computing in float (internal FP64 consumers).
+// Fills `bytes` bytes (a multiple of 4) at p with zeros (a kernel, not a memset).
+hipError_t launch_zero(void* p, long bytes, hipStream_t st);
 hipError_t launch_residual(const Geom& G, int recon, bool ns, bool fp32, int kind, bool out_double,
                            const ResArgs& A, hipStream_t st);
 

@@ -336,6 +336,10 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             }
             if constexpr (!PERT) num_flux<D, FLUX>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
             if constexpr (NSV) {
+                if (A.viscous_only) {
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) Fh[m] = Sc<S>::make(0.0);
+                }
                 const R half = (R)0.5;
                 const R mu = (R)G.mu, c23mu = (R)G.c23mu, kappa = (R)G.kappa;
                 S Gr[D][D];
@@ -357,17 +361,30 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 S div = Gr[0][0];
 #pragma unroll
                 for (int a = 1; a < D; ++a) div = div + Gr[a][a];
-                S work;
+                // stress, work and conduction for viscosity mu_, (2/3) mu_ and conductivity kappa_
+                auto viscous = [&](auto mu_, auto c23mu_, auto kappa_) {
+                    S work;
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    S tau = (a == d) ? mu * (Gr[a][d] + Gr[d][a]) - c23mu * div : mu * (Gr[a][d] + Gr[d][a]);
-                    S uf = half * (sq[OFF_VEL + a][ca] + sq[OFF_VEL + a][cb]);
-                    if constexpr (PERT) uf = s_ref.u0[a] + uf;   // perturbations staged: add the reference
-                    work = (a == 0) ? uf * tau : work + uf * tau;
-                    Fh[1 + a] = Fh[1 + a] - tau;
+                    for (int a = 0; a < D; ++a) {
+                        S tau = (a == d) ? mu_ * (Gr[a][d] + Gr[d][a]) - c23mu_ * div : mu_ * (Gr[a][d] + Gr[d][a]);
+                        S uf = half * (sq[OFF_VEL + a][ca] + sq[OFF_VEL + a][cb]);
+                        if constexpr (PERT) uf = s_ref.u0[a] + uf;   // perturbations staged: add the reference
+                        work = (a == 0) ? uf * tau : work + uf * tau;
+                        Fh[1 + a] = Fh[1 + a] - tau;
+                    }
+                    S dTdn = (sq[OFF_T][cb] - sq[OFF_T][ca]) * (R)G.invdx[d];
+                    Fh[D + 1] = Fh[D + 1] - (work + kappa_ * dTdn);
+                };
+                if (G.suth) {
+                    // Sutherland's law at the face temperature (T_a + T_b) / 2
+                    S Tf = half * (sq[OFF_T][ca] + sq[OFF_T][cb]);
+                    if constexpr (PERT) Tf = (R)s_refd[D + 2] + Tf;
+                    const S th = Tf / (R)G.t_ref;
+                    const S muf = mu * th * Sc<S>::sqrt_(th) * (R)G.suth_one_s / (th + (R)G.suth_s);
+                    viscous(muf, (R)(2.0 / 3.0) * muf, muf * (R)G.g / (R)G.kden);
+                } else {
+                    viscous(mu, c23mu, kappa);
                 }
-                S dTdn = (sq[OFF_T][cb] - sq[OFF_T][ca]) * (R)G.invdx[d];
-                Fh[D + 1] = Fh[D + 1] - (work + kappa * dTdn);
             }
 #pragma unroll
             for (int m = 0; m < NV; ++m) fb[m][f] = Fh[m];
@@ -460,6 +477,19 @@ static hipError_t dispatch_prec(const Geom& G, const ResArgs& A, int kind, bool 
     }
     if (out_double) return launch_v<D, RECON, NSV, FLUX, Dual<float>, MODE_TAN, double>(G, A, st);
     return launch_v<D, RECON, NSV, FLUX, Dual<float>, MODE_TAN, float>(G, A, st);
+}
+
+__global__ __launch_bounds__(256) void k_zero(unsigned* p, long n) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, long bytes, hipStream_t st) {
+    const long n = bytes / 4;
+    if (n <= 0) return hipSuccess;
+    long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)nb), dim3(256), 0, st, (unsigned*)p, n);
+    return hipGetLastError();
 }
 
 template <int D, int RECON, bool NSV>

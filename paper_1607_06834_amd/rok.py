@@ -24,7 +24,7 @@ JVP_FD, JVP_TANGENT = 0, 1
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER = 1, 2, 4, 8
 MAX_STAGES, MAX_M = 8, 64
 
-SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual",
+SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
            "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
            "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
            "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
@@ -35,7 +35,8 @@ class RokProblem(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("physics", ctypes.c_int), ("recon", ctypes.c_int),
                 ("flux", ctypes.c_int), ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
-                ("prandtl", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("prandtl", ctypes.c_double), ("precision", ctypes.c_int), ("sutherland", ctypes.c_double),
+                ("t_ref", ctypes.c_double)]
 
 
 class RokTableau(ctypes.Structure):
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.rok_workspace_bytes.restype = sz
     lib.rok_residual.argtypes = [vp, vp, vp, vp]
     lib.rok_residual.restype = i
+    lib.rok_residual_split.argtypes = [vp, vp, vp, vp, vp]
+    lib.rok_residual_split.restype = i
     lib.rok_jvp.argtypes = [vp, vp, vp, vp, vp, i, d, vp, sz, vp]
     lib.rok_jvp.restype = i
     lib.rok_arnoldi.argtypes = [vp, vp, vp, i, i, d, vp, vp, vp, vp, sz, vp]
@@ -174,6 +177,8 @@ class Rok:
         p.gamma = float(problem["gamma"])
         p.mu = float(problem.get("mu", 0.0))
         p.prandtl = float(problem.get("prandtl", 0.72))
+        p.sutherland = float(problem.get("sutherland", 0.0))
+        p.t_ref = float(problem.get("t_ref", 1.0))
         p.precision = FP32_RESIDUAL if precision == "fp32" else FP64
         self.precision = precision
         self._ctx = ctypes.c_void_p()
@@ -225,6 +230,14 @@ class Rok:
         F = out if out is not None else torch.empty(self.N, dtype=self._out_dtype(), device=y.device)
         _check(_lib.rok_residual(self._ctx, _ptr(y), _ptr(F), _stream()), "rok_residual")
         return F
+
+    def residual_split(self, y: torch.Tensor):
+        """(inviscid part, viscous part) of f(y) (rok_residual_split)."""
+        self._vec(y, "y")
+        Fi = torch.empty(self.N, dtype=self._out_dtype(), device=y.device)
+        Fv = torch.empty_like(Fi)
+        _check(_lib.rok_residual_split(self._ctx, _ptr(y), _ptr(Fi), _ptr(Fv), _stream()), "rok_residual_split")
+        return Fi, Fv
 
     def jvp(self, y, v, mode: str = "fd", fy=None, eps: float = 0.0, out=None) -> torch.Tensor:
         self._vec(y, "y")

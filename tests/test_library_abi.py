@@ -53,4 +53,19 @@ def test_host_validation_without_gpu():
     tab.s = 0
     assert lib.rok_step(ctx, ctypes.byref(tab), 4, 0, 0.1, ctypes.c_void_p(8), ctypes.c_void_p(16),
                         ctypes.c_void_p(256), 1 << 20, None) == rok.ROK_EINVAL
+    st = rok.RokAdaptiveStats()
+    assert lib.rok_integrate_adaptive(ctx, ctypes.byref(tab), 4, 0, 4, 1.0, 0.1, 1e-6, 1e-6, 100,
+                                      ctypes.c_void_p(8), ctypes.byref(st), None, 0, ctypes.c_void_p(256), 1 << 20,
+                                      None) == rok.ROK_EINVAL
+    assert lib.rok_error_norm(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(24), 0.0, 0.0, 15.0,
+                              ctypes.c_void_p(32), ctypes.c_void_p(256), 1 << 20, None) == rok.ROK_EINVAL
     lib.rok_destroy(ctx)
+    # inviscid flux and Sutherland's law are validated on the host
+    for flux, suth, tref, want in ((rok.ROE, 0.0, 1.0, rok.ROK_OK), (2, 0.0, 1.0, rok.ROK_EINVAL),
+                                   (0, -0.5, 1.0, rok.ROK_EINVAL), (0, 0.5, 0.0, rok.ROK_EINVAL),
+                                   (0, 0.5, 2.0, rok.ROK_OK)):
+        p.flux, p.sutherland, p.t_ref = flux, suth, tref
+        ctx = ctypes.c_void_p()
+        assert lib.rok_create(ctypes.byref(p), ctypes.byref(ctx)) == want, (flux, suth, tref)
+        if want == rok.ROK_OK:
+            lib.rok_destroy(ctx)
