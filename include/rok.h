@@ -381,6 +381,35 @@ rok_status rok_residual_vjp(rok_ctx* ctx, const double* y, const double* wbar, d
 rok_status rok_residual_vjp2(rok_ctx* ctx, const double* y, const double* v, const double* wbar, double* ybar,
                              double* ybar2, int accumulate, void* stream);
 
+/*
+ * The k eigenvalues of largest magnitude of the Jacobian J(y) of f, matrix
+ * free: the stiffness diagnostic of Sec. 4 (an implicitly restarted Arnoldi
+ * method on exact products J v).  An Arnoldi factorisation J V_m = V_m H_m +
+ * h_{m+1,m} v_{m+1} e_m^T is built from v0 (modified Gram-Schmidt, the
+ * library's kernels, applied twice per column); the Ritz values of H_m are its eigenvalues; while
+ * fewer than k of the wanted ones have residual estimates
+ * |h_{m+1,m}| |e_m^T x| <= tol |theta| (x the unit eigenvector of H_m), the
+ * factorisation is compressed to k (k + 1 when a conjugate pair straddles
+ * the cut) columns by exact shifted QR steps with the unwanted Ritz values
+ * and extended back to m, at most max_restarts times.  The small dense work
+ * on H (m x m) runs on the host; the call synchronises `stream`.
+ *   y, v0:  N doubles, device memory (v0 != 0: the start vector)
+ *   k, m:   1 <= k, k + 2 <= m <= ROK_MAX_M - 1, m + 1 <= N
+ *   tol:    > 0;  max_restarts >= 0
+ *   re, im, resid: host arrays of k doubles: the wanted Ritz values by
+ *           decreasing magnitude and their residual estimates (0 when the
+ *           Krylov space became invariant)
+ *   info:   host int[2]: restarts used, number of converged values
+ *   work:   rok_eigs_workspace_bytes(ctx, k, m) bytes, device memory
+ * ROK_EINVAL for a zero start vector; ROK_EHIP if the host QR iteration on
+ * H does not converge.
+ */
+rok_status rok_eigs(rok_ctx* ctx, const double* y, const double* v0, int k, int m, int max_restarts, double tol,
+                    double* re, double* im, double* resid, int* info, void* work, size_t work_bytes, void* stream);
+
+/* Bytes of device workspace rok_eigs needs (0 on invalid arguments). */
+size_t rok_eigs_workspace_bytes(const rok_ctx* ctx, int k, int m);
+
 /* Copies the status word of `work` (ROK_FLAG_* bits of the last call that
  * used it) to *host_flags; synchronises `stream`. */
 rok_status rok_read_status(rok_ctx* ctx, const void* work, int* host_flags, void* stream);

@@ -5,7 +5,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "rok.h"
 #include "rok_device.hpp"
@@ -484,6 +486,206 @@ rok_status rok_integrate_adaptive(rok_ctx* c, const rok_tableau* tab, int M, int
     stats->accepted = acc;
     stats->rejected = rej;
     stats->recorded = rec;
+    return ROK_OK;
+}
+
+namespace {
+struct EigLayout {
+    size_t work, vec, basis, coef, hb, total;
+};
+
+EigLayout eig_layout(long N, int m) {
+    EigLayout L;
+    L.work = al256h(rok::work_bytes(N, m + 1, 0, false));
+    L.vec = al256h(sizeof(double) * (size_t)N);
+    L.basis = L.vec * (size_t)(m + 1);
+    L.coef = al256h(sizeof(double) * (size_t)(m + 1) * (size_t)(m + 1));
+    L.hb = al256h(sizeof(double) * (size_t)(m + 2) * (size_t)(m + 1));
+    L.total = L.work + 2 * L.basis + L.coef + L.hb;
+    return L;
+}
+
+bool eig_args_ok(const rok_ctx* c, int k, int m) {
+    return c && m >= 3 && m <= ROK_MAX_M - 1 && k >= 1 && k + 2 <= m && (long)m + 1 <= c->G.N;
+}
+}  // namespace
+
+size_t rok_eigs_workspace_bytes(const rok_ctx* c, int k, int m) {
+    if (!eig_args_ok(c, k, m)) return 0;
+    return eig_layout(c->G.N, m).total;
+}
+
+rok_status rok_eigs(rok_ctx* c, const double* y, const double* v0, int k, int m, int max_restarts, double tol,
+                    double* re, double* im, double* resid, int* info, void* work, size_t wbytes, void* stream) {
+    if (!eig_args_ok(c, k, m) || !y || !v0 || !re || !im || !resid || !info) return ROK_EINVAL;
+    if (!aligned(y, 8) || !aligned(v0, 8) || max_restarts < 0 || !(tol > 0.0) || !isfinite(tol)) return ROK_EINVAL;
+    const long N = c->G.N;
+    const int Mp = m + 1;
+    const EigLayout L = eig_layout(N, m);
+    if (!work || !aligned(work, 256) || wbytes < L.total) return ROK_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    char* p = (char*)work;
+    rok::Work W = rok::carve(p, N, Mp, 0, false);
+    double* V = (double*)(p + L.work);
+    double* Vo = (double*)(p + L.work + L.basis);
+    double* Cd = (double*)(p + L.work + 2 * L.basis);
+    // a second pass of every Gram-Schmidt column writes its coefficients here
+    rok::Work W2 = W;
+    W2.H = (double*)(p + L.work + 2 * L.basis + L.coef);
+    const bool resident =
+        c->mgs_path != ROK_MGS_PER_PASS && rok::mgs_resident_per(N) > 0 && rok::mgs_resident_available();
+    if (c->mgs_path == ROK_MGS_RESIDENT && !resident) return ROK_EUNSUPPORTED;
+    auto mgs = [&](const rok::Work& Wx, int j, double* vnext) -> hipError_t {
+        return resident ? rok::launch_mgs_resident(Wx, Wx.w, V, N, Mp, j, vnext, st)
+                        : rok::launch_mgs_column(Wx, Wx.w, V, N, Mp, j, vnext, st);
+    };
+    // orthonormalise W.w against V[:, 0..j] into V[:, j+1] by modified Gram-Schmidt,
+    // twice (the second pass on the normalised result restores the orthogonality
+    // that one pass loses when w is nearly in the span, as near convergence)
+    auto orthonormalise = [&](int j) -> hipError_t {
+        double* vnext = V + (long)(j + 1) * N;
+        hipError_t e = mgs(W, j, vnext);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(W.w, vnext, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = mgs(W2, j, vnext);
+        return e;
+    };
+    // column j of the Arnoldi process: w = J v_j (exact product), then orthonormalised
+    auto column = [&](int j) -> hipError_t {
+        hipError_t e = jvp_into(c, y, nullptr, V + (long)j * N, W.w, ROK_JVP_TANGENT, nullptr, 0.0, st);
+        if (e != hipSuccess) return e;
+        return orthonormalise(j);
+    };
+    std::vector<double> Hd((size_t)(Mp + 1) * Mp), Hb((size_t)(Mp + 1) * Mp), Hh((size_t)(m + 1) * m, 0.0);
+    int ints[3] = {0, 0, 0};
+    // both passes' coefficients and the status words to the host
+    auto fetch = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(Hd.data(), W.H, sizeof(double) * Hd.size(), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(Hb.data(), W2.H, sizeof(double) * Hb.size(), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(ints, W.ints, sizeof(ints), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        return e;
+    };
+    // combined coefficient of column j: w = sum_i (h_ij + b h'_ij) v_i + b b' v_{j+1}
+    // (h, b = h_{j+1,j}: first pass; h', b': second pass on w / b)
+    auto hd = [&](int i, int j) {
+        const double b = Hd[(size_t)(j + 1) * Mp + j];
+        const double b2 = Hb[(size_t)(j + 1) * Mp + j];
+        if (i == j + 1) return b * b2;
+        return Hd[(size_t)i * Mp + j] + b * Hb[(size_t)i * Mp + j];
+    };
+    auto hh = [&](int i, int j) -> double& { return Hh[(size_t)i * m + j]; };
+
+    ROK_TRY(rok::launch_init(W2, Mp, 0, st));
+    ROK_TRY(rok::launch_init(W, Mp, 0, st));
+    ROK_TRY(rok::launch_start_basis(W, v0, N, V, st));
+    for (int j = 0; j < m; ++j) ROK_TRY(column(j));
+    ROK_TRY(fetch());
+    if (ints[2] & ROK_FLAG_ZERO_RHS) return ROK_EINVAL;   // v0 = 0
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i <= j + 1; ++i) hh(i, j) = hd(i, j);
+    int meff = ints[1] ? ints[0] : m;   // a breakdown leaves an invariant subspace of dimension meff
+
+    std::vector<double> wr(m), wi(m), Qacc((size_t)m * m), Hw((size_t)m * m), Cc((size_t)Mp * Mp);
+    std::vector<int> idx(m);
+    int restarts = 0;
+    for (;;) {
+        const int n = meff < m ? meff : m;
+        if (!rok::dense::hessenberg_eigenvalues(n, Hh.data(), m, wr.data(), wi.data())) return ROK_EHIP;
+        for (int i = 0; i < n; ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.begin() + n, [&](int a, int b) {
+            return std::hypot(wr[a], wi[a]) > std::hypot(wr[b], wi[b]);
+        });
+        const double hlast = n < m ? 0.0 : hh(m, m - 1);
+        int conv = 0;
+        for (int t = 0; t < k; ++t) {
+            if (t >= n) {
+                re[t] = im[t] = 0.0;
+                resid[t] = INFINITY;
+                continue;
+            }
+            const int i = idx[t];
+            re[t] = wr[i];
+            im[t] = wi[i];
+            resid[t] = (n < m) ? 0.0 : rok::dense::ritz_residual(m, Hh.data(), m, hlast, wr[i], wi[i]);
+            if (resid[t] <= tol * std::hypot(wr[i], wi[i])) ++conv;
+        }
+        info[0] = restarts;
+        info[1] = conv;
+        if (conv == k || n < m || restarts >= max_restarts) break;
+        // Ritz values of a real H come in conjugate pairs: pair them up (partner[i] = i for real ones)
+        std::vector<int> partner(m);
+        for (int i = 0; i < m; ++i) partner[i] = i;
+        {
+            std::vector<int> pos, neg;
+            for (int i = 0; i < m; ++i) {
+                if (fabs(wi[i]) <= 1e-12 * std::hypot(wr[i], wi[i])) continue;
+                (wi[i] > 0.0 ? pos : neg).push_back(i);
+            }
+            std::vector<char> taken(m, 0);
+            for (int i : pos) {
+                int best = -1;
+                double bd = INFINITY;
+                for (int j : neg) {
+                    if (taken[j]) continue;
+                    const double dd = std::hypot(wr[j] - wr[i], wi[j] + wi[i]);
+                    if (dd < bd) { bd = dd; best = j; }
+                }
+                if (best >= 0) {
+                    taken[best] = 1;
+                    partner[i] = best;
+                    partner[best] = i;
+                }
+            }
+        }
+        // wanted: the k largest and the partners of complex ones among them (kk values);
+        // the others are the exact shifts, each real one once and each pair as one double
+        // shift, so that the shifts' total degree is m - kk
+        std::vector<char> want(m, 0);
+        for (int t = 0; t < k; ++t) want[idx[t]] = want[partner[idx[t]]] = 1;
+        int kk = 0;
+        for (int i = 0; i < m; ++i) kk += want[i];
+        if (kk + 2 > m) break;   // no room to restart: keep the current estimate
+        std::fill(Qacc.begin(), Qacc.end(), 0.0);
+        for (int i = 0; i < m; ++i) Qacc[(size_t)i * m + i] = 1.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) Hw[(size_t)i * m + j] = hh(i, j);
+        for (int t = 0; t < m; ++t) {
+            const int i = idx[t];
+            if (want[i]) continue;
+            if (partner[i] == i) {
+                rok::dense::shift_step(m, Hw.data(), m, Qacc.data(), wr[i], 0.0, false);
+            } else if (wi[i] > 0.0) {
+                rok::dense::shift_step(m, Hw.data(), m, Qacc.data(), wr[i], wi[i], true);
+            }
+        }
+        // new basis [V Q[:, 0..kk-1], f_kk] with f_kk = (V Q)[:, kk] H+[kk, kk-1] + v_m h[m, m-1] Q[m-1, kk-1]
+        std::fill(Cc.begin(), Cc.end(), 0.0);
+        for (int cc = 0; cc < kk; ++cc)
+            for (int i = 0; i < m; ++i) Cc[(size_t)cc * Mp + i] = Qacc[(size_t)i * m + cc];
+        const double hk = Hw[(size_t)kk * m + kk - 1];
+        for (int i = 0; i < m; ++i) Cc[(size_t)kk * Mp + i] = hk * Qacc[(size_t)i * m + kk];
+        Cc[(size_t)kk * Mp + m] = hh(m, m - 1) * Qacc[(size_t)(m - 1) * m + kk - 1];
+        ROK_TRY(hipMemcpyAsync(Cd, Cc.data(), sizeof(double) * (size_t)Mp * (kk + 1), hipMemcpyHostToDevice, st));
+        ROK_TRY(rok::launch_combine(V, N, Mp, Cd, kk + 1, Vo, st));
+        std::swap(V, Vo);
+        // orthonormalise f_kk against the kept vectors (its projections correct column kk-1 of H), then extend
+        ROK_TRY(rok::launch_init(W2, Mp, 0, st));
+        ROK_TRY(rok::launch_init(W, Mp, 0, st));
+        ROK_TRY(hipMemcpyAsync(W.w, V + (long)kk * N, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, st));
+        ROK_TRY(orthonormalise(kk - 1));
+        for (int j = kk; j < m; ++j) ROK_TRY(column(j));
+        ROK_TRY(fetch());
+        std::fill(Hh.begin(), Hh.end(), 0.0);
+        for (int j = 0; j + 1 < kk; ++j)
+            for (int i = 0; i <= j + 1; ++i) hh(i, j) = Hw[(size_t)i * m + j];
+        for (int i = 0; i < kk; ++i) hh(i, kk - 1) = Hw[(size_t)i * m + kk - 1] + hd(i, kk - 1);
+        hh(kk, kk - 1) = hd(kk, kk - 1);
+        for (int j = kk; j < m; ++j)
+            for (int i = 0; i <= j + 1; ++i) hh(i, j) = hd(i, j);
+        meff = ints[1] ? ints[0] : m;
+        ++restarts;
+    }
     return ROK_OK;
 }
 

@@ -62,6 +62,13 @@ int mgs_resident_per(long n);
 bool mgs_resident_available();
 hipError_t launch_mgs_resident(const Work& W, const double* w, const double* V, long n, int M, int j, double* vnext,
                                hipStream_t st);
+// Eigenvalue estimate pieces (rok_eigs.hip)
+hipError_t launch_combine(const double* V, long n, int m1, const double* C, int nc, double* Vout, hipStream_t st);
+namespace dense {
+bool hessenberg_eigenvalues(int n, const double* H, int ldh, double* wr, double* wi);
+void shift_step(int m, double* H, int ldh, double* Qacc, double mre, double mim, bool pair);
+double ritz_residual(int m, const double* H, int ldh, double hlast, double tre, double tim);
+}  // namespace dense
 hipError_t launch_copy_h(const Work& W, int M, double* Hout, int* meff_out, hipStream_t st);
 hipError_t launch_lu(const Work& W, int M, double hg, hipStream_t st);
 hipError_t launch_project(const Work& W, const double* V, const double* F, long n, int M, hipStream_t st);

@@ -27,7 +27,7 @@ MAX_STAGES, MAX_M = 8, 64
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
            "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
            "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
-           "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
+           "rok_eigs", "rok_eigs_workspace_bytes", "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
 MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
@@ -98,6 +98,11 @@ def load_library(path: str = LIB_PATH):
     lib.rok_step_vjp_stored.restype = i
     lib.rok_step_vjp_adjoint_bytes.argtypes = [vp, i, i]
     lib.rok_step_vjp_adjoint_bytes.restype = sz
+    pd, pi = ctypes.POINTER(d), ctypes.POINTER(i)
+    lib.rok_eigs.argtypes = [vp, vp, vp, i, i, i, d, pd, pd, pd, pi, vp, sz, vp]
+    lib.rok_eigs.restype = i
+    lib.rok_eigs_workspace_bytes.argtypes = [vp, i, i]
+    lib.rok_eigs_workspace_bytes.restype = sz
     lib.rok_error_norm.argtypes = [vp, vp, vp, vp, d, d, d, vp, vp, sz, vp]
     lib.rok_error_norm.restype = i
     lib.rok_integrate_adaptive.argtypes = [vp, ctypes.POINTER(RokTableau), i, i, i, d, d, d, d, i, vp,
@@ -278,6 +283,25 @@ class Rok:
                              ws.numel(), _stream()), "rok_step")
         self._last_step_ws = ws
         return y1
+
+    def eigs(self, y, v0, k: int = 6, m: int = 40, max_restarts: int = 50, tol: float = 1e-10):
+        """k largest-magnitude eigenvalues of J(y) (rok_eigs).  Returns (values as a complex
+        numpy array, residual estimates, restarts used, number converged)."""
+        import numpy as np
+        self._vec(y, "y")
+        self._vec(v0, "v0")
+        nb = int(_lib.rok_eigs_workspace_bytes(self._ctx, int(k), int(m)))
+        if nb == 0:
+            raise ValueError(f"invalid eigenvalue request k={k}, m={m} for N={self.N}")
+        w = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-w.data_ptr()) % 256
+        ws = w[off:off + nb]
+        re, im, rs = (ctypes.c_double * k)(), (ctypes.c_double * k)(), (ctypes.c_double * k)()
+        info = (ctypes.c_int * 2)()
+        _check(_lib.rok_eigs(self._ctx, _ptr(y), _ptr(v0), int(k), int(m), int(max_restarts), float(tol), re, im,
+                             rs, info, _ptr(ws), ws.numel(), _stream()), "rok_eigs")
+        vals = np.array([complex(re[t], im[t]) for t in range(k)])
+        return vals, np.array(list(rs)), info[0], info[1]
 
     def error_norm(self, y_n, y_a, y_b, rtol: float, atol: float, scale: float, out=None) -> torch.Tensor:
         """sqrt(sum_i q_i^2 / N), q_i = (y_a - y_b)_i / (scale (atol + rtol max(|y_n|, |y_a|)_i)),

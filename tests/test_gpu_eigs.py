@@ -1,0 +1,112 @@
+"""Matrix-free eigenvalue estimate of J (rok_eigs) against the oracle's dense spectrum.
+
+The oracle's eigenvalues are LAPACK's on the dense exact Jacobian; the GPU
+estimate runs implicitly restarted Arnoldi on exact products.  The k
+largest-magnitude Ritz values must match the k largest-magnitude
+eigenvalues as multisets to 1e-8 relative (FP64 products; 1e-5 with the FP32
+form, whose J is the FP32 residual's), with every residual estimate within
+the requested tolerance.  Generic (seeded) states keep the spectrum simple.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import rok_inputs as ri
+from oracle import eigen
+from tests._util import oracle_problem, t64
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1607_06834_amd import load_library
+    load_library()
+    return torch.device("cuda", 0)
+
+
+def gpu(pb, precision="fp64"):
+    from paper_1607_06834_amd import Rok
+    return Rok(pb, precision)
+
+
+def _match(got, want):
+    """Relative distance between the k values returned and the oracle's k largest,
+    as sets: every returned value lies near one of the oracle's k + 1 largest, and
+    every one of the oracle's k largest (or its conjugate: the k-th may be half of
+    a pair whose other half is the (k+1)-th) lies near a returned value."""
+    k = len(got)
+    d1 = np.abs(got[:, None] - want[None, :k + 1]).min(axis=1).max()
+    w = want[:k]
+    d2 = np.minimum(np.abs(w[:, None] - got[None, :]), np.abs(np.conj(w)[:, None] - got[None, :])).min(axis=1).max()
+    return max(d1, d2) / np.abs(want).max()
+
+
+CASES = [
+    ("euler_fo_rusanov", ri.problem((16, 12), (0.0, 0.0), (1.0, 0.8), "euler", "first"), "fp64", 1e-8),
+    ("euler_muscl_roe", ri.problem((12, 10), (0.0, 0.0), (1.0, 0.8), "euler", "muscl", flux="roe"), "fp64", 1e-8),
+    ("ns_muscl_sutherland", ri.problem((12, 10), (0.0, 0.0), (1.0, 1.1), "ns", "muscl", mu=0.05, sutherland=0.4),
+     "fp64", 1e-8),
+    ("euler3d_fo", ri.problem((6, 5, 4), (0.0,) * 3, (1.0, 0.9, 0.8), "euler", "first"), "fp64", 1e-8),
+    ("ns_muscl_fp32", ri.problem((12, 10), (0.0, 0.0), (1.0, 1.1), "ns", "muscl", mu=0.05), "fp32", 1e-5),
+]
+
+
+@pytest.mark.parametrize("name,pb,prec,tol", CASES)
+def test_eigs_against_dense_spectrum(dev, name, pb, prec, tol):
+    k, m = 6, 40
+    say("eigs", name, prec)
+    P = oracle_problem(pb)
+    y = t64(ri.smooth_random_state(pb, seed=4, amplitude=0.2))
+    want = eigen.largest(P, y, k + 2)
+    g = gpu(pb, prec)
+    v0 = torch.tensor(ri.random_direction(g.N, seed=11), device=dev)
+    vals, res, restarts, conv = g.eigs(y.to(dev), v0, k=k, m=m, max_restarts=200, tol=1e-12 if prec == "fp64" else 1e-7)
+    say("  restarts", restarts, "converged", conv, "max rel residual", float(np.max(res / np.abs(vals))))
+    assert conv == k
+    e = _match(vals, want)
+    say("  error", e, "values", np.round(vals, 8), "oracle", np.round(want, 8))
+    assert e <= tol
+
+
+def test_eigs_invariant_start_and_bad_arguments(dev):
+    """At a uniform state a uniform perturbation is in the kernel of J: the Krylov
+    space is invariant after one vector and the estimate returns 0 exactly."""
+    from paper_1607_06834_amd.rok import RokError
+    pb = ri.problem((8, 6), (0.0, 0.0), (1.0, 0.8), "euler", "first")
+    g = gpu(pb)
+    y = torch.tensor(ri.uniform_state(pb, rho=1.2, vel=[0.3, -0.2], p=0.8), device=dev)
+    v0 = torch.zeros(g.N, dtype=torch.float64, device=dev)
+    v0[: g.N // 4] = 1.0                       # uniform density perturbation
+    vals, res, restarts, conv = g.eigs(y, v0, k=3, m=10)
+    assert abs(vals[0]) <= 1e-12 and res[0] == 0.0 and restarts == 0
+    with pytest.raises(RokError):
+        g.eigs(y, torch.zeros_like(v0), k=3, m=10)
+    with pytest.raises(ValueError):
+        g.eigs(y, v0, k=9, m=10)
+
+
+def test_eigs_full_size_spectral_radius(dev):
+    """1024^2 MUSCL vortex: the largest-magnitude Ritz value converges (relative
+    residual <= 1e-3), and the spectral radius is of the order of the step-size
+    estimate max sum_d (|u| + c) / dx_d (between a quarter and four times it: the
+    first-order symbol reaches twice the estimate, MUSCL's slopes add to it)."""
+    pb, y0, w = ri.workload("vortex1024_muscl")
+    g = gpu(pb)
+    y = torch.tensor(y0, device=dev)
+    v0 = torch.tensor(ri.random_direction(g.N, seed=5), device=dev)
+    vals, res, restarts, conv = g.eigs(y, v0, k=4, m=30, max_restarts=100, tol=1e-6)
+    rho = float(np.abs(vals).max())
+    est = ri.spectral_estimate(pb, y0)
+    say("full-size eigs", vals, "restarts", restarts, "conv", conv, "rho", rho, "estimate", est)
+    assert res[0] <= 1e-3 * abs(vals[0])
+    assert 0.25 * est <= rho <= 4.0 * est

@@ -59,6 +59,14 @@ def test_host_validation_without_gpu():
                                       None) == rok.ROK_EINVAL
     assert lib.rok_error_norm(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(24), 0.0, 0.0, 15.0,
                               ctypes.c_void_p(32), ctypes.c_void_p(256), 1 << 20, None) == rok.ROK_EINVAL
+    # eigenvalue estimate: sizes are validated on the host
+    assert lib.rok_eigs_workspace_bytes(ctx, 6, 40) > 0
+    assert lib.rok_eigs_workspace_bytes(ctx, 9, 10) == 0 and lib.rok_eigs_workspace_bytes(ctx, 0, 10) == 0
+    assert lib.rok_eigs_workspace_bytes(ctx, 4, 64) == 0
+    re_, im_, rs_ = (ctypes.c_double * 4)(), (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
+    inf = (ctypes.c_int * 2)()
+    assert lib.rok_eigs(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), 4, 5, 10, 1e-8, re_, im_, rs_, inf,
+                        ctypes.c_void_p(256), 1 << 30, None) == rok.ROK_EINVAL
     lib.rok_destroy(ctx)
     # inviscid flux and Sutherland's law are validated on the host
     for flux, suth, tref, want in ((rok.ROE, 0.0, 1.0, rok.ROK_OK), (2, 0.0, 1.0, rok.ROK_EINVAL),
