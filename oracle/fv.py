@@ -29,7 +29,10 @@ the paper leaves open:
   face gradients: two-point difference along the face normal, the average of
   the two neighbouring cells' central differences along the face;
 * assembly f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d over d = x, y, z in
-  that order, with 1/dx_d rounded once.
+  that order, with 1/dx_d rounded once;
+* curvilinear grids (2-D Euler; the paper's solver works on curvilinear
+  structured grids, Sec. 3.2): face vectors from the node coordinates, the
+  flux in the face frame, `metrics` and `_residual_curvilinear`.
 
 Every formula below is written in one fixed operation order (no fused
 multiply-add; left-to-right evaluation), which is the natural reading of the
@@ -68,6 +71,7 @@ class Problem:
     flux: str = RUSANOV
     sutherland: float = 0.0   # S / T_ref of Sutherland's law; 0: constant viscosity mu
     t_ref: float = 1.0        # temperature at which the viscosity is mu
+    nodes: tuple = None       # 2-D curvilinear grid: node coordinates (x, y), arrays [j][i]
     dtype: torch.dtype = field(default=torch.float64)
 
     @property
@@ -331,6 +335,70 @@ def _viscous_flux(P: Problem, r, vel, p, d):
     return [torch.zeros_like(r)] + tau + [energy]
 
 
+def metrics(P: Problem):
+    """Face vectors and inverse cell areas of a 2-D curvilinear periodic grid.
+
+    Cell (i, j) has the nodes p0 = (i, j), p1 = (i+1, j), p2 = (i+1, j+1) and
+    p3 = (i, j+1) (periodic offsets Lx, Ly applied past the last node).  Its
+    east face (towards i+1) is the edge p1 -> p2 and its north face (towards
+    j+1) the edge p3 -> p2; the face vectors are those edges turned by 90
+    degrees (length = face length, pointing to increasing i or j), and the
+    area is half the cross product of the diagonals.  Returns torch tensors
+    (Sx_e, Sy_e, Sx_n, Sy_n, 1/A), each [j][i]."""
+    xn, yn = (np.asarray(a, dtype=np.float64) for a in P.nodes)
+    Lx, Ly = P.hi[0] - P.lo[0], P.hi[1] - P.lo[1]
+
+    def node(di, dj):
+        x = np.roll(np.roll(xn, -di, axis=1), -dj, axis=0).copy()
+        y = np.roll(np.roll(yn, -di, axis=1), -dj, axis=0).copy()
+        if di:
+            x[:, -di:] = x[:, -di:] + Lx
+        if dj:
+            y[-dj:, :] = y[-dj:, :] + Ly
+        return x, y
+
+    x0, y0 = xn, yn
+    x1, y1 = node(1, 0)
+    x2, y2 = node(1, 1)
+    x3, y3 = node(0, 1)
+    sxe = y2 - y1
+    sye = x1 - x2
+    sxn = y3 - y2
+    syn = x2 - x3
+    area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0))
+    return tuple(torch.from_numpy(a) for a in (sxe, sye, sxn, syn, 1.0 / area))
+
+
+def _residual_curvilinear(P: Problem, y: torch.Tensor) -> torch.Tensor:
+    """f on a 2-D curvilinear periodic grid (Euler physics): reconstruction in
+    index space as on the Cartesian grid, then at each face the states are
+    rotated into the face frame (n = S/|S|: normal and tangential momentum and
+    velocity), the one-dimensional numerical flux is taken there, rotated back
+    and scaled by the face length; f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / A_c."""
+    if P.ndim != 2 or P.physics != EULER:
+        raise ValueError("curvilinear grids: 2-D Euler physics only")
+    U = y.reshape(P.shape)
+    U = [U[m] for m in range(P.nvar)]
+    r, vel, p = primitives(P, U)
+    sxe, sye, sxn, syn, inva = metrics(P)
+    out = None
+    for d in range(2):
+        (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, d)
+        sx, sy = (sxe, sye) if d == 0 else (sxn, syn)
+        ln = _sqrt(sx * sx + sy * sy)
+        nx = sx / ln
+        ny = sy / ln
+        vLr = [vL[0] * nx + vL[1] * ny, vL[1] * nx - vL[0] * ny]
+        vRr = [vR[0] * nx + vR[1] * ny, vR[1] * nx - vR[0] * ny]
+        ULr = [UL[0], UL[1] * nx + UL[2] * ny, UL[2] * nx - UL[1] * ny, UL[3]]
+        URr = [UR[0], UR[1] * nx + UR[2] * ny, UR[2] * nx - UR[1] * ny, UR[3]]
+        Fr = face_flux(P, ULr, rL, vLr, pL, URr, rR, vRr, pR, 0)
+        Fh = [Fr[0] * ln, (Fr[1] * nx - Fr[2] * ny) * ln, (Fr[1] * ny + Fr[2] * nx) * ln, Fr[3] * ln]
+        term = torch.stack([(_at(Fh[m], -1, d) - Fh[m]) * inva for m in range(P.nvar)])
+        out = term if out is None else out + term
+    return out.reshape(-1)
+
+
 def residual(P: Problem, y: torch.Tensor, part: str = "all") -> torch.Tensor:
     """f(y) for a flat state vector y of length P.size (float64).
 
@@ -338,6 +406,10 @@ def residual(P: Problem, y: torch.Tensor, part: str = "all") -> torch.Tensor:
     split output of the residual: the two parts add up to f)."""
     if part not in ("all", "inviscid", "viscous"):
         raise ValueError(f"unknown part {part!r}")
+    if P.nodes is not None:
+        if part != "all":
+            raise ValueError("curvilinear grids: the whole residual only")
+        return _residual_curvilinear(P, y)
     U = y.reshape(P.shape)
     U = [U[m] for m in range(P.nvar)]
     r, vel, p = primitives(P, U)

@@ -62,6 +62,43 @@ def _pack(pb, rho, vel, p):
 
 
 # ---------------------------------------------------------------------------
+# Curvilinear (mapped) periodic grids, 2-D
+# ---------------------------------------------------------------------------
+
+def warped_nodes(pb, amplitude=0.06):
+    """Node coordinates (x, y), arrays indexed [j][i] (node i along x, j along y),
+    of a smoothly warped periodic grid on the problem's box:
+    x = X + a Lx sin(2 pi (Y - lo_y) / Ly),  y = Y + a Ly sin(2 pi (X - lo_x) / Lx),
+    (X, Y) the Cartesian node positions.  Periodic: node (i + nx, j) is node
+    (i, j) shifted by (Lx, 0), node (i, j + ny) by (0, Ly).  The mapping is
+    one-to-one for 2 pi a < 1."""
+    nx, ny = pb["n"][:2]
+    lo, hi = pb["lo"], pb["hi"]
+    Lx, Ly = hi[0] - lo[0], hi[1] - lo[1]
+    X, Y = np.meshgrid(lo[0] + np.arange(nx) * (Lx / nx), lo[1] + np.arange(ny) * (Ly / ny))
+    x = X + amplitude * Lx * np.sin(2.0 * math.pi * (Y - lo[1]) / Ly)
+    y = Y + amplitude * Ly * np.sin(2.0 * math.pi * (X - lo[0]) / Lx)
+    return x.astype(np.float64), y.astype(np.float64)
+
+
+def cartesian_nodes(pb):
+    """The nodes of the problem's uniform Cartesian grid in the same layout."""
+    return warped_nodes(pb, 0.0)
+
+
+def node_centres(pb, xn, yn):
+    """Cell centres (mean of the four nodes, periodic offsets applied)."""
+    Lx, Ly = pb["hi"][0] - pb["lo"][0], pb["hi"][1] - pb["lo"][1]
+    x1 = np.roll(xn, -1, axis=1); x1[:, -1] += Lx
+    y2 = np.roll(yn, -1, axis=0); y2[-1, :] += Ly
+    x3 = np.roll(x1, -1, axis=0)
+    y3 = np.roll(yn, -1, axis=1); y3 = np.roll(y3, -1, axis=0); y3[-1, :] += Ly
+    x2 = np.roll(xn, -1, axis=0)
+    y1 = np.roll(yn, -1, axis=1)
+    return 0.25 * (xn + x1 + x2 + x3), 0.25 * (yn + y1 + y2 + y3)
+
+
+# ---------------------------------------------------------------------------
 # Isentropic vortex
 # ---------------------------------------------------------------------------
 
@@ -75,12 +112,13 @@ def vortex_freestream(gamma=GAMMA, mach=0.5):
     return speed / math.sqrt(2.0), speed / math.sqrt(2.0)
 
 
-def vortex_state(pb, t=0.0, strength=5.0, mach=0.5):
+def vortex_state(pb, t=0.0, strength=5.0, mach=0.5, centres=None):
     """Vortex centred at the origin at t = 0, translated by the free stream
     (minimum-image periodic displacement).  At t > 0 this is the exact
-    solution of the Euler equations up to the periodic Gaussian tail."""
+    solution of the Euler equations up to the periodic Gaussian tail.
+    centres: optional (x, y) cell centres of a curvilinear grid."""
     g = pb["gamma"]
-    x, y = _mesh(pb)
+    x, y = _mesh(pb) if centres is None else centres
     uinf, vinf = vortex_freestream(g, mach)
     Lx = pb["hi"][0] - pb["lo"][0]
     Ly = pb["hi"][1] - pb["lo"][1]
