@@ -138,6 +138,31 @@ void rok_destroy(rok_ctx* ctx);
  * ROK_EINVAL for an unknown path. */
 rok_status rok_set_mgs_path(rok_ctx* ctx, int path);
 
+/*
+ * Curvilinear grids (2-D, ROK_EULER): the box [lo, hi] becomes a periodic
+ * structured grid with the given nodes (the paper's residual works on
+ * curvilinear structured grids, Sec. 3.2).  xn, yn: n[0] * n[1] doubles each,
+ * device memory, node (i, j) at j * n[0] + i; node (i + n[0], j) is node (i, j)
+ * moved by (hi[0] - lo[0], 0) and node (i, j + n[1]) by (0, hi[1] - lo[1]).
+ * Cell (i, j) has the nodes (i, j), (i+1, j), (i+1, j+1), (i, j+1); its faces
+ * carry the edge vectors turned by 90 degrees and its area is half the cross
+ * product of its diagonals.  The call computes these metrics into `metrics`
+ * (rok_grid_metric_bytes(ctx) bytes of device memory owned by the caller, which
+ * must stay valid while the context uses it) on `stream`; afterwards the
+ * residual, both Jacobian-vector products, rok_arnoldi, rok_step and
+ * rok_integrate_adaptive evaluate f on the curvilinear grid: reconstruction in
+ * index space, then at each face the states are rotated into the face frame
+ * (normal and tangential momentum and velocity), the flux is taken there,
+ * rotated back and scaled by the face length, and
+ * f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / A_c.  All three pointers null:
+ * back to the Cartesian grid.  FP64 precision only (the FP32 form returns
+ * ROK_EUNSUPPORTED); the adjoint entry points return ROK_EUNSUPPORTED.
+ */
+rok_status rok_set_grid(rok_ctx* ctx, const double* xn, const double* yn, double* metrics, void* stream);
+
+/* Bytes of the metric buffer of rok_set_grid (0 unless 2-D Euler). */
+size_t rok_grid_metric_bytes(const rok_ctx* ctx);
+
 /* N, the length of a state vector. */
 size_t rok_state_size(const rok_ctx* ctx);
 

@@ -39,7 +39,7 @@ bool fp32(const rok_ctx* c) { return c->pb.precision == ROK_FP32_RESIDUAL; }
 
 // The adjoint kernels cover Euler physics with Rusanov's flux in FP64.
 bool adjoint_supported(const rok_ctx* c) {
-    return c->pb.physics == ROK_EULER && c->pb.flux == ROK_RUSANOV && !fp32(c);
+    return c->pb.physics == ROK_EULER && c->pb.flux == ROK_RUSANOV && !fp32(c) && !c->G.metric;
 }
 
 rok::ResArgs plain_args(const double* y, void* out) {
@@ -263,6 +263,25 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
 }
 
 void rok_destroy(rok_ctx* c) { delete c; }
+
+size_t rok_grid_metric_bytes(const rok_ctx* c) {
+    if (!c || c->pb.ndim != 2 || c->pb.physics != ROK_EULER) return 0;
+    return sizeof(double) * 5 * (size_t)c->G.ncell;
+}
+
+rok_status rok_set_grid(rok_ctx* c, const double* xn, const double* yn, double* metrics, void* stream) {
+    if (!c) return ROK_EINVAL;
+    if (!xn && !yn && !metrics) {
+        c->G.metric = nullptr;
+        return ROK_OK;
+    }
+    if (c->pb.ndim != 2 || c->pb.physics != ROK_EULER) return ROK_EUNSUPPORTED;
+    if (!xn || !yn || !metrics || !aligned(xn, 8) || !aligned(yn, 8) || !aligned(metrics, 8)) return ROK_EINVAL;
+    const double Lx = c->pb.hi[0] - c->pb.lo[0], Ly = c->pb.hi[1] - c->pb.lo[1];
+    ROK_TRY(rok::launch_metrics(xn, yn, c->pb.n[0], c->pb.n[1], Lx, Ly, metrics, (hipStream_t)stream));
+    c->G.metric = metrics;
+    return ROK_OK;
+}
 
 rok_status rok_set_mgs_path(rok_ctx* c, int path) {
     if (!c || (path != ROK_MGS_AUTO && path != ROK_MGS_PER_PASS && path != ROK_MGS_RESIDENT)) return ROK_EINVAL;

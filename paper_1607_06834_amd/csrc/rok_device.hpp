@@ -32,6 +32,7 @@ struct Geom {
     int flux;                 // inviscid flux: 0 Rusanov, 1 Roe
     int suth;                 // Sutherland's law (else constant mu)
     double suth_s, suth_one_s, t_ref, kden;   // S / T_ref, 1 + S / T_ref, T_ref, (gamma - 1) Pr
+    const double* metric;     // 2-D curvilinear grid: Sx_e, Sy_e, Sx_n, Sy_n, 1/A (ncell each), else null
 };
 
 // Residual-kernel inputs: the stage state Y = y + sum_t cs[t] xs[t]

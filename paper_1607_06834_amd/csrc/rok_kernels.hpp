@@ -8,6 +8,9 @@ namespace rok {
 // Residual family (rok_residual.hip).  kind: 0 = F = f(Y), 1 = FD product,
 // 2 = tangent product.  fp32: compute in float.  out_double: write doubles
 // even when computing in float (internal FP64 consumers).
+// Face vectors and inverse areas of a 2-D curvilinear periodic grid (5 x nx*ny doubles).
+hipError_t launch_metrics(const double* xn, const double* yn, int nx, int ny, double Lx, double Ly, double* out,
+                          hipStream_t st);
 // Fills `bytes` bytes (a multiple of 4) at p with zeros (a kernel, not a memset).
 hipError_t launch_zero(void* p, long bytes, hipStream_t st);
 hipError_t launch_residual(const Geom& G, int recon, bool ns, bool fp32, int kind, bool out_double,

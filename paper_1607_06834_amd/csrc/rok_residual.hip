@@ -115,7 +115,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-template <int D, int RECON, bool NSV, int FLUX, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
+template <int D, int RECON, bool NSV, int FLUX, int GEO, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt0, int nt1) {
     using T = Tile<D, TX, TY, TZ, (RECON == 0 ? 1 : 2)>;
     using R = typename Sc<S>::R;
@@ -334,7 +334,34 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 to_conserved<D>(G, rL, vL, pL, UL);
                 to_conserved<D>(G, rR, vR, pR, UR);
             }
-            if constexpr (!PERT) num_flux<D, FLUX>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+            if constexpr (GEO == 1) {
+                // curvilinear: the flux in the face frame n = S / |S|, rotated back, times |S|
+                const int ga = wrap(y0 + fy - (d == 1), n1) * n0 + wrap(x0 + fx - (d == 0), n0);
+                const double sx = G.metric[(long)(2 * d) * G.ncell + ga];
+                const double sy = G.metric[(long)(2 * d + 1) * G.ncell + ga];
+                const double ln = sqrt(sx * sx + sy * sy);
+                const double nx = sx / ln, ny = sy / ln;
+                S vLr[D], vRr[D], ULr[NV], URr[NV], Fr[NV];
+                vLr[0] = vL[0] * nx + vL[1] * ny;
+                vLr[1] = vL[1] * nx - vL[0] * ny;
+                vRr[0] = vR[0] * nx + vR[1] * ny;
+                vRr[1] = vR[1] * nx - vR[0] * ny;
+                ULr[0] = UL[0];
+                ULr[1] = UL[1] * nx + UL[2] * ny;
+                ULr[2] = UL[2] * nx - UL[1] * ny;
+                ULr[3] = UL[3];
+                URr[0] = UR[0];
+                URr[1] = UR[1] * nx + UR[2] * ny;
+                URr[2] = UR[2] * nx - UR[1] * ny;
+                URr[3] = UR[3];
+                num_flux<D, FLUX>(G, 0, ULr, rL, vLr, pL, URr, rR, vRr, pR, Fr);
+                Fh[0] = Fr[0] * ln;
+                Fh[1] = (Fr[1] * nx - Fr[2] * ny) * ln;
+                Fh[2] = (Fr[1] * ny + Fr[2] * nx) * ln;
+                Fh[3] = Fr[3] * ln;
+            } else if constexpr (!PERT) {
+                num_flux<D, FLUX>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+            }
             if constexpr (NSV) {
                 if (A.viscous_only) {
 #pragma unroll
@@ -400,9 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             int cy = (cell / TX) % TY;
             int cz = cell / (TX * TY);
             int fl = (cz * FY + cy) * FX + cx;
+            R icell = inv;
+            if constexpr (GEO == 1) icell = G.metric[4L * G.ncell + wrap(y0 + cy, n1) * n0 + wrap(x0 + cx, n0)];
 #pragma unroll
             for (int m = 0; m < NV; ++m) {
-                S term = (fb[m][fl] - fb[m][fl + fs]) * inv;
+                S term = (fb[m][fl] - fb[m][fl + fs]) * icell;
                 res[k][m] = (d == 0) ? term : res[k][m] + term;
             }
         }
@@ -437,46 +466,82 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 // Launchers
 // ---------------------------------------------------------------------------
 
-template <int D, int RECON, bool NSV, int FLUX, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
+template <int D, int RECON, bool NSV, int FLUX, int GEO, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
 static hipError_t launch_t(const Geom& G, const ResArgs& A, hipStream_t st) {
     int nt0 = (G.n[0] + TX - 1) / TX;
     int nt1 = (G.n[1] + TY - 1) / TY;
     int nt2 = (D == 3) ? (G.n[2] + TZ - 1) / TZ : 1;
     long nb = (long)nt0 * nt1 * nt2;
     if (nb <= 0 || nb > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_residual<D, RECON, NSV, FLUX, S, MODE, OUT, TX, TY, TZ>), dim3((unsigned)nb), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((k_residual<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, TX, TY, TZ>), dim3((unsigned)nb), dim3(kThreads), 0, st,
                        G, A, nt0, nt1);
     return hipGetLastError();
 }
 
 // Tile shape per variant: bigger tiles where the LDS footprint allows.
-template <int D, int RECON, bool NSV, int FLUX, typename S, int MODE, typename OUT>
+template <int D, int RECON, bool NSV, int FLUX, int GEO, typename S, int MODE, typename OUT>
 static hipError_t launch_v(const Geom& G, const ResArgs& A, hipStream_t st) {
     constexpr bool wide = sizeof(S) <= 8;   // double or float (not a dual number)
     if constexpr (D == 2) {
         if constexpr (RECON == 1 && sizeof(S) == 8 && sizeof(typename Sc<S>::R) == 8)
-            return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 16, 16, 1>(G, A, st);   // FP64 (measured best)
-        else if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 32, 16, 1>(G, A, st);
-        else return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 32, 8, 1>(G, A, st);
+            return launch_t<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, 16, 16, 1>(G, A, st);   // FP64 (measured best)
+        else if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, 32, 16, 1>(G, A, st);
+        else return launch_t<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, 32, 8, 1>(G, A, st);
     } else {
-        return launch_t<D, RECON, NSV, FLUX, S, MODE, OUT, 16, 4, 4>(G, A, st);
+        return launch_t<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, 16, 4, 4>(G, A, st);
     }
 }
 
-template <int D, int RECON, bool NSV, int FLUX>
+template <int D, int RECON, bool NSV, int FLUX, int GEO>
 static hipError_t dispatch_prec(const Geom& G, const ResArgs& A, int kind, bool fp32, bool out_double, hipStream_t st) {
     if (!fp32) {
-        if (kind == MODE_PLAIN) return launch_v<D, RECON, NSV, FLUX, double, MODE_PLAIN, double>(G, A, st);
-        if (kind == MODE_FD) return launch_v<D, RECON, NSV, FLUX, double, MODE_FD, double>(G, A, st);
-        return launch_v<D, RECON, NSV, FLUX, Dual<double>, MODE_TAN, double>(G, A, st);
+        if (kind == MODE_PLAIN) return launch_v<D, RECON, NSV, FLUX, GEO, double, MODE_PLAIN, double>(G, A, st);
+        if (kind == MODE_FD) return launch_v<D, RECON, NSV, FLUX, GEO, double, MODE_FD, double>(G, A, st);
+        return launch_v<D, RECON, NSV, FLUX, GEO, Dual<double>, MODE_TAN, double>(G, A, st);
     }
     if (kind == MODE_FD) return hipErrorNotSupported;
     if (kind == MODE_PLAIN) {
-        if (out_double) return launch_v<D, RECON, NSV, FLUX, float, MODE_PLAIN, double>(G, A, st);
-        return launch_v<D, RECON, NSV, FLUX, float, MODE_PLAIN, float>(G, A, st);
+        if (out_double) return launch_v<D, RECON, NSV, FLUX, GEO, float, MODE_PLAIN, double>(G, A, st);
+        return launch_v<D, RECON, NSV, FLUX, GEO, float, MODE_PLAIN, float>(G, A, st);
     }
-    if (out_double) return launch_v<D, RECON, NSV, FLUX, Dual<float>, MODE_TAN, double>(G, A, st);
-    return launch_v<D, RECON, NSV, FLUX, Dual<float>, MODE_TAN, float>(G, A, st);
+    if (out_double) return launch_v<D, RECON, NSV, FLUX, GEO, Dual<float>, MODE_TAN, double>(G, A, st);
+    return launch_v<D, RECON, NSV, FLUX, GEO, Dual<float>, MODE_TAN, float>(G, A, st);
+}
+
+// Metrics of a 2-D curvilinear periodic grid from its nodes (x, y indexed
+// j * nx + i; node (i + nx, j) is node (i, j) + (Lx, 0), node (i, j + ny) is
+// node (i, j) + (0, Ly)): for cell (i, j) with nodes p0 = (i, j), p1 = (i+1, j),
+// p2 = (i+1, j+1), p3 = (i, j+1), the east face vector (y2 - y1, x1 - x2), the
+// north face vector (y3 - y2, x2 - x3) and 1 / A with
+// A = ((x2 - x0)(y3 - y1) - (x3 - x1)(y2 - y0)) / 2; five arrays of ncell.
+__global__ __launch_bounds__(256) void k_metrics(const double* xn, const double* yn, int nx, int ny, double Lx,
+                                                 double Ly, double* out) {
+    const long c = (long)blockIdx.x * 256 + threadIdx.x;
+    const long ncell = (long)nx * ny;
+    if (c >= ncell) return;
+    const int i = (int)(c % nx), j = (int)(c / nx);
+    const bool ei = (i + 1 == nx), ej = (j + 1 == ny);
+    const int i1 = ei ? 0 : i + 1, j1 = ej ? 0 : j + 1;
+    const double x0 = xn[c], y0 = yn[c];
+    const double x1 = ei ? xn[(long)j * nx + i1] + Lx : xn[(long)j * nx + i1];
+    const double y1 = yn[(long)j * nx + i1];
+    const double x2 = ei ? xn[(long)j1 * nx + i1] + Lx : xn[(long)j1 * nx + i1];
+    const double y2 = ej ? yn[(long)j1 * nx + i1] + Ly : yn[(long)j1 * nx + i1];
+    const double x3 = xn[(long)j1 * nx + i];
+    const double y3 = ej ? yn[(long)j1 * nx + i] + Ly : yn[(long)j1 * nx + i];
+    out[c] = y2 - y1;
+    out[ncell + c] = x1 - x2;
+    out[2 * ncell + c] = y3 - y2;
+    out[3 * ncell + c] = x2 - x3;
+    const double area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0));
+    out[4 * ncell + c] = 1.0 / area;
+}
+
+hipError_t launch_metrics(const double* xn, const double* yn, int nx, int ny, double Lx, double Ly, double* out,
+                          hipStream_t st) {
+    const long n = (long)nx * ny;
+    hipLaunchKernelGGL(k_metrics, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xn, yn, nx, ny, Lx, Ly, out);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_zero(unsigned* p, long n) {
@@ -492,10 +557,25 @@ hipError_t launch_zero(void* p, long bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Curvilinear grids: 2-D Euler physics in FP64 (value, FD and tangent kernels).
+template <int RECON, int FLUX>
+static hipError_t dispatch_curv(const Geom& G, const ResArgs& A, int kind, hipStream_t st) {
+    if (kind == MODE_PLAIN) return launch_v<2, RECON, false, FLUX, 1, double, MODE_PLAIN, double>(G, A, st);
+    if (kind == MODE_FD) return launch_v<2, RECON, false, FLUX, 1, double, MODE_FD, double>(G, A, st);
+    return launch_v<2, RECON, false, FLUX, 1, Dual<double>, MODE_TAN, double>(G, A, st);
+}
+
 template <int D, int RECON, bool NSV>
 static hipError_t dispatch_flux(const Geom& G, const ResArgs& A, int kind, bool fp32, bool out_double, hipStream_t st) {
-    if (G.flux == 1) return dispatch_prec<D, RECON, NSV, 1>(G, A, kind, fp32, out_double, st);
-    return dispatch_prec<D, RECON, NSV, 0>(G, A, kind, fp32, out_double, st);
+    if (G.metric) {
+        if constexpr (D == 2 && !NSV) {
+            if (fp32) return hipErrorNotSupported;
+            return G.flux == 1 ? dispatch_curv<RECON, 1>(G, A, kind, st) : dispatch_curv<RECON, 0>(G, A, kind, st);
+        }
+        return hipErrorNotSupported;
+    }
+    if (G.flux == 1) return dispatch_prec<D, RECON, NSV, 1, 0>(G, A, kind, fp32, out_double, st);
+    return dispatch_prec<D, RECON, NSV, 0, 0>(G, A, kind, fp32, out_double, st);
 }
 
 hipError_t launch_residual(const Geom& G, int recon, bool ns, bool fp32, int kind, bool out_double,

@@ -27,7 +27,7 @@ MAX_STAGES, MAX_M = 8, 64
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
            "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
            "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
-           "rok_eigs", "rok_eigs_workspace_bytes", "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
+           "rok_eigs", "rok_eigs_workspace_bytes", "rok_set_grid", "rok_grid_metric_bytes", "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
 MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
@@ -99,6 +99,10 @@ def load_library(path: str = LIB_PATH):
     lib.rok_step_vjp_adjoint_bytes.argtypes = [vp, i, i]
     lib.rok_step_vjp_adjoint_bytes.restype = sz
     pd, pi = ctypes.POINTER(d), ctypes.POINTER(i)
+    lib.rok_set_grid.argtypes = [vp, vp, vp, vp, vp]
+    lib.rok_set_grid.restype = i
+    lib.rok_grid_metric_bytes.argtypes = [vp]
+    lib.rok_grid_metric_bytes.restype = sz
     lib.rok_eigs.argtypes = [vp, vp, vp, i, i, i, d, pd, pd, pd, pi, vp, sz, vp]
     lib.rok_eigs.restype = i
     lib.rok_eigs_workspace_bytes.argtypes = [vp, i, i]
@@ -283,6 +287,24 @@ class Rok:
                              ws.numel(), _stream()), "rok_step")
         self._last_step_ws = ws
         return y1
+
+    def set_grid(self, xn, yn):
+        """Use a 2-D curvilinear periodic grid with these node coordinates (arrays [j][i];
+        rok_set_grid); None, None: back to the Cartesian grid."""
+        if xn is None and yn is None:
+            _check(_lib.rok_set_grid(self._ctx, None, None, None, _stream()), "rok_set_grid")
+            self._metrics = None
+            return
+        nb = int(_lib.rok_grid_metric_bytes(self._ctx))
+        if nb == 0:
+            raise ValueError("curvilinear grids need a 2-D Euler problem")
+        xd = torch.as_tensor(xn, dtype=torch.float64).to(self.device).contiguous()
+        yd = torch.as_tensor(yn, dtype=torch.float64).to(self.device).contiguous()
+        if xd.numel() * 5 * 8 != nb or yd.numel() != xd.numel():
+            raise ValueError("node arrays must have n[0] * n[1] entries")
+        met = torch.empty(nb // 8, dtype=torch.float64, device=self.device)
+        _check(_lib.rok_set_grid(self._ctx, _ptr(xd), _ptr(yd), _ptr(met), _stream()), "rok_set_grid")
+        self._metrics = met            # kept alive while the context uses it
 
     def eigs(self, y, v0, k: int = 6, m: int = 40, max_restarts: int = 50, tol: float = 1e-10):
         """k largest-magnitude eigenvalues of J(y) (rok_eigs).  Returns (values as a complex

@@ -1,0 +1,122 @@
+"""Curvilinear (warped periodic) grids on the GPU against the oracle (rok_set_grid).
+
+Same bars as the Cartesian path: metrics, residual and FD products bit for
+bit (the same operation order on both sides), tangent products and exact
+steps to 1e-12, FD steps and a short vortex trajectory bit for bit.  The
+FP32 form and the adjoint refuse curvilinear grids; clearing the grid
+restores the Cartesian residual bit for bit.
+"""
+import sys
+
+import pytest
+import torch
+
+import rok_inputs as ri
+from oracle import fv, rok
+from tests._util import oracle_problem, relerr, t64
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1607_06834_amd import load_library
+    load_library()
+    return torch.device("cuda", 0)
+
+
+def setup(pb, amplitude=0.06, precision="fp64"):
+    from paper_1607_06834_amd import Rok
+    nodes = ri.warped_nodes(pb, amplitude)
+    P = oracle_problem(pb)
+    P.nodes = nodes
+    g = Rok(pb, precision)
+    return P, g, nodes
+
+
+CASES = [(s, r, f) for s in [(6, 5), (37, 21), (70, 33), (256, 192)] for r in ("first", "muscl")
+         for f in ("rusanov", "roe")]
+
+
+@pytest.mark.parametrize("shape,recon,flux", CASES)
+def test_curvilinear_residual_fd_tangent(dev, shape, recon, flux):
+    say("curvilinear", shape, recon, flux)
+    pb = ri.problem(shape, (-1.0, 0.0), (2.0, 1.4), "euler", recon, flux=flux)
+    P, g, nodes = setup(pb)
+    g.set_grid(*nodes)
+    met = g._metrics.cpu().reshape(5, -1)
+    for a, b in zip(met, fv.metrics(P)):
+        assert torch.equal(a, b.reshape(-1))
+    y = t64(ri.smooth_random_state(pb, seed=1, amplitude=0.2))
+    ref = fv.residual(P, y)
+    out = g.residual(y.to(dev)).cpu()
+    assert torch.equal(out, ref), relerr(out, ref)
+    if shape[0] > 100:
+        return
+    v = t64(ri.random_direction(P.size, seed=3))
+    eps = 1.7e-7
+    assert torch.equal(g.jvp(y.to(dev), v.to(dev), "fd", fy=ref.to(dev), eps=eps).cpu(), fv.jvp_fd(P, y, ref, v, eps))
+    assert relerr(g.jvp(y.to(dev), v.to(dev), "exact").cpu(), fv.jvp_exact(P, y, v)) <= 1e-12
+
+
+@pytest.mark.parametrize("mode,recon,M", [("fd", "muscl", 8), ("exact", "muscl", 8), ("fd", "first", 4)])
+def test_curvilinear_step_parity(dev, mode, recon, M):
+    say("curvilinear step", mode, recon, M)
+    pb = ri.vortex_problem(24, recon)
+    pb["n"] = (24, 20)
+    P, g, nodes = setup(pb)
+    g.set_grid(*nodes)
+    c = ri.node_centres(pb, *nodes)
+    y = t64(ri.perturb_density(pb, ri.vortex_state(pb, centres=c), 0.01, seed=12))
+    h = ri.cfl_step(pb, y.numpy(), 2.0)
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, mode)
+    ref = rok.rok_step(f, mv, tab, M, h, y)
+    out = g.step(y.to(dev), h, tab, M, "fd" if mode == "fd" else "exact").cpu()
+    assert relerr(out, ref) <= 1e-12
+    if mode == "fd":
+        assert torch.equal(out, ref)
+
+
+def test_curvilinear_vortex_trajectory(dev):
+    """32^2 first-order vortex on the warped grid, FD products, M = 8, 5 steps at CFL 2, bit for bit."""
+    pb = ri.vortex_problem(32, "first")
+    P, g, nodes = setup(pb)
+    g.set_grid(*nodes)
+    y0 = ri.vortex_state(pb, centres=ri.node_centres(pb, *nodes))
+    h = ri.cfl_step(pb, y0, 2.0)
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, "fd")
+    yr, yg = t64(y0), torch.tensor(y0, device=dev)
+    for n in range(5):
+        yr = rok.rok_step(f, mv, tab, 8, h, yr)
+        yg = g.step(yg, h, tab, 8, "fd")
+        assert torch.equal(yg.cpu(), yr), (n, relerr(yg.cpu(), yr))
+
+
+def test_curvilinear_refusals_and_reset(dev):
+    from paper_1607_06834_amd import Rok
+    from paper_1607_06834_amd.rok import RokError
+    pb = ri.problem((12, 10), (-1.0, 0.0), (2.0, 1.4), "euler", "muscl")
+    nodes = ri.warped_nodes(pb, 0.06)
+    y = torch.tensor(ri.smooth_random_state(pb, seed=1, amplitude=0.2), device=dev)
+    g32 = Rok(pb, "fp32")
+    g32.set_grid(*nodes)
+    with pytest.raises(RokError):
+        g32.residual(y)
+    g = Rok(pb)
+    g.set_grid(*nodes)
+    with pytest.raises(RokError):
+        g.vjp(y, torch.ones_like(y))
+    g.set_grid(None, None)
+    assert torch.equal(g.residual(y).cpu(), fv.residual(oracle_problem(pb), y.cpu()))
+    ns = Rok(ri.problem((12, 10), (0.0, 0.0), (1.0, 1.0), "ns", "muscl", mu=0.05))
+    with pytest.raises(ValueError):
+        ns.set_grid(*nodes)
