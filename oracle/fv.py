@@ -72,6 +72,8 @@ class Problem:
     sutherland: float = 0.0   # S / T_ref of Sutherland's law; 0: constant viscosity mu
     t_ref: float = 1.0        # temperature at which the viscosity is mu
     nodes: tuple = None       # 2-D curvilinear grid: node coordinates (x, y), arrays [j][i]
+    farfield: tuple = None    # O-grid (periodic in i, wall at j = 0, far field past the last row):
+                              # the free-stream conserved state (rho, rho u, rho v, E)
     dtype: torch.dtype = field(default=torch.float64)
 
     @property
@@ -369,6 +371,93 @@ def metrics(P: Problem):
     return tuple(torch.from_numpy(a) for a in (sxe, sye, sxn, syn, 1.0 / area))
 
 
+def ogrid_metrics(P: Problem):
+    """Face vectors and inverse areas of an O-grid: nodes (x, y) indexed [j][i] with
+    j = 0..ny (row 0 on the wall, row ny on the far-field boundary) and i periodic
+    without offset (node nx is node 0).  Same conventions as `metrics`; also the
+    wall face vectors (the south faces of row 0, pointing into the domain)."""
+    xn, yn = (np.asarray(a, dtype=np.float64) for a in P.nodes)
+    r1 = lambda a: np.roll(a, -1, axis=1)
+    x0, y0 = xn[:-1], yn[:-1]
+    x1, y1 = r1(xn)[:-1], r1(yn)[:-1]
+    x2, y2 = r1(xn)[1:], r1(yn)[1:]
+    x3, y3 = xn[1:], yn[1:]
+    sxe = y2 - y1
+    sye = x1 - x2
+    sxn = y3 - y2
+    syn = x2 - x3
+    area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0))
+    wx = yn[0] - r1(yn)[0]
+    wy = r1(xn)[0] - xn[0]
+    return tuple(torch.from_numpy(a) for a in (sxe, sye, sxn, syn, 1.0 / area, wx, wy))
+
+
+def _rotated_flux(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, sx, sy):
+    """Numerical flux through a face with vector (sx, sy): states rotated into the
+    face frame, the one-dimensional flux, rotated back, times the face length."""
+    ln = _sqrt(sx * sx + sy * sy)
+    nx = sx / ln
+    ny = sy / ln
+    vLr = [vL[0] * nx + vL[1] * ny, vL[1] * nx - vL[0] * ny]
+    vRr = [vR[0] * nx + vR[1] * ny, vR[1] * nx - vR[0] * ny]
+    ULr = [UL[0], UL[1] * nx + UL[2] * ny, UL[2] * nx - UL[1] * ny, UL[3]]
+    URr = [UR[0], UR[1] * nx + UR[2] * ny, UR[2] * nx - UR[1] * ny, UR[3]]
+    Fr = face_flux(P, ULr, rL, vLr, pL, URr, rR, vRr, pR, 0)
+    return [Fr[0] * ln, (Fr[1] * nx - Fr[2] * ny) * ln, (Fr[1] * ny + Fr[2] * nx) * ln, Fr[3] * ln]
+
+
+def _residual_ogrid(P: Problem, y: torch.Tensor) -> torch.Tensor:
+    """f on an O-grid around a body (2-D Euler): periodic in i; along j the faces
+    j + 1/2 for j = -1 (the wall: a slip wall carries the pressure of the first
+    cell, Fhat = (0, p S, 0)), 0..ny-2 (interior; MUSCL slopes that would reach
+    past the wall or the far field are zero) and ny - 1 (the far field: the
+    numerical flux between the last cell and the free stream)."""
+    if P.ndim != 2 or P.physics != EULER:
+        raise ValueError("O-grids: 2-D Euler physics only")
+    nx, ny = P.n
+    U = y.reshape(P.shape)
+    U = [U[m] for m in range(P.nvar)]
+    r, vel, p = primitives(P, U)
+    sxe, sye, sxn, syn, inva, wx, wy = ogrid_metrics(P)
+    # i direction: periodic, as on the curvilinear box
+    (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, 0)
+    Fh = _rotated_flux(P, UL, rL, vL, pL, UR, rR, vR, pR, sxe, sye)
+    out = torch.stack([(_at(Fh[m], -1, 0) - Fh[m]) * inva for m in range(P.nvar)])
+    # j direction: faces 1/2 .. ny - 3/2 between rows j and j + 1
+    q = [r] + list(vel) + [p]
+    if P.recon == FIRST_ORDER:
+        qL = [a[:-1] for a in q]
+        qR = [a[1:] for a in q]
+    else:
+        qL, qR = [], []
+        zero = torch.zeros_like(r[:1])
+        for a in q:
+            a0, ap1 = a[:-1], a[1:]
+            sl = torch.cat([zero, _minmod(a[1:-1] - a[:-2], a[2:] - a[1:-1])])       # row 0: no slope
+            sr = torch.cat([_minmod(a[1:-1] - a[:-2], a[2:] - a[1:-1]), zero])       # row ny-1: no slope
+            qL.append(a0 + 0.5 * sl)
+            qR.append(ap1 - 0.5 * sr)
+    rL, vL, pL = qL[0], qL[1:3], qL[3]
+    rR, vR, pR = qR[0], qR[1:3], qR[3]
+    if P.recon == FIRST_ORDER:
+        ULc = [u[:-1] for u in U]
+        URc = [u[1:] for u in U]
+    else:
+        ULc = conserved(P, rL, vL, pL)
+        URc = conserved(P, rR, vR, pR)
+    Fi = _rotated_flux(P, ULc, rL, vL, pL, URc, rR, vR, pR, sxn[:-1], syn[:-1])
+    # wall and far field
+    zw = torch.zeros_like(wx)
+    Fw = [zw, p[0] * wx, p[0] * wy, zw]
+    Uf = [torch.full_like(r[-1], float(v)) for v in P.farfield]
+    rf, vf, pf = primitives(P, Uf)
+    Ub = [u[-1] for u in U]
+    Ff = _rotated_flux(P, Ub, r[-1], [v[-1] for v in vel], p[-1], Uf, rf, vf, pf, sxn[-1], syn[-1])
+    Fj = [torch.cat([Fw[m][None], Fi[m], Ff[m][None]]) for m in range(P.nvar)]    # faces j - 1/2, j = 0..ny
+    out = out + torch.stack([(Fj[m][:-1] - Fj[m][1:]) * inva for m in range(P.nvar)])
+    return out.reshape(-1)
+
+
 def _residual_curvilinear(P: Problem, y: torch.Tensor) -> torch.Tensor:
     """f on a 2-D curvilinear periodic grid (Euler physics): reconstruction in
     index space as on the Cartesian grid, then at each face the states are
@@ -409,6 +498,8 @@ def residual(P: Problem, y: torch.Tensor, part: str = "all") -> torch.Tensor:
     if P.nodes is not None:
         if part != "all":
             raise ValueError("curvilinear grids: the whole residual only")
+        if P.farfield is not None:
+            return _residual_ogrid(P, y)
         return _residual_curvilinear(P, y)
     U = y.reshape(P.shape)
     U = [U[m] for m in range(P.nvar)]

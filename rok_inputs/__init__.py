@@ -86,6 +86,34 @@ def cartesian_nodes(pb):
     return warped_nodes(pb, 0.0)
 
 
+def cylinder_ogrid(nx, ny, radius=0.5, far=10.0, recon="first", flux="rusanov"):
+    """O-grid around a circular cylinder: nodes x(i, j), y(i, j) (arrays [j][i],
+    j = 0..ny) at angle -2 pi i / nx (clockwise, so that (i, j) is right-handed)
+    and radius r_j = radius q^j growing geometrically to `far` (thin cells at the
+    wall).  Returns (problem with n = (nx, ny), (x, y))."""
+    q = (far / radius) ** (1.0 / ny)
+    rj = radius * q ** np.arange(ny + 1)
+    th = -2.0 * math.pi * np.arange(nx) / nx
+    x = rj[:, None] * np.cos(th)[None, :]
+    y = rj[:, None] * np.sin(th)[None, :]
+    pb = problem((nx, ny), (0.0, 0.0), (1.0, 1.0), "euler", recon, flux=flux)
+    return pb, (x.astype(np.float64), y.astype(np.float64))
+
+
+def ogrid_centres(xn, yn):
+    """Cell centres of an O-grid (mean of the four nodes; i periodic, no offset)."""
+    r1 = lambda a: np.roll(a, -1, axis=1)
+    return (0.25 * (xn[:-1] + r1(xn)[:-1] + r1(xn)[1:] + xn[1:]),
+            0.25 * (yn[:-1] + r1(yn)[:-1] + r1(yn)[1:] + yn[1:]))
+
+
+def freestream(gamma=GAMMA, mach=0.3, rho=1.0, p=1.0, angle=0.0):
+    """Conserved free-stream state (rho, rho u, rho v, E) at the given Mach number."""
+    c = math.sqrt(gamma * p / rho)
+    u, v = mach * c * math.cos(angle), mach * c * math.sin(angle)
+    return (rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v))
+
+
 def node_centres(pb, xn, yn):
     """Cell centres (mean of the four nodes, periodic offsets applied)."""
     Lx, Ly = pb["hi"][0] - pb["lo"][0], pb["hi"][1] - pb["lo"][1]
