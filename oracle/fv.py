@@ -411,7 +411,8 @@ def _residual_ogrid(P: Problem, y: torch.Tensor) -> torch.Tensor:
     j + 1/2 for j = -1 (the wall: a slip wall carries the pressure of the first
     cell, Fhat = (0, p S, 0)), 0..ny-2 (interior; MUSCL slopes that would reach
     past the wall or the far field are zero) and ny - 1 (the far field: the
-    numerical flux between the last cell and the free stream)."""
+    numerical flux between the last cell's primitive state, taken back to
+    conserved variables, and the free stream)."""
     if P.ndim != 2 or P.physics != EULER:
         raise ValueError("O-grids: 2-D Euler physics only")
     nx, ny = P.n
@@ -451,8 +452,9 @@ def _residual_ogrid(P: Problem, y: torch.Tensor) -> torch.Tensor:
     Fw = [zw, p[0] * wx, p[0] * wy, zw]
     Uf = [torch.full_like(r[-1], float(v)) for v in P.farfield]
     rf, vf, pf = primitives(P, Uf)
-    Ub = [u[-1] for u in U]
-    Ff = _rotated_flux(P, Ub, r[-1], [v[-1] for v in vel], p[-1], Uf, rf, vf, pf, sxn[-1], syn[-1])
+    vb = [v[-1] for v in vel]
+    Ub = conserved(P, r[-1], vb, p[-1])          # from the last cell's primitive state
+    Ff = _rotated_flux(P, Ub, r[-1], vb, p[-1], Uf, rf, vf, pf, sxn[-1], syn[-1])
     Fj = [torch.cat([Fw[m][None], Fi[m], Ff[m][None]]) for m in range(P.nvar)]    # faces j - 1/2, j = 0..ny
     out = out + torch.stack([(Fj[m][:-1] - Fj[m][1:]) * inva for m in range(P.nvar)])
     return out.reshape(-1)
