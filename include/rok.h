@@ -163,6 +163,30 @@ rok_status rok_set_grid(rok_ctx* ctx, const double* xn, const double* yn, double
 /* Bytes of the metric buffer of rok_set_grid (0 unless 2-D Euler). */
 size_t rok_grid_metric_bytes(const rok_ctx* ctx);
 
+/*
+ * An O-grid around a body (2-D, ROK_EULER; the paper's cylinder cases use such
+ * grids with a wall and a far field, Sec. 4.2): nodes xn, yn of
+ * n[0] * (n[1] + 1) doubles each, device memory, node (i, j) at j * n[0] + i for
+ * j = 0..n[1] (row 0 on the body, row n[1] on the far-field boundary), periodic
+ * in i without offset (node n[0] is node 0).  Cell faces, areas and the flux in
+ * the face frame are as for rok_set_grid; along j the face below row 0 is a
+ * slip wall (it carries the first cell's pressure on the wall face vector), the
+ * face above the last row is the far field (the numerical flux between the last
+ * cell's primitive state, in conserved form, and `freestream`), and MUSCL slopes
+ * that would reach past either boundary are zero.
+ *   freestream: host, 4 doubles, the conserved free-stream state (rho, rho u,
+ *               rho v, E) with rho > 0 and a positive pressure
+ *   metrics:    rok_ogrid_metric_bytes(ctx) bytes of device memory owned by the
+ *               caller (valid while the context uses it)
+ * n[1] >= 2.  Same restrictions as rok_set_grid; rok_set_grid(ctx, 0, 0, 0, s)
+ * returns to the Cartesian grid.
+ */
+rok_status rok_set_ogrid(rok_ctx* ctx, const double* xn, const double* yn, const double* freestream, double* metrics,
+                         void* stream);
+
+/* Bytes of the metric buffer of rok_set_ogrid (0 unless 2-D Euler). */
+size_t rok_ogrid_metric_bytes(const rok_ctx* ctx);
+
 /* N, the length of a state vector. */
 size_t rok_state_size(const rok_ctx* ctx);
 

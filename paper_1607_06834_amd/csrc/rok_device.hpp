@@ -33,6 +33,8 @@ struct Geom {
     int suth;                 // Sutherland's law (else constant mu)
     double suth_s, suth_one_s, t_ref, kden;   // S / T_ref, 1 + S / T_ref, T_ref, (gamma - 1) Pr
     const double* metric;     // 2-D curvilinear grid: Sx_e, Sy_e, Sx_n, Sy_n, 1/A (ncell each), else null
+    int ogrid;                // the curvilinear grid is an O-grid (wall at j = 0, far field past j = n1 - 1):
+    double uinf[4];           //   then metric also holds the wall face vectors, and uinf is the free stream
 };
 
 // Residual-kernel inputs: the stage state Y = y + sum_t cs[t] xs[t]

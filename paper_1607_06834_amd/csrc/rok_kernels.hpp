@@ -11,6 +11,8 @@ namespace rok {
 // Face vectors and inverse areas of a 2-D curvilinear periodic grid (5 x nx*ny doubles).
 hipError_t launch_metrics(const double* xn, const double* yn, int nx, int ny, double Lx, double Ly, double* out,
                           hipStream_t st);
+// O-grid metrics (5 x nx*ny doubles, then 2 x nx wall face vectors).
+hipError_t launch_metrics_ogrid(const double* xn, const double* yn, int nx, int ny, double* out, hipStream_t st);
 // Fills `bytes` bytes (a multiple of 4) at p with zeros (a kernel, not a memset).
 hipError_t launch_zero(void* p, long bytes, hipStream_t st);
 hipError_t launch_residual(const Geom& G, int recon, bool ns, bool fp32, int kind, bool out_double,

@@ -319,11 +319,21 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             } else {
                 const R half = (R)0.5;
                 S qL[NV], qR[NV];
+                // O-grid: no slope across the wall (row 0) or the far field (row n1 - 1)
+                bool flatL = false, flatR = false;
+                if constexpr (GEO == 2) {
+                    if (d == 1) {
+                        flatL = (y0 + fy - 1 == 0);
+                        flatR = (y0 + fy == n1 - 1);
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < NV; ++k) {
                     S am1 = sq[k][ca - sd], a0 = sq[k][ca], ap1 = sq[k][cb], ap2 = sq[k][cb + sd];
-                    qL[k] = a0 + half * minmod(a0 - am1, ap1 - a0);
-                    qR[k] = ap1 - half * minmod(ap1 - a0, ap2 - ap1);
+                    const S sl = flatL ? Sc<S>::make(0.0) : minmod(a0 - am1, ap1 - a0);
+                    const S sr = flatR ? Sc<S>::make(0.0) : minmod(ap1 - a0, ap2 - ap1);
+                    qL[k] = a0 + half * sl;
+                    qR[k] = ap1 - half * sr;
                 }
                 rL = qL[0];
                 rR = qR[0];
@@ -334,7 +344,27 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 to_conserved<D>(G, rL, vL, pL, UL);
                 to_conserved<D>(G, rR, vR, pR, UR);
             }
-            if constexpr (GEO == 1) {
+            int bface = 0;   // O-grid faces along j: 1 wall, 2 far field, 3 outside the grid
+            if constexpr (GEO == 2) {
+                if (d == 1) {
+                    const int gy = y0 + fy;
+                    bface = gy == 0 ? 1 : (gy == n1 ? 2 : (gy > n1 ? 3 : 0));
+                }
+            }
+            if constexpr (GEO == 2) {
+                if (bface == 2) {
+                    // far field: the last cell's primitive state against the free stream
+                    rL = sq[0][ca];
+#pragma unroll
+                    for (int e = 0; e < D; ++e) vL[e] = sq[OFF_VEL + e][ca];
+                    pL = sq[OFF_P][ca];
+                    to_conserved<D>(G, rL, vL, pL, UL);
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) UR[m] = Sc<S>::make(G.uinf[m]);
+                    primitives<D>(G, UR, rR, vR, pR);
+                }
+            }
+            if constexpr (GEO >= 1) {
                 // curvilinear: the flux in the face frame n = S / |S|, rotated back, times |S|
                 const int ga = wrap(y0 + fy - (d == 1), n1) * n0 + wrap(x0 + fx - (d == 0), n0);
                 const double sx = G.metric[(long)(2 * d) * G.ncell + ga];
@@ -359,6 +389,21 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 Fh[1] = (Fr[1] * nx - Fr[2] * ny) * ln;
                 Fh[2] = (Fr[1] * ny + Fr[2] * nx) * ln;
                 Fh[3] = Fr[3] * ln;
+                if constexpr (GEO == 2) {
+                    if (bface == 1) {
+                        // slip wall: the pressure of the first cell on the wall face vector
+                        const int gi = wrap(x0 + fx, n0);
+                        const double wx = G.metric[5L * G.ncell + gi], wy = G.metric[5L * G.ncell + n0 + gi];
+                        const S pw = sq[OFF_P][cb];
+                        Fh[0] = Sc<S>::make(0.0);
+                        Fh[1] = pw * wx;
+                        Fh[2] = pw * wy;
+                        Fh[3] = Sc<S>::make(0.0);
+                    } else if (bface == 3) {
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) Fh[m] = Sc<S>::make(0.0);
+                    }
+                }
             } else if constexpr (!PERT) {
                 num_flux<D, FLUX>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
             }
@@ -428,7 +473,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             int cz = cell / (TX * TY);
             int fl = (cz * FY + cy) * FX + cx;
             R icell = inv;
-            if constexpr (GEO == 1) icell = G.metric[4L * G.ncell + wrap(y0 + cy, n1) * n0 + wrap(x0 + cx, n0)];
+            if constexpr (GEO >= 1) icell = G.metric[4L * G.ncell + wrap(y0 + cy, n1) * n0 + wrap(x0 + cx, n0)];
 #pragma unroll
             for (int m = 0; m < NV; ++m) {
                 S term = (fb[m][fl] - fb[m][fl + fs]) * icell;
@@ -537,6 +582,39 @@ __global__ __launch_bounds__(256) void k_metrics(const double* xn, const double*
     out[4 * ncell + c] = 1.0 / area;
 }
 
+// Metrics of an O-grid: nodes (x, y) indexed j * nx + i for j = 0..ny (row 0 on
+// the wall, row ny on the far-field boundary), i periodic without offset; the
+// same per-cell arrays as k_metrics, then the wall face vectors
+// (y(i, 0) - y(i+1, 0), x(i+1, 0) - x(i, 0)) as two arrays of nx.
+__global__ __launch_bounds__(256) void k_metrics_ogrid(const double* xn, const double* yn, int nx, int ny,
+                                                       double* out) {
+    const long c = (long)blockIdx.x * 256 + threadIdx.x;
+    const long ncell = (long)nx * ny;
+    if (c >= ncell) return;
+    const int i = (int)(c % nx), j = (int)(c / nx);
+    const int i1 = (i + 1 == nx) ? 0 : i + 1;
+    const double x0 = xn[(long)j * nx + i], y0 = yn[(long)j * nx + i];
+    const double x1 = xn[(long)j * nx + i1], y1 = yn[(long)j * nx + i1];
+    const double x2 = xn[(long)(j + 1) * nx + i1], y2 = yn[(long)(j + 1) * nx + i1];
+    const double x3 = xn[(long)(j + 1) * nx + i], y3 = yn[(long)(j + 1) * nx + i];
+    out[c] = y2 - y1;
+    out[ncell + c] = x1 - x2;
+    out[2 * ncell + c] = y3 - y2;
+    out[3 * ncell + c] = x2 - x3;
+    const double area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0));
+    out[4 * ncell + c] = 1.0 / area;
+    if (j == 0) {
+        out[5 * ncell + i] = y0 - y1;
+        out[5 * ncell + nx + i] = x1 - x0;
+    }
+}
+
+hipError_t launch_metrics_ogrid(const double* xn, const double* yn, int nx, int ny, double* out, hipStream_t st) {
+    const long n = (long)nx * ny;
+    hipLaunchKernelGGL(k_metrics_ogrid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xn, yn, nx, ny, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_metrics(const double* xn, const double* yn, int nx, int ny, double Lx, double Ly, double* out,
                           hipStream_t st) {
     const long n = (long)nx * ny;
@@ -558,11 +636,11 @@ hipError_t launch_zero(void* p, long bytes, hipStream_t st) {
 }
 
 // Curvilinear grids: 2-D Euler physics in FP64 (value, FD and tangent kernels).
-template <int RECON, int FLUX>
+template <int RECON, int FLUX, int GEO>
 static hipError_t dispatch_curv(const Geom& G, const ResArgs& A, int kind, hipStream_t st) {
-    if (kind == MODE_PLAIN) return launch_v<2, RECON, false, FLUX, 1, double, MODE_PLAIN, double>(G, A, st);
-    if (kind == MODE_FD) return launch_v<2, RECON, false, FLUX, 1, double, MODE_FD, double>(G, A, st);
-    return launch_v<2, RECON, false, FLUX, 1, Dual<double>, MODE_TAN, double>(G, A, st);
+    if (kind == MODE_PLAIN) return launch_v<2, RECON, false, FLUX, GEO, double, MODE_PLAIN, double>(G, A, st);
+    if (kind == MODE_FD) return launch_v<2, RECON, false, FLUX, GEO, double, MODE_FD, double>(G, A, st);
+    return launch_v<2, RECON, false, FLUX, GEO, Dual<double>, MODE_TAN, double>(G, A, st);
 }
 
 template <int D, int RECON, bool NSV>
@@ -570,7 +648,9 @@ static hipError_t dispatch_flux(const Geom& G, const ResArgs& A, int kind, bool 
     if (G.metric) {
         if constexpr (D == 2 && !NSV) {
             if (fp32) return hipErrorNotSupported;
-            return G.flux == 1 ? dispatch_curv<RECON, 1>(G, A, kind, st) : dispatch_curv<RECON, 0>(G, A, kind, st);
+            if (G.ogrid)
+                return G.flux == 1 ? dispatch_curv<RECON, 1, 2>(G, A, kind, st) : dispatch_curv<RECON, 0, 2>(G, A, kind, st);
+            return G.flux == 1 ? dispatch_curv<RECON, 1, 1>(G, A, kind, st) : dispatch_curv<RECON, 0, 1>(G, A, kind, st);
         }
         return hipErrorNotSupported;
     }

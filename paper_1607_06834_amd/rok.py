@@ -27,7 +27,8 @@ MAX_STAGES, MAX_M = 8, 64
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
            "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
            "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
-           "rok_eigs", "rok_eigs_workspace_bytes", "rok_set_grid", "rok_grid_metric_bytes", "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
+           "rok_eigs", "rok_eigs_workspace_bytes", "rok_set_grid", "rok_grid_metric_bytes", "rok_set_ogrid",
+           "rok_ogrid_metric_bytes", "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
 MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
 
 
@@ -103,6 +104,10 @@ def load_library(path: str = LIB_PATH):
     lib.rok_set_grid.restype = i
     lib.rok_grid_metric_bytes.argtypes = [vp]
     lib.rok_grid_metric_bytes.restype = sz
+    lib.rok_set_ogrid.argtypes = [vp, vp, vp, pd, vp, vp]
+    lib.rok_set_ogrid.restype = i
+    lib.rok_ogrid_metric_bytes.argtypes = [vp]
+    lib.rok_ogrid_metric_bytes.restype = sz
     lib.rok_eigs.argtypes = [vp, vp, vp, i, i, i, d, pd, pd, pd, pi, vp, sz, vp]
     lib.rok_eigs.restype = i
     lib.rok_eigs_workspace_bytes.argtypes = [vp, i, i]
@@ -174,6 +179,7 @@ class Rok:
     def __init__(self, problem: dict, precision: str = "fp64", mgs: str = "auto"):
         lib = load_library()
         p = RokProblem()
+        self._n = tuple(int(v) for v in problem["n"])
         D = len(problem["n"])
         p.ndim = D
         for d in range(3):
@@ -305,6 +311,22 @@ class Rok:
         met = torch.empty(nb // 8, dtype=torch.float64, device=self.device)
         _check(_lib.rok_set_grid(self._ctx, _ptr(xd), _ptr(yd), _ptr(met), _stream()), "rok_set_grid")
         self._metrics = met            # kept alive while the context uses it
+
+    def set_ogrid(self, xn, yn, freestream):
+        """Use an O-grid (nodes [j][i], j = 0..n[1]; wall at row 0, far field past the last
+        row, free stream (rho, rho u, rho v, E)); rok_set_ogrid."""
+        nb = int(_lib.rok_ogrid_metric_bytes(self._ctx))
+        if nb == 0:
+            raise ValueError("O-grids need a 2-D Euler problem")
+        xd = torch.as_tensor(xn, dtype=torch.float64).to(self.device).contiguous()
+        yd = torch.as_tensor(yn, dtype=torch.float64).to(self.device).contiguous()
+        n0, n1 = self._n[0], self._n[1]
+        if xd.numel() != n0 * (n1 + 1) or yd.numel() != xd.numel():
+            raise ValueError("node arrays must have n[0] * (n[1] + 1) entries")
+        met = torch.empty(nb // 8, dtype=torch.float64, device=self.device)
+        fs = (ctypes.c_double * 4)(*[float(v) for v in freestream])
+        _check(_lib.rok_set_ogrid(self._ctx, _ptr(xd), _ptr(yd), fs, _ptr(met), _stream()), "rok_set_ogrid")
+        self._metrics = met
 
     def eigs(self, y, v0, k: int = 6, m: int = 40, max_restarts: int = 50, tol: float = 1e-10):
         """k largest-magnitude eigenvalues of J(y) (rok_eigs).  Returns (values as a complex

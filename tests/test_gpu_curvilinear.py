@@ -120,3 +120,58 @@ def test_curvilinear_refusals_and_reset(dev):
     ns = Rok(ri.problem((12, 10), (0.0, 0.0), (1.0, 1.0), "ns", "muscl", mu=0.05))
     with pytest.raises(ValueError):
         ns.set_grid(*nodes)
+
+
+# ---------------------------------------------------------------------------
+# O-grid around a cylinder: slip wall and far field
+# ---------------------------------------------------------------------------
+
+def _ogrid_setup(nx, ny, recon, flux, seed=5):
+    from paper_1607_06834_amd import Rok
+    from tests.test_oracle_ogrid import _state
+    import numpy as np
+    fs = ri.freestream(mach=0.3)
+    pb, nodes = ri.cylinder_ogrid(nx, ny, recon=recon, flux=flux)
+    P = oracle_problem(pb)
+    P.nodes, P.farfield = nodes, fs
+    y0 = _state(pb, nodes, seed, fs)
+    y = t64(y0 + 1e-2 * np.random.default_rng(seed).uniform(-1.0, 1.0, y0.size))
+    g = Rok(pb)
+    g.set_ogrid(*nodes, fs)
+    return P, g, y
+
+
+OCASES = [(s, r, f) for s in [(16, 10), (37, 21), (128, 64)] for r in ("first", "muscl") for f in ("rusanov", "roe")]
+
+
+@pytest.mark.parametrize("shape,recon,flux", OCASES)
+def test_ogrid_residual_fd_tangent(dev, shape, recon, flux):
+    say("ogrid", shape, recon, flux)
+    P, g, y = _ogrid_setup(*shape, recon, flux)
+    met = g._metrics.cpu()
+    ref_m = fv.ogrid_metrics(P)
+    nc = shape[0] * shape[1]
+    for q in range(5):
+        assert torch.equal(met[q * nc:(q + 1) * nc], ref_m[q].reshape(-1))
+    assert torch.equal(met[5 * nc:5 * nc + shape[0]], ref_m[5]) and torch.equal(met[5 * nc + shape[0]:], ref_m[6])
+    ref = fv.residual(P, y)
+    out = g.residual(y.to(dev)).cpu()
+    assert torch.equal(out, ref), relerr(out, ref)
+    v = t64(ri.random_direction(P.size, seed=3))
+    eps = 1.7e-7
+    assert torch.equal(g.jvp(y.to(dev), v.to(dev), "fd", fy=ref.to(dev), eps=eps).cpu(), fv.jvp_fd(P, y, ref, v, eps))
+    assert relerr(g.jvp(y.to(dev), v.to(dev), "exact").cpu(), fv.jvp_exact(P, y, v)) <= 1e-12
+
+
+@pytest.mark.parametrize("mode,recon,M", [("fd", "muscl", 8), ("exact", "muscl", 8), ("fd", "first", 4)])
+def test_ogrid_step_parity(dev, mode, recon, M):
+    say("ogrid step", mode, recon, M)
+    P, g, y = _ogrid_setup(24, 16, recon, "roe")
+    h = 2e-3
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, mode)
+    ref = rok.rok_step(f, mv, tab, M, h, y)
+    out = g.step(y.to(dev), h, tab, M, "fd" if mode == "fd" else "exact").cpu()
+    assert relerr(out, ref) <= 1e-12
+    if mode == "fd":
+        assert torch.equal(out, ref)

@@ -63,6 +63,10 @@ def test_host_validation_without_gpu():
     assert lib.rok_grid_metric_bytes(ctx) == 5 * 64 * 8
     assert lib.rok_set_grid(ctx, ctypes.c_void_p(8), None, ctypes.c_void_p(16), None) == rok.ROK_EINVAL
     assert lib.rok_set_grid(ctx, None, None, None, None) == rok.ROK_OK
+    assert lib.rok_ogrid_metric_bytes(ctx) == (5 * 64 + 2 * 8) * 8
+    bad_fs = (ctypes.c_double * 4)(1.0, 0.0, 0.0, -1.0)          # negative pressure
+    assert lib.rok_set_ogrid(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), bad_fs, ctypes.c_void_p(24), None) == \
+        rok.ROK_EINVAL
     # eigenvalue estimate: sizes are validated on the host
     assert lib.rok_eigs_workspace_bytes(ctx, 6, 40) > 0
     assert lib.rok_eigs_workspace_bytes(ctx, 9, 10) == 0 and lib.rok_eigs_workspace_bytes(ctx, 0, 10) == 0
