@@ -86,13 +86,18 @@ def cartesian_nodes(pb):
     return warped_nodes(pb, 0.0)
 
 
-def cylinder_ogrid(nx, ny, radius=0.5, far=10.0, recon="first", flux="rusanov"):
+def cylinder_ogrid(nx, ny, radius=0.5, far=10.0, recon="first", flux="rusanov", cluster=None):
     """O-grid around a circular cylinder: nodes x(i, j), y(i, j) (arrays [j][i],
     j = 0..ny) at angle -2 pi i / nx (clockwise, so that (i, j) is right-handed)
-    and radius r_j = radius q^j growing geometrically to `far` (thin cells at the
-    wall).  Returns (problem with n = (nx, ny), (x, y))."""
-    q = (far / radius) ** (1.0 / ny)
-    rj = radius * q ** np.arange(ny + 1)
+    and radius r_j = radius q^j growing geometrically to `far`, or, with
+    cluster = beta, r_j = radius + (far - radius)(e^{beta j / ny} - 1)/(e^beta - 1)
+    (very thin cells at the wall, as on viscous meshes).  Returns (problem with
+    n = (nx, ny), (x, y))."""
+    if cluster is None:
+        q = (far / radius) ** (1.0 / ny)
+        rj = radius * q ** np.arange(ny + 1)
+    else:
+        rj = radius + (far - radius) * np.expm1(cluster * np.arange(ny + 1) / ny) / np.expm1(cluster)
     th = -2.0 * math.pi * np.arange(nx) / nx
     x = rj[:, None] * np.cos(th)[None, :]
     y = rj[:, None] * np.sin(th)[None, :]
