@@ -175,3 +175,33 @@ def test_ogrid_step_parity(dev, mode, recon, M):
     assert relerr(out, ref) <= 1e-12
     if mode == "fd":
         assert torch.equal(out, ref)
+
+
+def test_ogrid_adaptive_integration_bitwise(dev):
+    """Adaptive control on the cylinder O-grid (FD products, M = 4): the oracle's
+    decisions, step sizes, error values and final state, bit for bit."""
+    from oracle import adaptive
+    P, g, y = _ogrid_setup(24, 16, "muscl", "roe")
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, "fd")
+    T, H0 = 0.02, 1e-3
+    yr, rr = adaptive.integrate(lambda z, H: rok.rok_step(f, mv, tab, 4, H, z), y, T, H0, 1e-8, 1e-8)
+    yg, rg = g.integrate_adaptive(y.to(dev), T, H0, tab, 4, "fd", order=4, rtol=1e-8, atol=1e-8)
+    say("ogrid adaptive", len(rr["accepted"]), len(rr["rejected"]))
+    assert rg["accepted"] == rr["accepted"] and rg["rejected"] == rr["rejected"]
+    assert torch.equal(yg.cpu(), yr)
+
+
+def test_ogrid_eigs_against_dense_spectrum(dev):
+    """The stiffness diagnostic on a small cylinder O-grid with thin wall cells:
+    the 6 largest-magnitude eigenvalues match the dense spectrum."""
+    import numpy as np
+    from oracle import eigen
+    from tests.test_gpu_eigs import _match
+    P, g, y = _ogrid_setup(16, 8, "first", "rusanov")
+    want = eigen.largest(P, y, 8)
+    v0 = torch.tensor(ri.random_direction(g.N, seed=11), device=dev)
+    vals, res, restarts, conv = g.eigs(y.to(dev), v0, k=6, m=40, max_restarts=300, tol=1e-12)
+    e = _match(vals, want)
+    say("ogrid eigs", restarts, conv, e, np.round(vals, 4))
+    assert conv == 6 and e <= 1e-8
