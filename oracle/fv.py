@@ -74,6 +74,7 @@ class Problem:
     nodes: tuple = None       # 2-D curvilinear grid: node coordinates (x, y), arrays [j][i]
     farfield: tuple = None    # O-grid (periodic in i, wall at j = 0, far field past the last row):
                               # the free-stream conserved state (rho, rho u, rho v, E)
+    t_wall: float = 1.0       # O-grid with Navier-Stokes physics: the isothermal wall's temperature
     dtype: torch.dtype = field(default=torch.float64)
 
     @property
@@ -346,7 +347,8 @@ def metrics(P: Problem):
     j+1) the edge p3 -> p2; the face vectors are those edges turned by 90
     degrees (length = face length, pointing to increasing i or j), and the
     area is half the cross product of the diagonals.  Returns torch tensors
-    (Sx_e, Sy_e, Sx_n, Sy_n, 1/A), each [j][i]."""
+    (Sx_e, Sy_e, Sx_n, Sy_n, 1/A, dx_e, dy_e, dx_n, dy_n), each [j][i], the last
+    four the centroid differences across the east and north faces."""
     xn, yn = (np.asarray(a, dtype=np.float64) for a in P.nodes)
     Lx, Ly = P.hi[0] - P.lo[0], P.hi[1] - P.lo[1]
 
@@ -368,14 +370,26 @@ def metrics(P: Problem):
     sxn = y3 - y2
     syn = x2 - x3
     area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0))
-    return tuple(torch.from_numpy(a) for a in (sxe, sye, sxn, syn, 1.0 / area))
+    # centroid differences across the east and north faces (cell centroid: mean of its nodes)
+    x4, y4 = node(2, 0)
+    x5, y5 = node(2, 1)
+    x6, y6 = node(0, 2)
+    x7, y7 = node(1, 2)
+    dxe = 0.25 * ((x4 + x5) - (x0 + x3))
+    dye = 0.25 * ((y4 + y5) - (y0 + y3))
+    dxn = 0.25 * ((x6 + x7) - (x0 + x1))
+    dyn = 0.25 * ((y6 + y7) - (y0 + y1))
+    return tuple(torch.from_numpy(a) for a in (sxe, sye, sxn, syn, 1.0 / area, dxe, dye, dxn, dyn))
 
 
 def ogrid_metrics(P: Problem):
     """Face vectors and inverse areas of an O-grid: nodes (x, y) indexed [j][i] with
     j = 0..ny (row 0 on the wall, row ny on the far-field boundary) and i periodic
-    without offset (node nx is node 0).  Same conventions as `metrics`; also the
-    wall face vectors (the south faces of row 0, pointing into the domain)."""
+    without offset (node nx is node 0).  Same conventions as `metrics` (the north
+    centroid difference of the last row is zero: that face is the far field);
+    also the wall face vectors (the south faces of row 0, pointing into the
+    domain) and the vectors from each wall face's midpoint to the first
+    cell's centroid."""
     xn, yn = (np.asarray(a, dtype=np.float64) for a in P.nodes)
     r1 = lambda a: np.roll(a, -1, axis=1)
     x0, y0 = xn[:-1], yn[:-1]
@@ -389,7 +403,15 @@ def ogrid_metrics(P: Problem):
     area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0))
     wx = yn[0] - r1(yn)[0]
     wy = r1(xn)[0] - xn[0]
-    return tuple(torch.from_numpy(a) for a in (sxe, sye, sxn, syn, 1.0 / area, wx, wy))
+    r2 = lambda a: np.roll(a, -2, axis=1)
+    dxe = 0.25 * ((r2(xn)[:-1] + r2(xn)[1:]) - (x0 + x3))
+    dye = 0.25 * ((r2(yn)[:-1] + r2(yn)[1:]) - (y0 + y3))
+    z = np.zeros((1, xn.shape[1]))
+    dxn = np.concatenate([0.25 * ((xn[2:] + r1(xn)[2:]) - (xn[:-2] + r1(xn)[:-2])), z])   # no face past the far field
+    dyn = np.concatenate([0.25 * ((yn[2:] + r1(yn)[2:]) - (yn[:-2] + r1(yn)[:-2])), z])
+    awx = 0.25 * ((x2[0] + x3[0]) - (x0[0] + x1[0]))      # first centroid minus wall-face midpoint
+    awy = 0.25 * ((y2[0] + y3[0]) - (y0[0] + y1[0]))
+    return tuple(torch.from_numpy(a) for a in (sxe, sye, sxn, syn, 1.0 / area, dxe, dye, dxn, dyn, wx, wy, awx, awy))
 
 
 def _rotated_flux(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, sx, sy):
@@ -407,22 +429,38 @@ def _rotated_flux(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, sx, sy):
 
 
 def _residual_ogrid(P: Problem, y: torch.Tensor) -> torch.Tensor:
-    """f on an O-grid around a body (2-D Euler): periodic in i; along j the faces
-    j + 1/2 for j = -1 (the wall: a slip wall carries the pressure of the first
-    cell, Fhat = (0, p S, 0)), 0..ny-2 (interior; MUSCL slopes that would reach
-    past the wall or the far field are zero) and ny - 1 (the far field: the
-    numerical flux between the last cell's primitive state, taken back to
-    conserved variables, and the free stream)."""
-    if P.ndim != 2 or P.physics != EULER:
-        raise ValueError("O-grids: 2-D Euler physics only")
+    """f on an O-grid around a body (2-D): periodic in i; along j the faces
+    j + 1/2 for j = -1 (the wall), 0..ny-2 (interior; MUSCL slopes that would
+    reach past the wall or the far field are zero) and ny - 1 (the far field:
+    the numerical flux between the last cell's primitive state, taken back to
+    conserved variables, and the free stream).  Euler: a slip wall carrying the
+    first cell's pressure, Fhat = (0, p S, 0).  Navier-Stokes: the same pressure
+    flux plus the viscous flux of an isothermal no-slip wall (velocity 0 and
+    temperature t_wall on the wall; gradients from the wall value and the first
+    cell, through the vector from the wall face's midpoint to that cell's
+    centroid); index-space derivatives along j at rows 0 and ny-1 are one-sided;
+    no viscous flux through the far field."""
+    if P.ndim != 2:
+        raise ValueError("O-grids: 2-D only")
+    ns = P.physics == NS
     nx, ny = P.n
     U = y.reshape(P.shape)
     U = [U[m] for m in range(P.nvar)]
     r, vel, p = primitives(P, U)
-    sxe, sye, sxn, syn, inva, wx, wy = ogrid_metrics(P)
+    T = p / r
+    sxe, sye, sxn, syn, inva, dxe, dye, dxn, dyn, wx, wy, awx, awy = ogrid_metrics(P)
+    phis = [vel[0], vel[1], T]
     # i direction: periodic, as on the curvilinear box
     (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, 0)
     Fh = _rotated_flux(P, UL, rL, vL, pL, UR, rR, vR, pR, sxe, sye)
+    if ns:
+        dn = [_at(a, 1, 0) - a for a in phis]
+        gc = [torch.cat([(a[1] - a[0])[None], (a[2:] - a[:-2]) * 0.5, (a[-1] - a[-2])[None]]) for a in phis]
+        dt = [0.5 * (g + _at(g, 1, 0)) for g in gc]
+        uf = [0.5 * (vel[0] + _at(vel[0], 1, 0)), 0.5 * (vel[1] + _at(vel[1], 1, 0))]
+        fx, fy, en = _viscous_flux_curv(P, (sxe, sye), (dxe, dye), 0.5 * (T + _at(T, 1, 0)), dn[:2], dt[:2], dn[2],
+                                        dt[2], uf, -1)
+        Fh = [Fh[0], Fh[1] - fx, Fh[2] - fy, Fh[3] - en]
     out = torch.stack([(_at(Fh[m], -1, 0) - Fh[m]) * inva for m in range(P.nvar)])
     # j direction: faces 1/2 .. ny - 3/2 between rows j and j + 1
     q = [r] + list(vel) + [p]
@@ -447,9 +485,22 @@ def _residual_ogrid(P: Problem, y: torch.Tensor) -> torch.Tensor:
         ULc = conserved(P, rL, vL, pL)
         URc = conserved(P, rR, vR, pR)
     Fi = _rotated_flux(P, ULc, rL, vL, pL, URc, rR, vR, pR, sxn[:-1], syn[:-1])
+    if ns:
+        dn = [a[1:] - a[:-1] for a in phis]
+        gc = [(_at(a, 1, 0) - _at(a, -1, 0)) * 0.5 for a in phis]
+        dt = [0.5 * (g[:-1] + g[1:]) for g in gc]
+        uf = [0.5 * (vel[0][:-1] + vel[0][1:]), 0.5 * (vel[1][:-1] + vel[1][1:])]
+        fx, fy, en = _viscous_flux_curv(P, (sxn[:-1], syn[:-1]), (dxn[:-1], dyn[:-1]), 0.5 * (T[:-1] + T[1:]), dn[:2],
+                                        dt[:2], dn[2], dt[2], uf, 1)
+        Fi = [Fi[0], Fi[1] - fx, Fi[2] - fy, Fi[3] - en]
     # wall and far field
     zw = torch.zeros_like(wx)
     Fw = [zw, p[0] * wx, p[0] * wy, zw]
+    if ns:
+        tw = P.t_wall
+        fx, fy, en = _viscous_flux_curv(P, (wx, wy), (awx, awy), 0.5 * (T[0] + tw),
+                                        [vel[0][0] - 0.0, vel[1][0] - 0.0], [zw, zw], T[0] - tw, zw, [zw, zw], 1)
+        Fw = [Fw[0], Fw[1] - fx, Fw[2] - fy, Fw[3] - en]
     Uf = [torch.full_like(r[-1], float(v)) for v in P.farfield]
     rf, vf, pf = primitives(P, Uf)
     vb = [v[-1] for v in vel]
@@ -460,18 +511,50 @@ def _residual_ogrid(P: Problem, y: torch.Tensor) -> torch.Tensor:
     return out.reshape(-1)
 
 
+def _viscous_flux_curv(P: Problem, S, dc, mu_T, un, ut, Tn, Tt, uf, sign):
+    """Viscous flux through a curvilinear face with face vector S = (Sx, Sy) and
+    centroid difference dc across it, from index-space derivatives across the
+    face (un = (u_n, v_n), Tn) and along it (ut, Tt): with J = dc . S,
+    grad phi = (phi_n S -+ phi_t (dcy, -dcx)) / J (sign = -1 across i, +1 across
+    j: the chain rule through the face's two grid directions).  mu_T: the face
+    temperature for Sutherland's law.  uf: face velocity.  Returns
+    (F_v . S) for momentum x, y and energy."""
+    Sx, Sy = S
+    dcx, dcy = dc
+    J = dcx * Sx + dcy * Sy
+    if sign < 0:
+        grad = lambda n, t: ((n * Sx - t * dcy) / J, (n * Sy + t * dcx) / J)
+    else:
+        grad = lambda n, t: ((n * Sx + t * dcy) / J, (n * Sy - t * dcx) / J)
+    ux, uy = grad(un[0], ut[0])
+    vx, vy = grad(un[1], ut[1])
+    Tx, Ty = grad(Tn, Tt)
+    mu = sutherland_mu(P, mu_T) if P.sutherland > 0.0 else P.mu
+    c23 = (2.0 / 3.0) * mu
+    kap = mu * P.gamma / ((P.gamma - 1.0) * P.prandtl)
+    div = ux + vy
+    txx = mu * (ux + ux) - c23 * div
+    tyy = mu * (vy + vy) - c23 * div
+    txy = mu * (uy + vx)
+    fx = txx * Sx + txy * Sy
+    fy = txy * Sx + tyy * Sy
+    en = (uf[0] * txx + uf[1] * txy + kap * Tx) * Sx + (uf[0] * txy + uf[1] * tyy + kap * Ty) * Sy
+    return fx, fy, en
+
+
 def _residual_curvilinear(P: Problem, y: torch.Tensor) -> torch.Tensor:
     """f on a 2-D curvilinear periodic grid (Euler physics): reconstruction in
     index space as on the Cartesian grid, then at each face the states are
     rotated into the face frame (n = S/|S|: normal and tangential momentum and
     velocity), the one-dimensional numerical flux is taken there, rotated back
     and scaled by the face length; f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / A_c."""
-    if P.ndim != 2 or P.physics != EULER:
-        raise ValueError("curvilinear grids: 2-D Euler physics only")
+    if P.ndim != 2:
+        raise ValueError("curvilinear grids: 2-D only")
     U = y.reshape(P.shape)
     U = [U[m] for m in range(P.nvar)]
     r, vel, p = primitives(P, U)
-    sxe, sye, sxn, syn, inva = metrics(P)
+    sxe, sye, sxn, syn, inva, dxe, dye, dxn, dyn = metrics(P)
+    T = p / r
     out = None
     for d in range(2):
         (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, d)
@@ -485,6 +568,17 @@ def _residual_curvilinear(P: Problem, y: torch.Tensor) -> torch.Tensor:
         URr = [UR[0], UR[1] * nx + UR[2] * ny, UR[2] * nx - UR[1] * ny, UR[3]]
         Fr = face_flux(P, ULr, rL, vLr, pL, URr, rR, vRr, pR, 0)
         Fh = [Fr[0] * ln, (Fr[1] * nx - Fr[2] * ny) * ln, (Fr[1] * ny + Fr[2] * nx) * ln, Fr[3] * ln]
+        if P.physics == NS:
+            t = 1 - d                      # the grid direction along the face
+            phis = [vel[0], vel[1], T]
+            dn = [_at(a, 1, d) - a for a in phis]
+            gc = [(_at(a, 1, t) - _at(a, -1, t)) * 0.5 for a in phis]
+            dt = [0.5 * (g + _at(g, 1, d)) for g in gc]
+            uf = [0.5 * (vel[0] + _at(vel[0], 1, d)), 0.5 * (vel[1] + _at(vel[1], 1, d))]
+            dc = (dxe, dye) if d == 0 else (dxn, dyn)
+            fx, fy, en = _viscous_flux_curv(P, (sx, sy), dc, 0.5 * (T + _at(T, 1, d)), dn[:2], dt[:2], dn[2], dt[2],
+                                            uf, -1 if d == 0 else 1)
+            Fh = [Fh[0], Fh[1] - fx, Fh[2] - fy, Fh[3] - en]
         term = torch.stack([(_at(Fh[m], -1, d) - Fh[m]) * inva for m in range(P.nvar)])
         out = term if out is None else out + term
     return out.reshape(-1)

@@ -29,7 +29,7 @@ def _P(pb, nodes):
 def test_metric_identities():
     pb = ri.problem((12, 9), (-1.0, 0.0), (2.0, 1.5), "euler", "first")
     P = _P(pb, ri.warped_nodes(pb, 0.06))
-    sxe, sye, sxn, syn, inva = (a.numpy() for a in fv.metrics(P))
+    sxe, sye, sxn, syn, inva = (a.numpy() for a in fv.metrics(P)[:5])
     gx = sxe - np.roll(sxe, 1, axis=1) + sxn - np.roll(sxn, 1, axis=0)
     gy = sye - np.roll(sye, 1, axis=1) + syn - np.roll(syn, 1, axis=0)
     assert np.abs(gx).max() <= 1e-14 and np.abs(gy).max() <= 1e-14
@@ -78,6 +78,56 @@ def test_vortex_on_a_warped_grid_converges(recon, order):
 
 def test_warped_jacobian_bruteforce():
     pb = ri.problem((5, 4), (0.0, 0.0), (1.0, 0.8), "euler", "muscl", flux="roe")
+    P = _P(pb, ri.warped_nodes(pb, 0.06))
+    y = t64(ri.smooth_random_state(pb, seed=5, amplitude=0.2))
+    J = fv.dense_jacobian_fd(P, y, delta=1e-6)
+    v = t64(ri.random_direction(P.size, seed=7))
+    assert relerr(fv.jvp_exact(P, y, v), J @ v) <= 1e-7
+
+
+@pytest.mark.parametrize("recon", ["first", "muscl"])
+@pytest.mark.parametrize("suth", [0.0, 0.4])
+def test_ns_cartesian_nodes_reduce_to_the_cartesian_residual(recon, suth):
+    """Viscous terms through the chain rule reduce to the Cartesian face
+    gradients on Cartesian nodes (to rounding)."""
+    pb = ri.problem((10, 7), (-1.0, 0.0), (2.0, 1.4), "ns", recon, mu=0.05, sutherland=suth, t_ref=0.8)
+    y = t64(ri.smooth_random_state(pb, seed=2, amplitude=0.2))
+    assert relerr(fv.residual(_P(pb, ri.cartesian_nodes(pb)), y), fv.residual(oracle_problem(pb), y)) <= 1e-13
+
+
+def test_ns_conservation_on_a_warped_grid():
+    pb = ri.problem((12, 10), (-1.0, 0.0), (2.0, 1.4), "ns", "muscl", mu=0.05, flux="roe", sutherland=0.4)
+    P = _P(pb, ri.warped_nodes(pb, 0.06))
+    y = t64(ri.uniform_state(pb, rho=1.3, vel=[0.4, -0.7], p=0.9))
+    scale = float(torch.abs(fv.residual(oracle_problem(pb), t64(ri.smooth_random_state(pb, seed=1)))).max())
+    assert float(torch.abs(fv.residual(P, y)).max()) <= 1e-12 * max(scale, 1.0)
+    y = t64(ri.smooth_random_state(pb, seed=3, amplitude=0.2))
+    F = fv.residual(P, y).reshape(4, -1)
+    area = (1.0 / fv.metrics(P)[4]).reshape(-1)
+    assert float(torch.abs((F * area).sum(dim=1)).max()) <= 1e-13 * float((torch.abs(F) * area).sum(dim=1).max())
+
+
+def test_ns_shear_wave_on_a_warped_grid_converges():
+    """Viscous part of the y-momentum residual for v = 0.3 sin(2 pi x / Lx) (rho,
+    p uniform) on warped grids: converges to mu v_xx at first order or better."""
+    errs = []
+    for n in (16, 32, 64):
+        pb = ri.problem((n, n), (0.0, 0.0), (2.0, 2.0), "ns", "muscl", mu=0.07)
+        nodes = ri.warped_nodes(pb, 0.05)
+        xc, yc = ri.node_centres(pb, *nodes)
+        one = np.ones_like(xc)
+        v = 0.3 * np.sin(math.pi * xc)
+        y = t64(ri._pack(pb, one, [0 * xc, v], one))
+        Pn, Pe = _P(pb, nodes), _P(dict(pb, physics="euler", mu=0.0), nodes)
+        visc = (fv.residual(Pn, y) - fv.residual(Pe, y)).reshape(4, n, n)[2].numpy()
+        want = -0.07 * math.pi ** 2 * v
+        errs.append(np.sqrt(((visc - want) ** 2).mean()) / np.sqrt((want ** 2).mean()))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 0.05 and min(rates) >= 0.9, (errs, rates)
+
+
+def test_ns_warped_jacobian_bruteforce():
+    pb = ri.problem((5, 4), (0.0, 0.0), (1.0, 0.8), "ns", "muscl", mu=0.05, flux="roe", sutherland=0.4)
     P = _P(pb, ri.warped_nodes(pb, 0.06))
     y = t64(ri.smooth_random_state(pb, seed=5, amplitude=0.2))
     J = fv.dense_jacobian_fd(P, y, delta=1e-6)

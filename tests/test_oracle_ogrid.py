@@ -117,3 +117,55 @@ def test_interior_consistency_order(recon, order):
         errs.append(float(torch.sqrt(((F - ex) ** 2).mean()) / torch.sqrt((ex ** 2).mean())))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(rates) >= order, (errs, rates)
+
+
+def _Pns(nx, ny, recon, flux, fs, t_wall, suth=0.0):
+    pb, nodes = ri.cylinder_ogrid(nx, ny, recon=recon, flux=flux)
+    pb = dict(pb, physics="ns", mu=0.02, sutherland=suth, t_ref=0.9)
+    P = oracle_problem(pb)
+    P.nodes, P.farfield, P.t_wall = nodes, fs, t_wall
+    return pb, P, nodes
+
+
+@pytest.mark.parametrize("recon", ["first", "muscl"])
+def test_ns_gas_at_rest_at_the_wall_temperature_is_steady(recon):
+    fs = (1.2, 0.0, 0.0, 0.9 / 0.4)
+    pb, P, nodes = _Pns(16, 10, recon, "roe", fs, t_wall=0.9 / 1.2, suth=0.4)
+    y = t64(ri.uniform_state(pb, rho=1.2, vel=[0.0, 0.0], p=0.9))
+    F = fv.residual(P, y)
+    scale = 0.9 * float(fv.ogrid_metrics(P)[4].max()) * float(torch.abs(fv.ogrid_metrics(P)[0]).max())
+    assert float(torch.abs(F).max()) <= 1e-13 * scale
+
+
+def test_ns_hot_wall_heats_only_the_first_row():
+    """Gas at rest at T0 with a wall at Tw > T0: only the energy of the wall cells
+    changes, and it grows (heat flows in through the wall)."""
+    fs = (1.2, 0.0, 0.0, 0.9 / 0.4)
+    pb, P, nodes = _Pns(16, 10, "muscl", "rusanov", fs, t_wall=1.5)
+    y = t64(ri.uniform_state(pb, rho=1.2, vel=[0.0, 0.0], p=0.9))
+    F = fv.residual(P, y).reshape(4, 10, 16)
+    scale = float(torch.abs(F).max())
+    assert (F[3, 0] > 0).all()
+    rest = torch.cat([F[:3].reshape(-1), F[3, 1:].reshape(-1)])
+    assert float(torch.abs(rest).max()) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("recon", ["first", "muscl"])
+def test_ns_mirror_symmetry(recon):
+    fs = ri.freestream(mach=0.3)
+    nx, ny = 16, 10
+    pb, P, nodes = _Pns(nx, ny, recon, "roe", fs, t_wall=1.1, suth=0.4)
+    y = t64(_state(pb, nodes, 3, fs)).reshape(4, ny, nx)
+    mirror = lambda U: torch.stack([U[0], U[1], -U[2], U[3]])[:, :, list(range(nx - 1, -1, -1))]
+    F = fv.residual(P, y.reshape(-1)).reshape(4, ny, nx)
+    assert relerr(mirror(F), F) <= 1e-12
+
+
+def test_ns_bruteforce_jacobian():
+    fs = ri.freestream(mach=0.3)
+    pb, P, nodes = _Pns(6, 4, "muscl", "roe", fs, t_wall=1.1, suth=0.4)
+    y0 = _state(pb, nodes, 5, fs)
+    y = t64(y0 + 1e-2 * np.random.default_rng(9).uniform(-1.0, 1.0, y0.size))
+    J = fv.dense_jacobian_fd(P, y, delta=1e-6)
+    v = t64(ri.random_direction(P.size, seed=7))
+    assert relerr(fv.jvp_exact(P, y, v), J @ v) <= 1e-7
