@@ -139,7 +139,7 @@ void rok_destroy(rok_ctx* ctx);
 rok_status rok_set_mgs_path(rok_ctx* ctx, int path);
 
 /*
- * Curvilinear grids (2-D, ROK_EULER): the box [lo, hi] becomes a periodic
+ * Curvilinear grids (2-D, n[0], n[1] >= 2): the box [lo, hi] becomes a periodic
  * structured grid with the given nodes (the paper's residual works on
  * curvilinear structured grids, Sec. 3.2).  xn, yn: n[0] * n[1] doubles each,
  * device memory, node (i, j) at j * n[0] + i; node (i + n[0], j) is node (i, j)
@@ -154,37 +154,48 @@ rok_status rok_set_mgs_path(rok_ctx* ctx, int path);
  * index space, then at each face the states are rotated into the face frame
  * (normal and tangential momentum and velocity), the flux is taken there,
  * rotated back and scaled by the face length, and
- * f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / A_c.  All three pointers null:
- * back to the Cartesian grid.  FP64 precision only (the FP32 form returns
- * ROK_EUNSUPPORTED); the adjoint entry points return ROK_EUNSUPPORTED.
+ * f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / A_c.  Navier-Stokes physics: face
+ * gradients by the chain rule through the face's two grid directions (the
+ * index-space difference across the face and the mean of the two cells'
+ * central differences along it, with the face vector and the difference of
+ * the two cells' centroids, each centroid the mean of its nodes).  All three
+ * pointers null: back to the Cartesian grid.  FP64 precision only (the FP32
+ * form returns ROK_EUNSUPPORTED); the adjoint entry points return
+ * ROK_EUNSUPPORTED.
  */
 rok_status rok_set_grid(rok_ctx* ctx, const double* xn, const double* yn, double* metrics, void* stream);
 
-/* Bytes of the metric buffer of rok_set_grid (0 unless 2-D Euler). */
+/* Bytes of the metric buffer of rok_set_grid (0 unless 2-D with n[0], n[1] >= 2). */
 size_t rok_grid_metric_bytes(const rok_ctx* ctx);
 
 /*
- * An O-grid around a body (2-D, ROK_EULER; the paper's cylinder cases use such
- * grids with a wall and a far field, Sec. 4.2): nodes xn, yn of
+ * An O-grid around a body (2-D, n[0], n[1] >= 2; the paper's cylinder cases use
+ * such grids with a wall and a far field, Sec. 4.2): nodes xn, yn of
  * n[0] * (n[1] + 1) doubles each, device memory, node (i, j) at j * n[0] + i for
  * j = 0..n[1] (row 0 on the body, row n[1] on the far-field boundary), periodic
  * in i without offset (node n[0] is node 0).  Cell faces, areas and the flux in
- * the face frame are as for rok_set_grid; along j the face below row 0 is a
- * slip wall (it carries the first cell's pressure on the wall face vector), the
- * face above the last row is the far field (the numerical flux between the last
- * cell's primitive state, in conserved form, and `freestream`), and MUSCL slopes
- * that would reach past either boundary are zero.
+ * the face frame are as for rok_set_grid; along j the face below row 0 is the
+ * wall (it carries the first cell's pressure on the wall face vector: a slip
+ * wall for ROK_EULER; for ROK_NS also the viscous flux of an isothermal no-slip
+ * wall at temperature t_wall, with gradients from the wall values and the
+ * first cell through the vector from the wall face's midpoint to that cell's
+ * centroid), the face above the last row is the far field (the numerical flux
+ * between the last cell's primitive state, in conserved form, and
+ * `freestream`; no viscous flux), MUSCL slopes that would reach past either
+ * boundary are zero, and index differences along j are one-sided in the
+ * boundary rows.
  *   freestream: host, 4 doubles, the conserved free-stream state (rho, rho u,
  *               rho v, E) with rho > 0 and a positive pressure
+ *   t_wall:     the wall temperature p / rho (> 0; read for ROK_NS only)
  *   metrics:    rok_ogrid_metric_bytes(ctx) bytes of device memory owned by the
  *               caller (valid while the context uses it)
- * n[1] >= 2.  Same restrictions as rok_set_grid; rok_set_grid(ctx, 0, 0, 0, s)
- * returns to the Cartesian grid.
+ * Same restrictions as rok_set_grid; rok_set_grid(ctx, 0, 0, 0, s) returns to
+ * the Cartesian grid.
  */
-rok_status rok_set_ogrid(rok_ctx* ctx, const double* xn, const double* yn, const double* freestream, double* metrics,
-                         void* stream);
+rok_status rok_set_ogrid(rok_ctx* ctx, const double* xn, const double* yn, const double* freestream, double t_wall,
+                         double* metrics, void* stream);
 
-/* Bytes of the metric buffer of rok_set_ogrid (0 unless 2-D Euler). */
+/* Bytes of the metric buffer of rok_set_ogrid (0 unless 2-D with n[0], n[1] >= 2). */
 size_t rok_ogrid_metric_bytes(const rok_ctx* ctx);
 
 /* N, the length of a state vector. */

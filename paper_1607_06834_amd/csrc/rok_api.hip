@@ -265,8 +265,8 @@ rok_status rok_create(const rok_problem* p, rok_ctx** out) {
 void rok_destroy(rok_ctx* c) { delete c; }
 
 size_t rok_grid_metric_bytes(const rok_ctx* c) {
-    if (!c || c->pb.ndim != 2 || c->pb.physics != ROK_EULER) return 0;
-    return sizeof(double) * 5 * (size_t)c->G.ncell;
+    if (!c || c->pb.ndim != 2 || c->pb.n[0] < 2 || c->pb.n[1] < 2) return 0;
+    return sizeof(double) * 9 * (size_t)c->G.ncell;
 }
 
 rok_status rok_set_grid(rok_ctx* c, const double* xn, const double* yn, double* metrics, void* stream) {
@@ -276,7 +276,8 @@ rok_status rok_set_grid(rok_ctx* c, const double* xn, const double* yn, double* 
         c->G.ogrid = 0;
         return ROK_OK;
     }
-    if (c->pb.ndim != 2 || c->pb.physics != ROK_EULER) return ROK_EUNSUPPORTED;
+    if (c->pb.ndim != 2) return ROK_EUNSUPPORTED;
+    if (c->pb.n[0] < 2 || c->pb.n[1] < 2) return ROK_EINVAL;
     if (!xn || !yn || !metrics || !aligned(xn, 8) || !aligned(yn, 8) || !aligned(metrics, 8)) return ROK_EINVAL;
     const double Lx = c->pb.hi[0] - c->pb.lo[0], Ly = c->pb.hi[1] - c->pb.lo[1];
     ROK_TRY(rok::launch_metrics(xn, yn, c->pb.n[0], c->pb.n[1], Lx, Ly, metrics, (hipStream_t)stream));
@@ -286,23 +287,25 @@ rok_status rok_set_grid(rok_ctx* c, const double* xn, const double* yn, double* 
 }
 
 size_t rok_ogrid_metric_bytes(const rok_ctx* c) {
-    if (!c || c->pb.ndim != 2 || c->pb.physics != ROK_EULER) return 0;
-    return sizeof(double) * (5 * (size_t)c->G.ncell + 2 * (size_t)c->pb.n[0]);
+    if (!c || c->pb.ndim != 2 || c->pb.n[0] < 2 || c->pb.n[1] < 2) return 0;
+    return sizeof(double) * (9 * (size_t)c->G.ncell + 4 * (size_t)c->pb.n[0]);
 }
 
-rok_status rok_set_ogrid(rok_ctx* c, const double* xn, const double* yn, const double* freestream, double* metrics,
-                         void* stream) {
+rok_status rok_set_ogrid(rok_ctx* c, const double* xn, const double* yn, const double* freestream, double t_wall,
+                         double* metrics, void* stream) {
     if (!c) return ROK_EINVAL;
-    if (c->pb.ndim != 2 || c->pb.physics != ROK_EULER) return ROK_EUNSUPPORTED;
+    if (c->pb.ndim != 2) return ROK_EUNSUPPORTED;
+    if (c->pb.physics == ROK_NS && (!(t_wall > 0.0) || !isfinite(t_wall))) return ROK_EINVAL;
     if (!xn || !yn || !metrics || !freestream || !aligned(xn, 8) || !aligned(yn, 8) || !aligned(metrics, 8))
         return ROK_EINVAL;
     const double r = freestream[0], E = freestream[3];
     const double ke = (freestream[1] * freestream[1] + freestream[2] * freestream[2]) / r;
     if (!(r > 0.0) || !isfinite(E) || !((c->pb.gamma - 1.0) * (E - 0.5 * ke) > 0.0)) return ROK_EINVAL;
-    if (c->pb.n[1] < 2) return ROK_EINVAL;
+    if (c->pb.n[0] < 2 || c->pb.n[1] < 2) return ROK_EINVAL;
     ROK_TRY(rok::launch_metrics_ogrid(xn, yn, c->pb.n[0], c->pb.n[1], metrics, (hipStream_t)stream));
     c->G.metric = metrics;
     c->G.ogrid = 1;
+    c->G.t_wall = t_wall;
     for (int m = 0; m < 4; ++m) c->G.uinf[m] = freestream[m];
     return ROK_OK;
 }

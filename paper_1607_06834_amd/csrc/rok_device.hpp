@@ -35,6 +35,7 @@ struct Geom {
     const double* metric;     // 2-D curvilinear grid: Sx_e, Sy_e, Sx_n, Sy_n, 1/A (ncell each), else null
     int ogrid;                // the curvilinear grid is an O-grid (wall at j = 0, far field past j = n1 - 1):
     double uinf[4];           //   then metric also holds the wall face vectors, and uinf is the free stream
+    double t_wall;            //   and (Navier-Stokes) t_wall the isothermal wall's temperature
 };
 
 // Residual-kernel inputs: the stage state Y = y + sum_t cs[t] xs[t]

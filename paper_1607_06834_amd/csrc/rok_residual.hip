@@ -393,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                     if (bface == 1) {
                         // slip wall: the pressure of the first cell on the wall face vector
                         const int gi = wrap(x0 + fx, n0);
-                        const double wx = G.metric[5L * G.ncell + gi], wy = G.metric[5L * G.ncell + n0 + gi];
+                        const double wx = G.metric[9L * G.ncell + gi], wy = G.metric[9L * G.ncell + n0 + gi];
                         const S pw = sq[OFF_P][cb];
                         Fh[0] = Sc<S>::make(0.0);
                         Fh[1] = pw * wx;
@@ -407,7 +407,98 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             } else if constexpr (!PERT) {
                 num_flux<D, FLUX>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
             }
-            if constexpr (NSV) {
+            if constexpr (NSV && GEO >= 1) {
+                if (A.viscous_only) {
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) Fh[m] = Sc<S>::make(0.0);
+                }
+                if (bface != 2 && bface != 3) {   // no viscous flux through the far field
+                    const R half = (R)0.5;
+                    const int gy = y0 + fy;
+                    const int ga = wrap(gy - (d == 1), n1) * n0 + wrap(x0 + fx - (d == 0), n0);
+                    const S zero = Sc<S>::make(0.0);
+                    double sx, sy, dcx, dcy;
+                    S nu, nv, nT, tu, tv, tT, ufx, ufy, Tf;
+                    if (bface == 1) {
+                        // isothermal no-slip wall: velocity 0 and temperature t_wall on the wall
+                        const int gi = wrap(x0 + fx, n0);
+                        sx = G.metric[9L * G.ncell + gi];
+                        sy = G.metric[9L * G.ncell + n0 + gi];
+                        dcx = G.metric[9L * G.ncell + 2 * n0 + gi];
+                        dcy = G.metric[9L * G.ncell + 3 * n0 + gi];
+                        nu = sq[OFF_VEL][cb] - 0.0;
+                        nv = sq[OFF_VEL + 1][cb] - 0.0;
+                        nT = sq[OFF_T][cb] - G.t_wall;
+                        tu = tv = tT = zero;
+                        ufx = ufy = zero;
+                        Tf = half * (sq[OFF_T][cb] + G.t_wall);
+                    } else {
+                        sx = G.metric[(long)(2 * d) * G.ncell + ga];
+                        sy = G.metric[(long)(2 * d + 1) * G.ncell + ga];
+                        dcx = G.metric[(long)(5 + 2 * d) * G.ncell + ga];
+                        dcy = G.metric[(long)(6 + 2 * d) * G.ncell + ga];
+                        nu = sq[OFF_VEL][cb] - sq[OFF_VEL][ca];
+                        nv = sq[OFF_VEL + 1][cb] - sq[OFF_VEL + 1][ca];
+                        nT = sq[OFF_T][cb] - sq[OFF_T][ca];
+                        // index-space central differences along the face of both cells, averaged
+                        // (O-grid rows next to the wall or the far field: one-sided)
+                        const int st = T::stride(1 - d);
+                        int side = 0;
+                        if constexpr (GEO == 2) {
+                            if (d == 0) side = (gy == 0) ? 1 : (gy == n1 - 1 ? 2 : 0);
+                        }
+                        auto gc = [&](int k, int c) -> S {
+                            if (side == 1) return sq[k][c + st] - sq[k][c];
+                            if (side == 2) return sq[k][c] - sq[k][c - st];
+                            return (sq[k][c + st] - sq[k][c - st]) * half;
+                        };
+                        tu = half * (gc(OFF_VEL, ca) + gc(OFF_VEL, cb));
+                        tv = half * (gc(OFF_VEL + 1, ca) + gc(OFF_VEL + 1, cb));
+                        tT = half * (gc(OFF_T, ca) + gc(OFF_T, cb));
+                        ufx = half * (sq[OFF_VEL][ca] + sq[OFF_VEL][cb]);
+                        ufy = half * (sq[OFF_VEL + 1][ca] + sq[OFF_VEL + 1][cb]);
+                        Tf = half * (sq[OFF_T][ca] + sq[OFF_T][cb]);
+                    }
+                    // chain rule through the face's two grid directions
+                    const double J = dcx * sx + dcy * sy;
+                    S ux, uy, vx, vy, Tx, Ty;
+                    if (d == 0) {
+                        ux = (nu * sx - tu * dcy) / J;
+                        uy = (nu * sy + tu * dcx) / J;
+                        vx = (nv * sx - tv * dcy) / J;
+                        vy = (nv * sy + tv * dcx) / J;
+                        Tx = (nT * sx - tT * dcy) / J;
+                        Ty = (nT * sy + tT * dcx) / J;
+                    } else {
+                        ux = (nu * sx + tu * dcy) / J;
+                        uy = (nu * sy - tu * dcx) / J;
+                        vx = (nv * sx + tv * dcy) / J;
+                        vy = (nv * sy - tv * dcx) / J;
+                        Tx = (nT * sx + tT * dcy) / J;
+                        Ty = (nT * sy - tT * dcx) / J;
+                    }
+                    auto vflux = [&](auto mu_, auto c23_, auto kap_) {
+                        const S div = ux + vy;
+                        const S txx = mu_ * (ux + ux) - c23_ * div;
+                        const S tyy = mu_ * (vy + vy) - c23_ * div;
+                        const S txy = mu_ * (uy + vx);
+                        const S fx = txx * sx + txy * sy;
+                        const S fy = txy * sx + tyy * sy;
+                        const S en = (ufx * txx + ufy * txy + kap_ * Tx) * sx + (ufx * txy + ufy * tyy + kap_ * Ty) * sy;
+                        Fh[1] = Fh[1] - fx;
+                        Fh[2] = Fh[2] - fy;
+                        Fh[3] = Fh[3] - en;
+                    };
+                    if (G.suth) {
+                        const S th = Tf / (R)G.t_ref;
+                        const S muf = (R)G.mu * th * Sc<S>::sqrt_(th) * (R)G.suth_one_s / (th + (R)G.suth_s);
+                        vflux(muf, (R)(2.0 / 3.0) * muf, muf * (R)G.g / (R)G.kden);
+                    } else {
+                        vflux((R)G.mu, (R)G.c23mu, (R)G.kappa);
+                    }
+                }
+            }
+            if constexpr (NSV && GEO == 0) {
                 if (A.viscous_only) {
 #pragma unroll
                     for (int m = 0; m < NV; ++m) Fh[m] = Sc<S>::make(0.0);
@@ -557,8 +648,9 @@ static hipError_t dispatch_prec(const Geom& G, const ResArgs& A, int kind, bool 
 // j * nx + i; node (i + nx, j) is node (i, j) + (Lx, 0), node (i, j + ny) is
 // node (i, j) + (0, Ly)): for cell (i, j) with nodes p0 = (i, j), p1 = (i+1, j),
 // p2 = (i+1, j+1), p3 = (i, j+1), the east face vector (y2 - y1, x1 - x2), the
-// north face vector (y3 - y2, x2 - x3) and 1 / A with
-// A = ((x2 - x0)(y3 - y1) - (x3 - x1)(y2 - y0)) / 2; five arrays of ncell.
+// north face vector (y3 - y2, x2 - x3), 1 / A with
+// A = ((x2 - x0)(y3 - y1) - (x3 - x1)(y2 - y0)) / 2, and the centroid
+// differences across the east and north faces; nine arrays of ncell.
 __global__ __launch_bounds__(256) void k_metrics(const double* xn, const double* yn, int nx, int ny, double Lx,
                                                  double Ly, double* out) {
     const long c = (long)blockIdx.x * 256 + threadIdx.x;
@@ -580,12 +672,29 @@ __global__ __launch_bounds__(256) void k_metrics(const double* xn, const double*
     out[3 * ncell + c] = x2 - x3;
     const double area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0));
     out[4 * ncell + c] = 1.0 / area;
+    // centroid differences across the east and north faces: nodes (i+2, j), (i+2, j+1), (i, j+2), (i+1, j+2)
+    const bool e2 = (i + 2 >= nx), f2 = (j + 2 >= ny);
+    const int i2 = e2 ? i + 2 - nx : i + 2, j2 = f2 ? j + 2 - ny : j + 2;
+    const double x4 = e2 ? xn[(long)j * nx + i2] + Lx : xn[(long)j * nx + i2];
+    const double y4 = yn[(long)j * nx + i2];
+    const double x5 = e2 ? xn[(long)j1 * nx + i2] + Lx : xn[(long)j1 * nx + i2];
+    const double y5 = ej ? yn[(long)j1 * nx + i2] + Ly : yn[(long)j1 * nx + i2];
+    const double x6 = xn[(long)j2 * nx + i];
+    const double y6 = f2 ? yn[(long)j2 * nx + i] + Ly : yn[(long)j2 * nx + i];
+    const double x7 = ei ? xn[(long)j2 * nx + i1] + Lx : xn[(long)j2 * nx + i1];
+    const double y7 = f2 ? yn[(long)j2 * nx + i1] + Ly : yn[(long)j2 * nx + i1];
+    out[5 * ncell + c] = 0.25 * ((x4 + x5) - (x0 + x3));
+    out[6 * ncell + c] = 0.25 * ((y4 + y5) - (y0 + y3));
+    out[7 * ncell + c] = 0.25 * ((x6 + x7) - (x0 + x1));
+    out[8 * ncell + c] = 0.25 * ((y6 + y7) - (y0 + y1));
 }
 
 // Metrics of an O-grid: nodes (x, y) indexed j * nx + i for j = 0..ny (row 0 on
 // the wall, row ny on the far-field boundary), i periodic without offset; the
-// same per-cell arrays as k_metrics, then the wall face vectors
-// (y(i, 0) - y(i+1, 0), x(i+1, 0) - x(i, 0)) as two arrays of nx.
+// same nine per-cell arrays as k_metrics (the last row's north centroid
+// difference is 0: that face is the far field), then the wall face vectors
+// (y(i, 0) - y(i+1, 0), x(i+1, 0) - x(i, 0)) and the vectors from each wall
+// face's midpoint to the first cell's centroid, as four arrays of nx.
 __global__ __launch_bounds__(256) void k_metrics_ogrid(const double* xn, const double* yn, int nx, int ny,
                                                        double* out) {
     const long c = (long)blockIdx.x * 256 + threadIdx.x;
@@ -603,9 +712,21 @@ __global__ __launch_bounds__(256) void k_metrics_ogrid(const double* xn, const d
     out[3 * ncell + c] = x2 - x3;
     const double area = 0.5 * ((x2 - x0) * (y3 - y1) - (x3 - x1) * (y2 - y0));
     out[4 * ncell + c] = 1.0 / area;
+    const int i2 = (i + 2 >= nx) ? i + 2 - nx : i + 2;
+    out[5 * ncell + c] = 0.25 * ((xn[(long)j * nx + i2] + xn[(long)(j + 1) * nx + i2]) - (x0 + x3));
+    out[6 * ncell + c] = 0.25 * ((yn[(long)j * nx + i2] + yn[(long)(j + 1) * nx + i2]) - (y0 + y3));
+    if (j + 2 <= ny) {
+        out[7 * ncell + c] = 0.25 * ((xn[(long)(j + 2) * nx + i] + xn[(long)(j + 2) * nx + i1]) - (x0 + x1));
+        out[8 * ncell + c] = 0.25 * ((yn[(long)(j + 2) * nx + i] + yn[(long)(j + 2) * nx + i1]) - (y0 + y1));
+    } else {
+        out[7 * ncell + c] = 0.0;   // the far-field face
+        out[8 * ncell + c] = 0.0;
+    }
     if (j == 0) {
-        out[5 * ncell + i] = y0 - y1;
-        out[5 * ncell + nx + i] = x1 - x0;
+        out[9 * ncell + i] = y0 - y1;
+        out[9 * ncell + nx + i] = x1 - x0;
+        out[9 * ncell + 2 * nx + i] = 0.25 * ((x2 + x3) - (x0 + x1));
+        out[9 * ncell + 3 * nx + i] = 0.25 * ((y2 + y3) - (y0 + y1));
     }
 }
 
@@ -636,21 +757,23 @@ hipError_t launch_zero(void* p, long bytes, hipStream_t st) {
 }
 
 // Curvilinear grids: 2-D Euler physics in FP64 (value, FD and tangent kernels).
-template <int RECON, int FLUX, int GEO>
+template <int RECON, bool NSV, int FLUX, int GEO>
 static hipError_t dispatch_curv(const Geom& G, const ResArgs& A, int kind, hipStream_t st) {
-    if (kind == MODE_PLAIN) return launch_v<2, RECON, false, FLUX, GEO, double, MODE_PLAIN, double>(G, A, st);
-    if (kind == MODE_FD) return launch_v<2, RECON, false, FLUX, GEO, double, MODE_FD, double>(G, A, st);
-    return launch_v<2, RECON, false, FLUX, GEO, Dual<double>, MODE_TAN, double>(G, A, st);
+    if (kind == MODE_PLAIN) return launch_v<2, RECON, NSV, FLUX, GEO, double, MODE_PLAIN, double>(G, A, st);
+    if (kind == MODE_FD) return launch_v<2, RECON, NSV, FLUX, GEO, double, MODE_FD, double>(G, A, st);
+    return launch_v<2, RECON, NSV, FLUX, GEO, Dual<double>, MODE_TAN, double>(G, A, st);
 }
 
 template <int D, int RECON, bool NSV>
 static hipError_t dispatch_flux(const Geom& G, const ResArgs& A, int kind, bool fp32, bool out_double, hipStream_t st) {
     if (G.metric) {
-        if constexpr (D == 2 && !NSV) {
+        if constexpr (D == 2) {
             if (fp32) return hipErrorNotSupported;
             if (G.ogrid)
-                return G.flux == 1 ? dispatch_curv<RECON, 1, 2>(G, A, kind, st) : dispatch_curv<RECON, 0, 2>(G, A, kind, st);
-            return G.flux == 1 ? dispatch_curv<RECON, 1, 1>(G, A, kind, st) : dispatch_curv<RECON, 0, 1>(G, A, kind, st);
+                return G.flux == 1 ? dispatch_curv<RECON, NSV, 1, 2>(G, A, kind, st)
+                                   : dispatch_curv<RECON, NSV, 0, 2>(G, A, kind, st);
+            return G.flux == 1 ? dispatch_curv<RECON, NSV, 1, 1>(G, A, kind, st)
+                               : dispatch_curv<RECON, NSV, 0, 1>(G, A, kind, st);
         }
         return hipErrorNotSupported;
     }

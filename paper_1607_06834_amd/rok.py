@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib.rok_set_grid.restype = i
     lib.rok_grid_metric_bytes.argtypes = [vp]
     lib.rok_grid_metric_bytes.restype = sz
-    lib.rok_set_ogrid.argtypes = [vp, vp, vp, pd, vp, vp]
+    lib.rok_set_ogrid.argtypes = [vp, vp, vp, pd, d, vp, vp]
     lib.rok_set_ogrid.restype = i
     lib.rok_ogrid_metric_bytes.argtypes = [vp]
     lib.rok_ogrid_metric_bytes.restype = sz
@@ -303,21 +303,22 @@ class Rok:
             return
         nb = int(_lib.rok_grid_metric_bytes(self._ctx))
         if nb == 0:
-            raise ValueError("curvilinear grids need a 2-D Euler problem")
+            raise ValueError("curvilinear grids need a 2-D problem with at least 2 x 2 cells")
         xd = torch.as_tensor(xn, dtype=torch.float64).to(self.device).contiguous()
         yd = torch.as_tensor(yn, dtype=torch.float64).to(self.device).contiguous()
-        if xd.numel() * 5 * 8 != nb or yd.numel() != xd.numel():
+        if xd.numel() * 9 * 8 != nb or yd.numel() != xd.numel():
             raise ValueError("node arrays must have n[0] * n[1] entries")
         met = torch.empty(nb // 8, dtype=torch.float64, device=self.device)
         _check(_lib.rok_set_grid(self._ctx, _ptr(xd), _ptr(yd), _ptr(met), _stream()), "rok_set_grid")
         self._metrics = met            # kept alive while the context uses it
 
-    def set_ogrid(self, xn, yn, freestream):
-        """Use an O-grid (nodes [j][i], j = 0..n[1]; wall at row 0, far field past the last
-        row, free stream (rho, rho u, rho v, E)); rok_set_ogrid."""
+    def set_ogrid(self, xn, yn, freestream, t_wall: float = 1.0):
+        """Use an O-grid (nodes [j][i], j = 0..n[1]; wall at row 0 (isothermal at t_wall for
+        Navier-Stokes), far field past the last row, free stream (rho, rho u, rho v, E));
+        rok_set_ogrid."""
         nb = int(_lib.rok_ogrid_metric_bytes(self._ctx))
         if nb == 0:
-            raise ValueError("O-grids need a 2-D Euler problem")
+            raise ValueError("O-grids need a 2-D problem with at least 2 x 2 cells")
         xd = torch.as_tensor(xn, dtype=torch.float64).to(self.device).contiguous()
         yd = torch.as_tensor(yn, dtype=torch.float64).to(self.device).contiguous()
         n0, n1 = self._n[0], self._n[1]
@@ -325,7 +326,8 @@ class Rok:
             raise ValueError("node arrays must have n[0] * (n[1] + 1) entries")
         met = torch.empty(nb // 8, dtype=torch.float64, device=self.device)
         fs = (ctypes.c_double * 4)(*[float(v) for v in freestream])
-        _check(_lib.rok_set_ogrid(self._ctx, _ptr(xd), _ptr(yd), fs, _ptr(met), _stream()), "rok_set_ogrid")
+        _check(_lib.rok_set_ogrid(self._ctx, _ptr(xd), _ptr(yd), fs, float(t_wall), _ptr(met), _stream()),
+               "rok_set_ogrid")
         self._metrics = met
 
     def eigs(self, y, v0, k: int = 6, m: int = 40, max_restarts: int = 50, tol: float = 1e-10):

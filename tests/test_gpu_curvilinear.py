@@ -51,7 +51,7 @@ def test_curvilinear_residual_fd_tangent(dev, shape, recon, flux):
     pb = ri.problem(shape, (-1.0, 0.0), (2.0, 1.4), "euler", recon, flux=flux)
     P, g, nodes = setup(pb)
     g.set_grid(*nodes)
-    met = g._metrics.cpu().reshape(5, -1)
+    met = g._metrics.cpu().reshape(9, -1)
     for a, b in zip(met, fv.metrics(P)):
         assert torch.equal(a, b.reshape(-1))
     y = t64(ri.smooth_random_state(pb, seed=1, amplitude=0.2))
@@ -117,9 +117,9 @@ def test_curvilinear_refusals_and_reset(dev):
         g.vjp(y, torch.ones_like(y))
     g.set_grid(None, None)
     assert torch.equal(g.residual(y).cpu(), fv.residual(oracle_problem(pb), y.cpu()))
-    ns = Rok(ri.problem((12, 10), (0.0, 0.0), (1.0, 1.0), "ns", "muscl", mu=0.05))
+    g3 = Rok(ri.problem((6, 5, 4), (0.0,) * 3, (1.0, 1.0, 1.0), "euler", "first"))
     with pytest.raises(ValueError):
-        ns.set_grid(*nodes)
+        g3.set_grid(*nodes)
 
 
 # ---------------------------------------------------------------------------
@@ -151,9 +151,10 @@ def test_ogrid_residual_fd_tangent(dev, shape, recon, flux):
     met = g._metrics.cpu()
     ref_m = fv.ogrid_metrics(P)
     nc = shape[0] * shape[1]
-    for q in range(5):
+    for q in range(9):
         assert torch.equal(met[q * nc:(q + 1) * nc], ref_m[q].reshape(-1))
-    assert torch.equal(met[5 * nc:5 * nc + shape[0]], ref_m[5]) and torch.equal(met[5 * nc + shape[0]:], ref_m[6])
+    for q in range(4):
+        assert torch.equal(met[9 * nc + q * shape[0]:9 * nc + (q + 1) * shape[0]], ref_m[9 + q])
     ref = fv.residual(P, y)
     out = g.residual(y.to(dev)).cpu()
     assert torch.equal(out, ref), relerr(out, ref)
@@ -205,3 +206,82 @@ def test_ogrid_eigs_against_dense_spectrum(dev):
     e = _match(vals, want)
     say("ogrid eigs", restarts, conv, e, np.round(vals, 4))
     assert conv == 6 and e <= 1e-8
+
+
+
+# ---------------------------------------------------------------------------
+# Navier-Stokes on curvilinear grids and the isothermal wall
+# ---------------------------------------------------------------------------
+
+NSCASES = [(s, r, f, su) for s in [(6, 5), (37, 21), (70, 33)] for r in ("first", "muscl") for f in ("rusanov", "roe")
+           for su in (0.0, 0.4) if not (s == (6, 5) and f == "roe")]
+
+
+@pytest.mark.parametrize("shape,recon,flux,suth", NSCASES)
+def test_ns_curvilinear_residual_fd_tangent(dev, shape, recon, flux, suth):
+    say("ns curvilinear", shape, recon, flux, suth)
+    pb = ri.problem(shape, (-1.0, 0.0), (2.0, 1.4), "ns", recon, mu=0.05, flux=flux, sutherland=suth, t_ref=0.8)
+    P, g, nodes = setup(pb)
+    g.set_grid(*nodes)
+    y = t64(ri.smooth_random_state(pb, seed=1, amplitude=0.2))
+    ref = fv.residual(P, y)
+    out = g.residual(y.to(dev)).cpu()
+    assert torch.equal(out, ref), relerr(out, ref)
+    v = t64(ri.random_direction(P.size, seed=3))
+    eps = 1.7e-7
+    assert torch.equal(g.jvp(y.to(dev), v.to(dev), "fd", fy=ref.to(dev), eps=eps).cpu(), fv.jvp_fd(P, y, ref, v, eps))
+    assert relerr(g.jvp(y.to(dev), v.to(dev), "exact").cpu(), fv.jvp_exact(P, y, v)) <= 1e-12
+
+
+def _ogrid_ns_setup(nx, ny, recon, flux, suth, seed=5):
+    from paper_1607_06834_amd import Rok
+    from tests.test_oracle_ogrid import _state
+    import numpy as np
+    fs = ri.freestream(mach=0.3)
+    pb, nodes = ri.cylinder_ogrid(nx, ny, recon=recon, flux=flux)
+    pb = dict(pb, physics="ns", mu=0.02, sutherland=suth, t_ref=0.9)
+    P = oracle_problem(pb)
+    P.nodes, P.farfield, P.t_wall = nodes, fs, 1.1
+    y0 = _state(pb, nodes, seed, fs)
+    y = t64(y0 + 1e-2 * np.random.default_rng(seed).uniform(-1.0, 1.0, y0.size))
+    g = Rok(pb)
+    g.set_ogrid(*nodes, fs, t_wall=1.1)
+    return P, g, y
+
+
+ONSCASES = [(s, r, f, su) for s in [(16, 10), (37, 21)] for r in ("first", "muscl") for f in ("rusanov", "roe")
+            for su in (0.0, 0.4)]
+
+
+@pytest.mark.parametrize("shape,recon,flux,suth", ONSCASES)
+def test_ns_ogrid_isothermal_wall(dev, shape, recon, flux, suth):
+    say("ns ogrid", shape, recon, flux, suth)
+    P, g, y = _ogrid_ns_setup(*shape, recon, flux, suth)
+    met = g._metrics.cpu()
+    ref_m = fv.ogrid_metrics(P)
+    nc = shape[0] * shape[1]
+    for q in range(9):
+        assert torch.equal(met[q * nc:(q + 1) * nc], ref_m[q].reshape(-1))
+    for q in range(4):
+        assert torch.equal(met[9 * nc + q * shape[0]:9 * nc + (q + 1) * shape[0]], ref_m[9 + q])
+    ref = fv.residual(P, y)
+    out = g.residual(y.to(dev)).cpu()
+    assert torch.equal(out, ref), relerr(out, ref)
+    v = t64(ri.random_direction(P.size, seed=3))
+    eps = 1.7e-7
+    assert torch.equal(g.jvp(y.to(dev), v.to(dev), "fd", fy=ref.to(dev), eps=eps).cpu(), fv.jvp_fd(P, y, ref, v, eps))
+    assert relerr(g.jvp(y.to(dev), v.to(dev), "exact").cpu(), fv.jvp_exact(P, y, v)) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", ["fd", "exact"])
+def test_ns_ogrid_step_parity(dev, mode):
+    say("ns ogrid step", mode)
+    P, g, y = _ogrid_ns_setup(24, 16, "muscl", "roe", 0.4)
+    h = 1e-3
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, mode)
+    ref = rok.rok_step(f, mv, tab, 8, h, y)
+    out = g.step(y.to(dev), h, tab, 8, "fd" if mode == "fd" else "exact").cpu()
+    assert relerr(out, ref) <= 1e-12
+    if mode == "fd":
+        assert torch.equal(out, ref)

@@ -60,13 +60,13 @@ def test_host_validation_without_gpu():
     assert lib.rok_error_norm(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(24), 0.0, 0.0, 15.0,
                               ctypes.c_void_p(32), ctypes.c_void_p(256), 1 << 20, None) == rok.ROK_EINVAL
     # curvilinear grids: validated on the host (a partial set of pointers; 3-D or Navier-Stokes refused)
-    assert lib.rok_grid_metric_bytes(ctx) == 5 * 64 * 8
+    assert lib.rok_grid_metric_bytes(ctx) == 9 * 64 * 8
     assert lib.rok_set_grid(ctx, ctypes.c_void_p(8), None, ctypes.c_void_p(16), None) == rok.ROK_EINVAL
     assert lib.rok_set_grid(ctx, None, None, None, None) == rok.ROK_OK
-    assert lib.rok_ogrid_metric_bytes(ctx) == (5 * 64 + 2 * 8) * 8
+    assert lib.rok_ogrid_metric_bytes(ctx) == (9 * 64 + 4 * 8) * 8
     bad_fs = (ctypes.c_double * 4)(1.0, 0.0, 0.0, -1.0)          # negative pressure
-    assert lib.rok_set_ogrid(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), bad_fs, ctypes.c_void_p(24), None) == \
-        rok.ROK_EINVAL
+    assert lib.rok_set_ogrid(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), bad_fs, 1.0, ctypes.c_void_p(24),
+                             None) == rok.ROK_EINVAL
     # eigenvalue estimate: sizes are validated on the host
     assert lib.rok_eigs_workspace_bytes(ctx, 6, 40) > 0
     assert lib.rok_eigs_workspace_bytes(ctx, 9, 10) == 0 and lib.rok_eigs_workspace_bytes(ctx, 0, 10) == 0
@@ -86,6 +86,14 @@ def test_host_validation_without_gpu():
         if want == rok.ROK_OK:
             lib.rok_destroy(ctx)
     p.flux, p.sutherland, p.physics, p.mu = 0, 0.0, rok.NS, 0.05
+    ctx = ctypes.c_void_p()
+    assert lib.rok_create(ctypes.byref(p), ctypes.byref(ctx)) == rok.ROK_OK
+    assert lib.rok_grid_metric_bytes(ctx) == 9 * 64 * 8          # Navier-Stokes on curvilinear grids
+    ok_fs = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 2.5)
+    assert lib.rok_set_ogrid(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), ok_fs, -1.0, ctypes.c_void_p(24),
+                             None) == rok.ROK_EINVAL              # wall temperature must be positive
+    lib.rok_destroy(ctx)
+    p.ndim, p.n[2], p.hi[2] = 3, 4, 1.0
     ctx = ctypes.c_void_p()
     assert lib.rok_create(ctypes.byref(p), ctypes.byref(ctx)) == rok.ROK_OK
     assert lib.rok_grid_metric_bytes(ctx) == 0
