@@ -419,7 +419,10 @@ def adaptive_leg(args):
       * the 1024^2 MUSCL vortex to T = 40 h(CFL 4);
       * an impulsively started Mach 0.3 flow around a cylinder on a 128 x 64
         O-grid with very thin wall cells (first cell 2.5e-5, and 6.1e-7 in a
-        second case; slip wall, far field, Roe flux) to T = 0.05 from H0 = 1e-5.
+        second case; slip wall, far field, Roe flux) to T = 0.05 from H0 = 1e-5,
+        and a viscous one (Navier-Stokes, mu = 0.01 with Sutherland's law,
+        isothermal wall at the free-stream temperature, first cell 1.5e-4) to
+        T = 0.01.
     Error: ||y_T - y_ref|| / ||y_ref|| with y_ref the exact-product ROK solution
     (M = 20) at CFL 1/8, explicit RK4 at CFL 1/4 for the Mach 0.01 case, and
     adaptive explicit RK4 at rtol = atol = 1e-11 for the cylinder (the paper's
@@ -455,14 +458,19 @@ def adaptive_leg(args):
     # the same with wall cells 40 times thinner (first cell 6.1e-7)
     spb, snodes = ri.cylinder_ogrid(128, 64, radius=0.5, far=20.0, recon="first", flux="roe", cluster=16.0)
     cases.append(("cylinder_ogrid_128x64_thin", spb, cy0, ("time", 0.05), "erk_tight", (0, 4, 8)))
-    grids = {"cylinder_ogrid_128x64": cnodes, "cylinder_ogrid_128x64_thin": snodes}
+    # viscous cylinder (Re about 35 on the diameter, isothermal wall at the free-stream temperature, Sutherland
+    # viscosity): the wall-normal diffusion in the thin wall cells is the stiffest part of the spectrum
+    vpb, vnodes = ri.cylinder_ogrid(128, 64, radius=0.5, far=20.0, recon="first", flux="roe", cluster=10.0)
+    vpb = dict(vpb, physics="ns", mu=0.01, sutherland=0.4, t_ref=1.0)
+    cases.append(("cylinder_ns_128x64", vpb, cy0, ("time", 0.01), "erk_tight", (0, 4, 8)))
+    grids = {"cylinder_ogrid_128x64": cnodes, "cylinder_ogrid_128x64_thin": snodes, "cylinder_ns_128x64": vnodes}
     if args.adaptive_cases != "all":
         keep = args.adaptive_cases.split(",")
         cases = [c for c in cases if any(c[0].startswith(k) for k in keep)]
     for name, pb, y0, (kind, span), ref_kind, Ms in cases:
         g = Rok(pb, "fp64")
         if name.startswith("cylinder"):
-            g.set_ogrid(*grids[name], cfs)
+            g.set_ogrid(*grids[name], cfs, t_wall=(1.4 - 1.0) * (cfs[3] - 0.5 * cfs[1] ** 2 / cfs[0]) / cfs[0])
             h1 = 1e-5                   # first attempted step; "mean_cfl" is then in units of h1
         else:
             h1 = ri.cfl_step(pb, y0, 1.0)
