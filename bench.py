@@ -61,6 +61,8 @@ def parse():
                     help="also run the adaptive work-precision sweep (step doubling; ERK4 vs ROK4 M = 4, 8)")
     ap.add_argument("--adaptive-cases", default="all",
                     help="comma-separated name prefixes of the adaptive sweep's cases (default: all)")
+    ap.add_argument("--eigs", action="store_true",
+                    help="also run the stiffness diagnostic (largest eigenvalues of J on the cylinder O-grids)")
     ap.add_argument("--chain", action="store_true",
                     help="time a trajectory (each step starts from the previous result) instead of K passes "
                          "over the seeded input state")
@@ -519,6 +521,43 @@ def adaptive_leg(args):
     return out
 
 
+def eigs_leg(args):
+    """Stiffness diagnostic (rok_eigs): the 12 largest-magnitude eigenvalues of J at
+    the free stream on the cylinder O-grids of the adaptive sweep (inviscid with
+    wall cells of 2.5e-5 and 6.2e-7, viscous with 1.5e-4), with the restarts used,
+    the number converged (relative residual 1e-8) and the time of the call."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import rok_inputs as ri
+    from paper_1607_06834_amd import Rok
+
+    dev = torch.device("cuda", 0)
+    fs = ri.freestream(mach=0.3)
+    y0 = np.tile(np.asarray(fs, dtype=np.float64)[:, None], (1, 128 * 64)).reshape(-1)
+    tw = (1.4 - 1.0) * (fs[3] - 0.5 * fs[1] ** 2 / fs[0]) / fs[0]
+    out = {}
+    for name, cluster, ns in (("inviscid_wall_2.5e-5", 12.0, False), ("inviscid_wall_6.2e-7", 16.0, False),
+                              ("viscous_wall_1.5e-4", 10.0, True)):
+        pb, nodes = ri.cylinder_ogrid(128, 64, radius=0.5, far=20.0, recon="first", flux="roe", cluster=cluster)
+        if ns:
+            pb = dict(pb, physics="ns", mu=0.01, sutherland=0.4, t_ref=1.0)
+        g = Rok(pb, "fp64")
+        g.set_ogrid(*nodes, fs, t_wall=tw)
+        y = torch.tensor(y0, device=dev)
+        v0 = torch.tensor(ri.random_direction(g.N, seed=11), device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vals, res, restarts, conv = g.eigs(y, v0, k=12, m=40, max_restarts=300, tol=1e-8)
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"eigenvalues": [[round(float(v.real), 3), round(float(v.imag), 3)] for v in vals],
+                     "restarts": restarts, "converged": conv, "ms": round(ms, 1)}
+        print(f"[eigs] {name} {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_leg(args, pb, y0, w, tab, h):
     import torch
 
@@ -558,6 +597,7 @@ def main():
     eq = None if (args.no_equal_error or args.roofline_only) else equal_error_leg(args)
     ksw = krylov_sweep_leg(args) if (args.krylov_sweep and not args.roofline_only) else None
     ada = adaptive_leg(args) if (args.adaptive and not args.roofline_only) else None
+    eig = eigs_leg(args) if (args.eigs and not args.roofline_only) else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, pb, y0, w, tab, h)
     n = "x".join(str(x) for x in pb["n"])
     line = {
@@ -588,6 +628,7 @@ def main():
         "equal_error": eq,
         "krylov_sweep": ksw,
         "adaptive": ada,
+        "eigs": eig,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
