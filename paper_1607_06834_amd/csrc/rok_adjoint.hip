@@ -2,7 +2,7 @@
 //   ybar (+)= J(y)^T wbar                          (first-order adjoint)
 //   ybar2 (+)= d/dt [J(y + t v)^T wbar] at t = 0   (second-order adjoint)
 // for the Euler right-hand side f of Sec. 3.2, eq. (11) (first-order or
-// MUSCL-minmod reconstruction, Rusanov flux, periodic grid).
+// MUSCL-minmod reconstruction, Rusanov or Roe flux, periodic grid).
 //
 // f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d, so the adjoint of the face
 // a+1/2 (between cells a and a+1) is Fbar = (wbar_{a+1} - wbar_a) / dx_d, and
@@ -11,7 +11,8 @@
 // Each thread owns one cell and gathers its own contributions, so the result
 // is deterministic without atomics; Fbar^T dFhat/dU_c comes from one reverse
 // sweep of the face flux (face_flux_vjp, the transpose of the tangent of the
-// residual's flux code).  With a dual scalar (y + t v) the same kernel returns
+// residual's flux code) for Rusanov's flux, and from one forward-mode
+// evaluation per variable of c for Roe's.  With a dual scalar (y + t v) the same kernel returns
 // the second-order adjoint in the tangent part.
 #include "rok.h"
 #include "rok_device.hpp"
@@ -20,7 +21,7 @@
 
 namespace rok {
 
-template <int D, int RECON, bool SECOND>
+template <int D, int RECON, bool SECOND, int FLUX>
 __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const double* v, const double* wbar,
                                             double* ybar, double* ybar2, int accumulate, const int* gate, int col) {
     if (gate && col >= gate[0]) return;   // Krylov column beyond M_eff: nothing to add
@@ -73,7 +74,26 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
                         else base[q][m] = y[i];
                         ub[q][m] = Sc<T>::make(0.0);
                     }
-                face_flux_vjp<D, RECON, T>(G, base, d, fbar, ub);
+                if constexpr (FLUX == 0) {
+                    face_flux_vjp<D, RECON, T>(G, base, d, fbar, ub);
+                } else {
+                    // Roe: Fbar^T dFhat/dU_c by forward mode, one dual direction per variable of c
+                    using TT = Dual<T>;
+#pragma unroll 1
+                    for (int m = 0; m < NV; ++m) {
+                        TT Ud[NS][NV], Fd[NV];
+#pragma unroll
+                        for (int q = 0; q < NS; ++q)
+#pragma unroll
+                            for (int k = 0; k < NV; ++k)
+                                Ud[q][k] = TT{base[q][k], Sc<T>::make((q == kc && k == m) ? 1.0 : 0.0)};
+                        face_flux_cells<D, RECON, TT, 1>(G, Ud, d, Fd);
+                        T sum = Sc<T>::make(0.0);
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) sum = sum + fbar[k] * Fd[k].d;
+                        ub[kc][m] = sum;
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
                     if (q == kc)
@@ -94,18 +114,25 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
     }
 }
 
-template <int D, int RECON>
-static hipError_t launch_vjp_t(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
+template <int D, int RECON, int FLUX>
+static hipError_t launch_vjp_f(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
                                double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
     long g = (G.ncell + 255) / 256;
     if (g > 16384) g = 16384;
     if (v)
-        hipLaunchKernelGGL((k_vjp<D, RECON, true>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar, ybar2,
-                           accumulate, gate, col);
+        hipLaunchKernelGGL((k_vjp<D, RECON, true, FLUX>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar,
+                           ybar2, accumulate, gate, col);
     else
-        hipLaunchKernelGGL((k_vjp<D, RECON, false>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar,
+        hipLaunchKernelGGL((k_vjp<D, RECON, false, FLUX>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar,
                            ybar2, accumulate, gate, col);
     return hipGetLastError();
+}
+
+template <int D, int RECON>
+static hipError_t launch_vjp_t(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
+                               double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
+    if (G.flux == 1) return launch_vjp_f<D, RECON, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+    return launch_vjp_f<D, RECON, 0>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
 }
 
 hipError_t launch_vjp(const Geom& G, int recon, const double* y, const double* v, const double* wbar, double* ybar,

@@ -170,8 +170,8 @@ __device__ __forceinline__ void primitives(const Geom& G, const S* U, S& r, S* v
 
 // Inviscid flux of the face between stencil cells a and b = a + 1 along d,
 // from the conserved states of the stencil: first order U[0] = a, U[1] = b;
-// MUSCL U[0..3] = a-1, a, b, b+1.
-template <int D, int RECON, typename S>
+// MUSCL U[0..3] = a-1, a, b, b+1.  FLUX: 0 Rusanov, 1 Roe.
+template <int D, int RECON, typename S, int FLUX = 0>
 __device__ __forceinline__ void face_flux_cells(const Geom& G, const S (*U)[D + 2], int d, S* Fh) {
     using R = typename Sc<S>::R;
     constexpr int NV = D + 2;
@@ -215,7 +215,8 @@ __device__ __forceinline__ void face_flux_cells(const Geom& G, const S (*U)[D + 
         to_conserved<D>(G, rL, vL, pL, UL);
         to_conserved<D>(G, rR, vR, pR, UR);
     }
-    rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+    if constexpr (FLUX == 0) rusanov<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+    else roe<D>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
 }
 
 // ---------------------------------------------------------------------------

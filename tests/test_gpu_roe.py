@@ -6,7 +6,8 @@ Same bars as the Rusanov path: FP64 residual and FD products bit for bit
 vortex trajectory bit for bit, FP32 residual/tangent within 2e-6 of the FP64
 oracle on smooth states.  A transonic state puts many faces inside the
 entropy-fix band of the acoustic waves, so both branches are compared.  The
-adjoint entry points refuse the Roe flux (ROK_EUNSUPPORTED).
+adjoint products (Euler, FP64) against the oracle's reverse mode to 1e-12,
+the step adjoint to 1e-10.
 """
 import math
 import sys
@@ -158,12 +159,76 @@ def test_roe_vortex32_trajectory(dev):
         assert torch.equal(yg.cpu(), yr), (n, relerr(yg.cpu(), yr))
 
 
-def test_roe_adjoint_refused(dev):
-    from paper_1607_06834_amd.rok import RokError
-    pb = VARIANTS["euler_fo"]((8, 8))
+ADJ_CASES = [("euler_fo", (37, 21)), ("euler_muscl", (6, 5)), ("euler_muscl", (37, 21)), ("euler3d_fo", (5, 4, 3)),
+             ("euler3d_muscl", (11, 7, 6))]
+
+
+@pytest.mark.parametrize("name,shape", ADJ_CASES)
+def test_roe_vjp_matches_oracle(dev, name, shape):
+    """J(y)^T wbar and d/dt [J(y + t v)^T wbar] of the Roe residual against
+    the oracle's reverse-mode products, 1e-12 normwise."""
+    pb = VARIANTS[name](shape)
+    # first order also on the transonic state (entropy-fix branch); MUSCL's
+    # minmod would meet zero transverse slopes there, a kink
+    states = _states(pb, 3) if "fo" in name else _states(pb, 3)[:1]
+    for kind, y in states:
+        _roe_vjp_case(dev, pb, name, shape, kind, y)
+
+
+def _roe_vjp_case(dev, pb, name, shape, kind, y):
+    say("roe vjp", name, shape, kind)
+    v, w = ri.random_direction(y.size, 103), ri.random_direction(y.size, 203)
+    P = oracle_problem(pb)
+    ref1 = fv.vjp(P, t64(y), t64(w))
+    ref2 = fv.vjp_second(P, t64(y), t64(v), t64(w))
     g = gpu(pb)
+    yd, vd, wd = (torch.tensor(a, device=dev) for a in (y, v, w))
+    got = g.vjp(yd, wd).cpu()
+    e1 = relerr(got, ref1)
+    g1, g2 = g.vjp(yd, wd, v=vd)
+    e2 = relerr(g2.cpu(), ref2)
+    say("  relerr", e1, e2)
+    assert e1 <= 1e-12
+    assert torch.equal(g1.cpu(), got)
+    assert e2 <= 1e-12
+    # <J v, w> = <v, J^T w> with the GPU tangent and adjoint kernels
+    jv = g.jvp(yd, vd, mode="tangent")
+    a, b = float(torch.dot(jv, wd)), float(torch.dot(vd, g1))
+    assert abs(a - b) <= 1e-13 * float(torch.linalg.norm(jv) * torch.linalg.norm(wd))
+
+
+@pytest.mark.parametrize("recon,n,M", [("first", 8, 6), ("muscl", 12, 8), ("first", 8, 0)])
+def test_roe_step_vjp_matches_oracle_gradient(dev, recon, n, M):
+    """Gradient of c . y_{n+1} through one exact-product ROK4 step with Roe's
+    flux, against the oracle's reverse-mode differentiation of the step, 1e-10."""
+    from oracle import rok_ad
+    say("roe step vjp", recon, n, M)
+    pb = dict(ri.vortex_problem(n, recon), flux="roe")
+    y0 = ri.smooth_random_state(pb, seed=11)
+    P = oracle_problem(pb)
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, 2.0 if M else 0.5)
+    c = ri.random_direction(y0.size, 5)
+    ref = rok_ad.gradient(lambda z: torch.dot(t64(c), rok_ad.rok_step(P, tab, M, h, z)), t64(y0))
+    g = gpu(pb)
+    yd, cd = torch.tensor(y0, device=dev), torch.tensor(c, device=dev)
+    y1 = torch.empty_like(yd)
+    gr = g.step_vjp(yd, cd, h, tab, M, y_next_out=y1).cpu()
+    err = relerr(gr, ref)
+    say("  relerr", err)
+    assert err <= 1e-10
+    assert torch.equal(y1, g.step(yd, h, tab, M, mode="tangent"))
+
+
+def test_roe_adjoint_refused_outside_euler_fp64(dev):
+    from paper_1607_06834_amd.rok import RokError
+    pb = VARIANTS["ns_fo"]((8, 8))
     y = torch.tensor(ri.smooth_random_state(pb, seed=1), device=dev)
     with pytest.raises(RokError):
-        g.vjp(y, torch.ones_like(y))
+        gpu(pb).vjp(y, torch.ones_like(y))
+    pe = VARIANTS["euler_fo"]((8, 8))
+    ye = torch.tensor(ri.smooth_random_state(pe, seed=1), device=dev)
     with pytest.raises(RokError):
-        g.step_vjp(y, torch.ones_like(y), 1e-3, ri.rok4_tableau(), 4)
+        gpu(pe, precision="fp32").vjp(ye, torch.ones_like(ye))
+    with pytest.raises(RokError):
+        gpu(pe, precision="fp32").step_vjp(ye, torch.ones_like(ye), 1e-3, ri.rok4_tableau(), 4)
