@@ -384,8 +384,8 @@ size_t rok_adaptive_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *   y_n, ybar_np1, ybar_n, y_np1: N doubles each, device memory; ybar_n and
  *               y_np1 may not alias any other argument
  *   work:       rok_step_vjp_workspace_bytes(ctx, M, tab->s) bytes
- * Euler physics on Cartesian grids and FP64 precision only (ROK_EUNSUPPORTED
- * otherwise).
+ * Cartesian grids (Euler or Navier-Stokes physics, either flux) and FP64
+ * precision only (ROK_EUNSUPPORTED otherwise).
  */
 rok_status rok_step_vjp(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
                         const double* ybar_np1, double* ybar_n, double* y_np1, void* work, size_t work_bytes,
@@ -410,7 +410,7 @@ size_t rok_step_vjp_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *           vector, exchange and status words), so a forward may be reversed
  *           several times
  *   adj_work: rok_step_vjp_adjoint_bytes(ctx, M, tab->s) bytes, device memory
- * Results are bitwise those of rok_step_vjp.  Euler physics, Cartesian grids and FP64
+ * Results are bitwise those of rok_step_vjp.  Cartesian grids and FP64
  * precision only (ROK_EUNSUPPORTED otherwise).
  */
 rok_status rok_step_vjp_stored(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
@@ -424,9 +424,10 @@ size_t rok_step_vjp_adjoint_bytes(const rok_ctx* ctx, int M, int s);
  * Adjoint product of the residual (transposed Jacobian, Sec. 2.3 / eq. 11):
  *   ybar = J(y)^T wbar          (accumulate = 0)
  *   ybar = ybar + J(y)^T wbar   (accumulate = 1)
- * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  Euler physics on
- * Cartesian grids, either flux, FP64 precision only (ROK_EUNSUPPORTED otherwise).  Deterministic: each cell
- * gathers its own contributions.
+ * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  Euler or
+ * Navier-Stokes physics (constant or Sutherland viscosity), either flux, on
+ * Cartesian grids in FP64 precision only (ROK_EUNSUPPORTED otherwise).
+ * Deterministic: each cell gathers its own contributions.
  */
 rok_status rok_residual_vjp(rok_ctx* ctx, const double* y, const double* wbar, double* ybar, int accumulate,
                             void* stream);

@@ -1,8 +1,9 @@
 // Adjoint (transposed) Jacobian products of the finite-volume residual:
 //   ybar (+)= J(y)^T wbar                          (first-order adjoint)
 //   ybar2 (+)= d/dt [J(y + t v)^T wbar] at t = 0   (second-order adjoint)
-// for the Euler right-hand side f of Sec. 3.2, eq. (11) (first-order or
-// MUSCL-minmod reconstruction, Rusanov or Roe flux, periodic grid).
+// for the right-hand side f of Sec. 3.2, eq. (11) (Euler or Navier-Stokes
+// physics, first-order or MUSCL-minmod reconstruction, Rusanov or Roe flux,
+// periodic Cartesian grid).
 //
 // f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d, so the adjoint of the face
 // a+1/2 (between cells a and a+1) is Fbar = (wbar_{a+1} - wbar_a) / dx_d, and
@@ -21,7 +22,66 @@
 
 namespace rok {
 
-template <int D, int RECON, bool SECOND, int FLUX>
+// Viscous flux of the Cartesian face between cells a and b = a + e_d
+// (Sec. 3.2: stress row and energy term), from the conserved states of its
+// stencil: U[0] = a, U[1] = b and, for the k-th direction t != d,
+// U[2 + 4k .. 5 + 4k] = a - e_t, a + e_t, b - e_t, b + e_t.  Normal
+// derivatives are the difference across the face; tangential ones the mean
+// of the central differences in a and b; the viscosity is constant or
+// Sutherland's law at the mean temperature of a and b.
+template <int D, typename S>
+__device__ __forceinline__ void visc_face(const Geom& G, const S (*U)[D + 2], int d, S* Fv) {
+    constexpr int NQ = 2 + 4 * (D - 1);
+    const double half = 0.5;
+    S vel[NQ][D], Tq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        S r, p;
+        primitives<D>(G, U[q], r, vel[q], p);
+        Tq[q] = p / r;
+    }
+    S Gr[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+            if (bb == d) {
+                Gr[a][bb] = (vel[1][a] - vel[0][a]) * G.invdx[d];
+            } else {
+                const int k = (bb < d) ? bb : bb - 1;
+                const S gca = (vel[3 + 4 * k][a] - vel[2 + 4 * k][a]) * G.hinv[bb];
+                const S gcb = (vel[5 + 4 * k][a] - vel[4 + 4 * k][a]) * G.hinv[bb];
+                Gr[a][bb] = half * (gca + gcb);
+            }
+        }
+    }
+    S div = Gr[0][0];
+#pragma unroll
+    for (int a = 1; a < D; ++a) div = div + Gr[a][a];
+    S mu, c23mu, kappa;
+    if (G.suth) {
+        const S th = (half * (Tq[0] + Tq[1])) / G.t_ref;
+        mu = G.mu * th * Sc<S>::sqrt_(th) * G.suth_one_s / (th + G.suth_s);
+        c23mu = (2.0 / 3.0) * mu;
+        kappa = mu * G.g / G.kden;
+    } else {
+        mu = Sc<S>::make(G.mu);
+        c23mu = Sc<S>::make(G.c23mu);
+        kappa = Sc<S>::make(G.kappa);
+    }
+    S work;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const S tau = (a == d) ? mu * (Gr[a][d] + Gr[d][a]) - c23mu * div : mu * (Gr[a][d] + Gr[d][a]);
+        const S uf = half * (vel[0][a] + vel[1][a]);
+        work = (a == 0) ? uf * tau : work + uf * tau;
+        Fv[1 + a] = tau;
+    }
+    Fv[0] = Sc<S>::make(0.0);
+    Fv[D + 1] = work + kappa * ((Tq[1] - Tq[0]) * G.invdx[d]);
+}
+
+template <int D, int RECON, bool SECOND, int FLUX, bool NSV>
 __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const double* v, const double* wbar,
                                             double* ybar, double* ybar2, int accumulate, const int* gate, int col) {
     if (gate && col >= gate[0]) return;   // Krylov column beyond M_eff: nothing to add
@@ -100,6 +160,84 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
 #pragma unroll
                         for (int k = 0; k < NV; ++k) acc[k] = acc[k] + ub[q][k];
             }
+            if constexpr (NSV) {
+                // The face flux is Fhat - Fv: cell c collects -Fbar^T dFv/dU_c
+                // from every face whose viscous stencil holds it, one face per
+                // stencil position (position kv of c), each by forward mode.
+                constexpr int NQ = 2 + 4 * (D - 1);
+                auto cell_at = [&](int od, int ot, int t) -> long {
+                    int o[3] = {0, 0, 0};
+                    o[d] += od;
+                    if (ot) o[t] += ot;
+                    const int x = wrap(cx + o[0], n0), yy = wrap(cy + o[1], n1);
+                    const int z = (D == 3) ? wrap(cz + o[2], n2) : 0;
+                    return ((long)z * n1 + yy) * n0 + x;
+                };
+#pragma nounroll
+                for (int kv = 0; kv < NQ; ++kv) {
+                    // offset of face cell a from c, and of each stencil cell from a
+                    int ad = 0, at = 0, tdir = 0;
+                    if (kv == 0) ad = 0;
+                    else if (kv == 1) ad = -1;
+                    else {
+                        const int k = (kv - 2) / 4, r = (kv - 2) % 4;
+                        tdir = (k < d) ? k : k + 1;
+                        ad = (r >= 2) ? -1 : 0;          // c on the b side
+                        at = (r % 2 == 0) ? 1 : -1;      // c = a - e_t (r even) or a + e_t
+                    }
+                    long cell[NQ];
+                    cell[0] = cell_at(ad, at, tdir);
+                    cell[1] = cell_at(ad + 1, at, tdir);
+#pragma unroll
+                    for (int k = 0; k < D - 1; ++k) {
+                        const int t = (k < d) ? k : k + 1;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int od = ad + (r >= 2 ? 1 : 0);
+                            int ot = (r % 2 == 0) ? -1 : 1;
+                            // offsets along t add up: (a's offset from c) + (stencil cell's from a)
+                            if (t == tdir) cell[2 + 4 * k + r] = cell_at(od, at + ot, t);
+                            else {
+                                int o3[3] = {0, 0, 0};
+                                o3[d] += od;
+                                o3[tdir] += at;
+                                o3[t] += ot;
+                                const int x = wrap(cx + o3[0], n0), yy = wrap(cy + o3[1], n1);
+                                const int z = (D == 3) ? wrap(cz + o3[2], n2) : 0;
+                                cell[2 + 4 * k + r] = ((long)z * n1 + yy) * n0 + x;
+                            }
+                        }
+                    }
+                    T fbar[NV];
+#pragma unroll
+                    for (int m = 0; m < NV; ++m)
+                        fbar[m] = Sc<T>::make((wbar[m * ncell + cell[1]] - wbar[m * ncell + cell[0]]) * inv);
+                    T base[NQ][NV];
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) {
+                            const long i = m * ncell + cell[q];
+                            if constexpr (SECOND) base[q][m] = T{y[i], v[i]};
+                            else base[q][m] = y[i];
+                        }
+                    using TT = Dual<T>;
+#pragma unroll 1
+                    for (int m = 0; m < NV; ++m) {
+                        TT Ud[NQ][NV], Fd[NV];
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                            for (int k = 0; k < NV; ++k)
+                                Ud[q][k] = TT{base[q][k], Sc<T>::make((q == kv && k == m) ? 1.0 : 0.0)};
+                        visc_face<D, TT>(G, Ud, d, Fd);
+                        T sum = Sc<T>::make(0.0);
+#pragma unroll
+                        for (int k = 1; k < NV; ++k) sum = sum + fbar[k] * Fd[k].d;
+                        acc[m] = acc[m] - sum;
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -114,25 +252,32 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
     }
 }
 
-template <int D, int RECON, int FLUX>
+template <int D, int RECON, int FLUX, bool NSV>
 static hipError_t launch_vjp_f(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
                                double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
     long g = (G.ncell + 255) / 256;
     if (g > 16384) g = 16384;
     if (v)
-        hipLaunchKernelGGL((k_vjp<D, RECON, true, FLUX>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar,
-                           ybar2, accumulate, gate, col);
+        hipLaunchKernelGGL((k_vjp<D, RECON, true, FLUX, NSV>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar,
+                           ybar, ybar2, accumulate, gate, col);
     else
-        hipLaunchKernelGGL((k_vjp<D, RECON, false, FLUX>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar, ybar,
-                           ybar2, accumulate, gate, col);
+        hipLaunchKernelGGL((k_vjp<D, RECON, false, FLUX, NSV>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar,
+                           ybar, ybar2, accumulate, gate, col);
     return hipGetLastError();
+}
+
+template <int D, int RECON, bool NSV>
+static hipError_t launch_vjp_n(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
+                               double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
+    if (G.flux == 1) return launch_vjp_f<D, RECON, 1, NSV>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+    return launch_vjp_f<D, RECON, 0, NSV>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
 }
 
 template <int D, int RECON>
 static hipError_t launch_vjp_t(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
                                double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
-    if (G.flux == 1) return launch_vjp_f<D, RECON, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
-    return launch_vjp_f<D, RECON, 0>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+    if (G.mu != 0.0) return launch_vjp_n<D, RECON, true>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+    return launch_vjp_n<D, RECON, false>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
 }
 
 hipError_t launch_vjp(const Geom& G, int recon, const double* y, const double* v, const double* wbar, double* ybar,

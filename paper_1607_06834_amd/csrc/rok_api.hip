@@ -37,9 +37,9 @@ rok_status hip_status(hipError_t e) {
 
 bool fp32(const rok_ctx* c) { return c->pb.precision == ROK_FP32_RESIDUAL; }
 
-// The adjoint kernels cover Euler physics on Cartesian grids in FP64.
+// The adjoint kernels cover Euler and Navier-Stokes physics on Cartesian grids in FP64.
 bool adjoint_supported(const rok_ctx* c) {
-    return c->pb.physics == ROK_EULER && !fp32(c) && !c->G.metric;
+    return !fp32(c) && !c->G.metric;
 }
 
 rok::ResArgs plain_args(const double* y, void* out) {
