@@ -384,8 +384,9 @@ size_t rok_adaptive_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *   y_n, ybar_np1, ybar_n, y_np1: N doubles each, device memory; ybar_n and
  *               y_np1 may not alias any other argument
  *   work:       rok_step_vjp_workspace_bytes(ctx, M, tab->s) bytes
- * Cartesian grids (Euler or Navier-Stokes physics, either flux) and FP64
- * precision only (ROK_EUNSUPPORTED otherwise).
+ * FP64 precision; Euler or Navier-Stokes physics on Cartesian grids, Euler
+ * physics on periodic curvilinear grids (rok_set_grid); either flux
+ * (ROK_EUNSUPPORTED otherwise: FP32, O-grids, Navier-Stokes on curvilinear grids).
  */
 rok_status rok_step_vjp(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
                         const double* ybar_np1, double* ybar_n, double* y_np1, void* work, size_t work_bytes,
@@ -410,8 +411,7 @@ size_t rok_step_vjp_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *           vector, exchange and status words), so a forward may be reversed
  *           several times
  *   adj_work: rok_step_vjp_adjoint_bytes(ctx, M, tab->s) bytes, device memory
- * Results are bitwise those of rok_step_vjp.  Cartesian grids and FP64
- * precision only (ROK_EUNSUPPORTED otherwise).
+ * Results are bitwise those of rok_step_vjp; the same restrictions.
  */
 rok_status rok_step_vjp_stored(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
                                const double* ybar_np1, double* ybar_n, void* fwd_work, size_t fwd_bytes,
@@ -424,9 +424,10 @@ size_t rok_step_vjp_adjoint_bytes(const rok_ctx* ctx, int M, int s);
  * Adjoint product of the residual (transposed Jacobian, Sec. 2.3 / eq. 11):
  *   ybar = J(y)^T wbar          (accumulate = 0)
  *   ybar = ybar + J(y)^T wbar   (accumulate = 1)
- * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  Euler or
- * Navier-Stokes physics (constant or Sutherland viscosity), either flux, on
- * Cartesian grids in FP64 precision only (ROK_EUNSUPPORTED otherwise).
+ * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  FP64 precision;
+ * Euler or Navier-Stokes physics (constant or Sutherland viscosity) on
+ * Cartesian grids, Euler physics on periodic curvilinear grids; either flux
+ * (ROK_EUNSUPPORTED otherwise).
  * Deterministic: each cell gathers its own contributions.
  */
 rok_status rok_residual_vjp(rok_ctx* ctx, const double* y, const double* wbar, double* ybar, int accumulate,

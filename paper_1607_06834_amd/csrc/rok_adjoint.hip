@@ -3,7 +3,9 @@
 //   ybar2 (+)= d/dt [J(y + t v)^T wbar] at t = 0   (second-order adjoint)
 // for the right-hand side f of Sec. 3.2, eq. (11) (Euler or Navier-Stokes
 // physics, first-order or MUSCL-minmod reconstruction, Rusanov or Roe flux,
-// periodic Cartesian grid).
+// periodic Cartesian grid; Euler physics also on a periodic 2-D curvilinear
+// grid, where f_c divides by the cell area and each face flux is the
+// rotated one).
 //
 // f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d, so the adjoint of the face
 // a+1/2 (between cells a and a+1) is Fbar = (wbar_{a+1} - wbar_a) / dx_d, and
@@ -81,7 +83,73 @@ __device__ __forceinline__ void visc_face(const Geom& G, const S (*U)[D + 2], in
     Fv[D + 1] = work + kappa * ((Tq[1] - Tq[0]) * G.invdx[d]);
 }
 
-template <int D, int RECON, bool SECOND, int FLUX, bool NSV>
+// Inviscid flux through a face of a 2-D curvilinear grid with face vector
+// (sx, sy): the stencil's states reconstructed in index space (first order
+// U[0] = a, U[1] = b; MUSCL U[0..3] = a-1, a, b, b+1), rotated into the face
+// frame n = S / |S|, the one-dimensional numerical flux there, rotated back
+// and scaled by |S|.
+template <int RECON, int FLUX, typename S>
+__device__ __forceinline__ void curv_face_flux(const Geom& G, const S (*U)[4], double sx, double sy, S* Fh) {
+    S UL[4], UR[4], vL[2], vR[2], rL, rR, pL, pR;
+    if constexpr (RECON == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            UL[m] = U[0][m];
+            UR[m] = U[1][m];
+        }
+        primitives<2>(G, UL, rL, vL, pL);
+        primitives<2>(G, UR, rR, vR, pR);
+    } else {
+        S q[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            S rr, vv[2], pp;
+            primitives<2>(G, U[k], rr, vv, pp);
+            q[k][0] = rr;
+            q[k][1] = vv[0];
+            q[k][2] = vv[1];
+            q[k][3] = pp;
+        }
+        S qL[4], qR[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            qL[m] = q[1][m] + 0.5 * minmod(q[1][m] - q[0][m], q[2][m] - q[1][m]);
+            qR[m] = q[2][m] - 0.5 * minmod(q[2][m] - q[1][m], q[3][m] - q[2][m]);
+        }
+        rL = qL[0];
+        rR = qR[0];
+        vL[0] = qL[1];
+        vL[1] = qL[2];
+        vR[0] = qR[1];
+        vR[1] = qR[2];
+        pL = qL[3];
+        pR = qR[3];
+        to_conserved<2>(G, rL, vL, pL, UL);
+        to_conserved<2>(G, rR, vR, pR, UR);
+    }
+    const double ln = sqrt(sx * sx + sy * sy);
+    const double nx = sx / ln, ny = sy / ln;
+    S vLr[2], vRr[2], ULr[4], URr[4], Fr[4];
+    vLr[0] = vL[0] * nx + vL[1] * ny;
+    vLr[1] = vL[1] * nx - vL[0] * ny;
+    vRr[0] = vR[0] * nx + vR[1] * ny;
+    vRr[1] = vR[1] * nx - vR[0] * ny;
+    ULr[0] = UL[0];
+    ULr[1] = UL[1] * nx + UL[2] * ny;
+    ULr[2] = UL[2] * nx - UL[1] * ny;
+    ULr[3] = UL[3];
+    URr[0] = UR[0];
+    URr[1] = UR[1] * nx + UR[2] * ny;
+    URr[2] = UR[2] * nx - UR[1] * ny;
+    URr[3] = UR[3];
+    num_flux<2, FLUX>(G, 0, ULr, rL, vLr, pL, URr, rR, vRr, pR, Fr);
+    Fh[0] = Fr[0] * ln;
+    Fh[1] = (Fr[1] * nx - Fr[2] * ny) * ln;
+    Fh[2] = (Fr[1] * ny + Fr[2] * nx) * ln;
+    Fh[3] = Fr[3] * ln;
+}
+
+template <int D, int RECON, bool SECOND, int FLUX, bool NSV, int GEO>
 __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const double* v, const double* wbar,
                                             double* ybar, double* ybar2, int accumulate, const int* gate, int col) {
     if (gate && col >= gate[0]) return;   // Krylov column beyond M_eff: nothing to add
@@ -121,9 +189,17 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
                 const long ca = cell[(RECON == 0) ? 0 : 1];
                 const long cb = cell[(RECON == 0) ? 1 : 2];
                 T fbar[NV];
+                if constexpr (GEO == 0) {
 #pragma unroll
-                for (int m = 0; m < NV; ++m)
-                    fbar[m] = Sc<T>::make((wbar[m * ncell + cb] - wbar[m * ncell + ca]) * inv);
+                    for (int m = 0; m < NV; ++m)
+                        fbar[m] = Sc<T>::make((wbar[m * ncell + cb] - wbar[m * ncell + ca]) * inv);
+                } else {
+                    // f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / A_c
+                    const double ia = G.metric[4 * ncell + ca], ib = G.metric[4 * ncell + cb];
+#pragma unroll
+                    for (int m = 0; m < NV; ++m)
+                        fbar[m] = Sc<T>::make(wbar[m * ncell + cb] * ib - wbar[m * ncell + ca] * ia);
+                }
                 T base[NS][NV], ub[NS][NV];
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
@@ -134,7 +210,26 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
                         else base[q][m] = y[i];
                         ub[q][m] = Sc<T>::make(0.0);
                     }
-                if constexpr (FLUX == 0) {
+                if constexpr (GEO == 1) {
+                    // rotated face flux: Fbar^T dFhat/dU_c by forward mode, one dual direction per variable of c
+                    const double sx = G.metric[(long)(2 * d) * ncell + ca];
+                    const double sy = G.metric[(long)(2 * d + 1) * ncell + ca];
+                    using TT = Dual<T>;
+#pragma unroll 1
+                    for (int m = 0; m < NV; ++m) {
+                        TT Ud[NS][4], Fd[4];
+#pragma unroll
+                        for (int q = 0; q < NS; ++q)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                Ud[q][k] = TT{base[q][k], Sc<T>::make((q == kc && k == m) ? 1.0 : 0.0)};
+                        curv_face_flux<RECON, FLUX, TT>(G, Ud, sx, sy, Fd);
+                        T sum = Sc<T>::make(0.0);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) sum = sum + fbar[k] * Fd[k].d;
+                        ub[kc][m] = sum;
+                    }
+                } else if constexpr (FLUX == 0) {
                     face_flux_vjp<D, RECON, T>(G, base, d, fbar, ub);
                 } else {
                     // Roe: Fbar^T dFhat/dU_c by forward mode, one dual direction per variable of c
@@ -252,16 +347,16 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
     }
 }
 
-template <int D, int RECON, int FLUX, bool NSV>
+template <int D, int RECON, int FLUX, bool NSV, int GEO = 0>
 static hipError_t launch_vjp_f(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
                                double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
     long g = (G.ncell + 255) / 256;
     if (g > 16384) g = 16384;
     if (v)
-        hipLaunchKernelGGL((k_vjp<D, RECON, true, FLUX, NSV>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar,
+        hipLaunchKernelGGL((k_vjp<D, RECON, true, FLUX, NSV, GEO>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar,
                            ybar, ybar2, accumulate, gate, col);
     else
-        hipLaunchKernelGGL((k_vjp<D, RECON, false, FLUX, NSV>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar,
+        hipLaunchKernelGGL((k_vjp<D, RECON, false, FLUX, NSV, GEO>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar,
                            ybar, ybar2, accumulate, gate, col);
     return hipGetLastError();
 }
@@ -276,6 +371,13 @@ static hipError_t launch_vjp_n(const Geom& G, const double* y, const double* v, 
 template <int D, int RECON>
 static hipError_t launch_vjp_t(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
                                double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
+    if constexpr (D == 2) {
+        // periodic curvilinear grid, Euler physics (the only curvilinear case the adjoint accepts)
+        if (G.metric) {
+            if (G.flux == 1) return launch_vjp_f<2, RECON, 1, false, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+            return launch_vjp_f<2, RECON, 0, false, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+        }
+    }
     if (G.mu != 0.0) return launch_vjp_n<D, RECON, true>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
     return launch_vjp_n<D, RECON, false>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
 }

@@ -3,8 +3,9 @@
 Same bars as the Cartesian path: metrics, residual and FD products bit for
 bit (the same operation order on both sides), tangent products and exact
 steps to 1e-12, FD steps and a short vortex trajectory bit for bit.  The
-FP32 form and the adjoint refuse curvilinear grids; clearing the grid
-restores the Cartesian residual bit for bit.
+FP32 form refuses curvilinear grids; clearing the grid restores the
+Cartesian residual bit for bit.  The adjoint (Euler physics, periodic grid)
+against the oracle's reverse mode: 1e-12 for the products, 1e-10 for a step.
 """
 import sys
 
@@ -111,15 +112,68 @@ def test_curvilinear_refusals_and_reset(dev):
     g32.set_grid(*nodes)
     with pytest.raises(RokError):
         g32.residual(y)
+    gn = Rok(dict(pb, physics="ns", mu=0.01))
+    gn.set_grid(*nodes)
+    with pytest.raises(RokError):   # the adjoint takes Euler physics only on curvilinear grids
+        gn.vjp(y, torch.ones_like(y))
+    pbo, onodes = ri.cylinder_ogrid(16, 8, recon="muscl", flux="rusanov")
+    go = Rok(pbo)
+    go.set_ogrid(*onodes, ri.freestream(mach=0.3))
+    yo = torch.ones(4 * 16 * 8, dtype=torch.float64, device=dev)
+    with pytest.raises(RokError):   # and periodic grids only
+        go.vjp(yo, yo.clone())
     g = Rok(pb)
     g.set_grid(*nodes)
-    with pytest.raises(RokError):
-        g.vjp(y, torch.ones_like(y))
     g.set_grid(None, None)
     assert torch.equal(g.residual(y).cpu(), fv.residual(oracle_problem(pb), y.cpu()))
     g3 = Rok(ri.problem((6, 5, 4), (0.0,) * 3, (1.0, 1.0, 1.0), "euler", "first"))
     with pytest.raises(ValueError):
         g3.set_grid(*nodes)
+
+
+@pytest.mark.parametrize("shape,recon,flux", [((6, 5), "muscl", "rusanov"), ((37, 21), "first", "rusanov"),
+                                               ((37, 21), "muscl", "rusanov"), ((37, 21), "muscl", "roe")])
+def test_curvilinear_vjp_matches_oracle(dev, shape, recon, flux):
+    say("curvilinear vjp", shape, recon, flux)
+    pb = ri.problem(shape, (-1.0, 0.0), (2.0, 1.4), "euler", recon, flux=flux)
+    P, g, nodes = setup(pb)
+    g.set_grid(*nodes)
+    y = t64(ri.smooth_random_state(pb, seed=1, amplitude=0.2))
+    v, w = t64(ri.random_direction(P.size, seed=3)), t64(ri.random_direction(P.size, seed=4))
+    ref1 = fv.vjp(P, y, w)
+    ref2 = fv.vjp_second(P, y, v, w)
+    yd, vd, wd = y.to(dev), v.to(dev), w.to(dev)
+    g1, g2 = g.vjp(yd, wd, v=vd)
+    e1, e2 = relerr(g1.cpu(), ref1), relerr(g2.cpu(), ref2)
+    say("  relerr", e1, e2)
+    assert e1 <= 1e-12 and e2 <= 1e-12
+    assert torch.equal(g.vjp(yd, wd), g1)
+    jv = g.jvp(yd, vd, "exact")
+    a, b = float(torch.dot(jv, wd)), float(torch.dot(vd, g1))
+    assert abs(a - b) <= 1e-13 * float(torch.linalg.norm(jv) * torch.linalg.norm(wd))
+
+
+@pytest.mark.parametrize("recon,M", [("muscl", 8), ("first", 6)])
+def test_curvilinear_step_vjp_matches_oracle_gradient(dev, recon, M):
+    from oracle import rok_ad
+    say("curvilinear step vjp", recon, M)
+    pb = ri.vortex_problem(12, recon)
+    pb["n"] = (12, 10)
+    P, g, nodes = setup(pb)
+    g.set_grid(*nodes)
+    c = ri.node_centres(pb, *nodes)
+    y0 = t64(ri.perturb_density(pb, ri.vortex_state(pb, centres=c), 0.01, seed=12))
+    h = ri.cfl_step(pb, y0.numpy(), 2.0)
+    tab = ri.rok4_tableau()
+    cv = t64(ri.random_direction(P.size, 5))
+    ref = rok_ad.gradient(lambda z: torch.dot(cv, rok_ad.rok_step(P, tab, M, h, z)), y0)
+    yd = y0.to(dev)
+    y1 = torch.empty_like(yd)
+    gr = g.step_vjp(yd, cv.to(dev), h, tab, M, y_next_out=y1).cpu()
+    err = relerr(gr, ref)
+    say("  relerr", err)
+    assert err <= 1e-10
+    assert torch.equal(y1, g.step(yd, h, tab, M, mode="tangent"))
 
 
 # ---------------------------------------------------------------------------
