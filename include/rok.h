@@ -384,9 +384,9 @@ size_t rok_adaptive_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *   y_n, ybar_np1, ybar_n, y_np1: N doubles each, device memory; ybar_n and
  *               y_np1 may not alias any other argument
  *   work:       rok_step_vjp_workspace_bytes(ctx, M, tab->s) bytes
- * FP64 precision; Euler or Navier-Stokes physics on Cartesian grids, Euler
- * physics on periodic curvilinear grids (rok_set_grid); either flux
- * (ROK_EUNSUPPORTED otherwise: FP32, O-grids, Navier-Stokes on curvilinear grids).
+ * FP64 precision; Euler or Navier-Stokes physics, either flux, on Cartesian
+ * or periodic curvilinear grids (rok_set_grid) (ROK_EUNSUPPORTED otherwise:
+ * FP32, O-grids).
  */
 rok_status rok_step_vjp(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
                         const double* ybar_np1, double* ybar_n, double* y_np1, void* work, size_t work_bytes,
@@ -425,9 +425,9 @@ size_t rok_step_vjp_adjoint_bytes(const rok_ctx* ctx, int M, int s);
  *   ybar = J(y)^T wbar          (accumulate = 0)
  *   ybar = ybar + J(y)^T wbar   (accumulate = 1)
  * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  FP64 precision;
- * Euler or Navier-Stokes physics (constant or Sutherland viscosity) on
- * Cartesian grids, Euler physics on periodic curvilinear grids; either flux
- * (ROK_EUNSUPPORTED otherwise).
+ * Euler or Navier-Stokes physics (constant or Sutherland viscosity), either
+ * flux, on Cartesian or periodic curvilinear grids (ROK_EUNSUPPORTED
+ * otherwise: FP32, O-grids).
  * Deterministic: each cell gathers its own contributions.
  */
 rok_status rok_residual_vjp(rok_ctx* ctx, const double* y, const double* wbar, double* ybar, int accumulate,

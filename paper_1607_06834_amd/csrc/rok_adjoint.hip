@@ -3,9 +3,9 @@
 //   ybar2 (+)= d/dt [J(y + t v)^T wbar] at t = 0   (second-order adjoint)
 // for the right-hand side f of Sec. 3.2, eq. (11) (Euler or Navier-Stokes
 // physics, first-order or MUSCL-minmod reconstruction, Rusanov or Roe flux,
-// periodic Cartesian grid; Euler physics also on a periodic 2-D curvilinear
-// grid, where f_c divides by the cell area and each face flux is the
-// rotated one).
+// periodic Cartesian or 2-D curvilinear grid; on the latter f_c divides by
+// the cell area, each inviscid face flux is the rotated one and the viscous
+// one follows the chain rule through the face vector).
 //
 // f_c = sum_d (Fhat_{c-1/2} - Fhat_{c+1/2}) / dx_d, so the adjoint of the face
 // a+1/2 (between cells a and a+1) is Fbar = (wbar_{a+1} - wbar_a) / dx_d, and
@@ -81,6 +81,69 @@ __device__ __forceinline__ void visc_face(const Geom& G, const S (*U)[D + 2], in
     }
     Fv[0] = Sc<S>::make(0.0);
     Fv[D + 1] = work + kappa * ((Tq[1] - Tq[0]) * G.invdx[d]);
+}
+
+// Viscous flux through a face of a 2-D curvilinear grid (Sec. 3.2), the
+// stencil as in visc_face (U[0] = a, U[1] = b, U[2..5] = a - e_t, a + e_t,
+// b - e_t, b + e_t with t the grid direction along the face): index-space
+// differences across the face and means of the two cells' central
+// differences along it, turned into Cartesian gradients by the chain rule
+// through the face vector S = (sx, sy) and the centroid difference
+// (dcx, dcy) across the face; the stress, work and conduction terms dotted
+// with S.
+template <typename S>
+__device__ __forceinline__ void curv_visc_face(const Geom& G, const S (*U)[4], int d, double sx, double sy,
+                                               double dcx, double dcy, S* Fv) {
+    const double half = 0.5;
+    S u[6], v[6], Tq[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        S r, vel[2], p;
+        primitives<2>(G, U[q], r, vel, p);
+        u[q] = vel[0];
+        v[q] = vel[1];
+        Tq[q] = p / r;
+    }
+    auto along = [&](const S* f) { return half * ((f[3] - f[2]) * half + (f[5] - f[4]) * half); };
+    const S nu = u[1] - u[0], nv = v[1] - v[0], nT = Tq[1] - Tq[0];
+    const S tu = along(u), tv = along(v), tT = along(Tq);
+    const double J = dcx * sx + dcy * sy;
+    S ux, uy, vx, vy, Tx, Ty;
+    if (d == 0) {
+        ux = (nu * sx - tu * dcy) / J;
+        uy = (nu * sy + tu * dcx) / J;
+        vx = (nv * sx - tv * dcy) / J;
+        vy = (nv * sy + tv * dcx) / J;
+        Tx = (nT * sx - tT * dcy) / J;
+        Ty = (nT * sy + tT * dcx) / J;
+    } else {
+        ux = (nu * sx + tu * dcy) / J;
+        uy = (nu * sy - tu * dcx) / J;
+        vx = (nv * sx + tv * dcy) / J;
+        vy = (nv * sy - tv * dcx) / J;
+        Tx = (nT * sx + tT * dcy) / J;
+        Ty = (nT * sy - tT * dcx) / J;
+    }
+    S mu, c23, kap;
+    if (G.suth) {
+        const S th = (half * (Tq[0] + Tq[1])) / G.t_ref;
+        mu = G.mu * th * Sc<S>::sqrt_(th) * G.suth_one_s / (th + G.suth_s);
+        c23 = (2.0 / 3.0) * mu;
+        kap = mu * G.g / G.kden;
+    } else {
+        mu = Sc<S>::make(G.mu);
+        c23 = Sc<S>::make(G.c23mu);
+        kap = Sc<S>::make(G.kappa);
+    }
+    const S ufx = half * (u[0] + u[1]), ufy = half * (v[0] + v[1]);
+    const S div = ux + vy;
+    const S txx = mu * (ux + ux) - c23 * div;
+    const S tyy = mu * (vy + vy) - c23 * div;
+    const S txy = mu * (uy + vx);
+    Fv[0] = Sc<S>::make(0.0);
+    Fv[1] = txx * sx + txy * sy;
+    Fv[2] = txy * sx + tyy * sy;
+    Fv[3] = (ufx * txx + ufy * txy + kap * Tx) * sx + (ufx * txy + ufy * tyy + kap * Ty) * sy;
 }
 
 // Inviscid flux through a face of a 2-D curvilinear grid with face vector
@@ -304,9 +367,16 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
                         }
                     }
                     T fbar[NV];
+                    if constexpr (GEO == 0) {
 #pragma unroll
-                    for (int m = 0; m < NV; ++m)
-                        fbar[m] = Sc<T>::make((wbar[m * ncell + cell[1]] - wbar[m * ncell + cell[0]]) * inv);
+                        for (int m = 0; m < NV; ++m)
+                            fbar[m] = Sc<T>::make((wbar[m * ncell + cell[1]] - wbar[m * ncell + cell[0]]) * inv);
+                    } else {
+                        const double ia = G.metric[4 * ncell + cell[0]], ib = G.metric[4 * ncell + cell[1]];
+#pragma unroll
+                        for (int m = 0; m < NV; ++m)
+                            fbar[m] = Sc<T>::make(wbar[m * ncell + cell[1]] * ib - wbar[m * ncell + cell[0]] * ia);
+                    }
                     T base[NQ][NV];
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
@@ -325,7 +395,15 @@ __global__ __launch_bounds__(256) void k_vjp(Geom G, const double* y, const doub
 #pragma unroll
                             for (int k = 0; k < NV; ++k)
                                 Ud[q][k] = TT{base[q][k], Sc<T>::make((q == kv && k == m) ? 1.0 : 0.0)};
-                        visc_face<D, TT>(G, Ud, d, Fd);
+                        if constexpr (GEO == 0) {
+                            visc_face<D, TT>(G, Ud, d, Fd);
+                        } else {
+                            const long a0 = cell[0];
+                            curv_visc_face<TT>(G, Ud, d, G.metric[(long)(2 * d) * ncell + a0],
+                                               G.metric[(long)(2 * d + 1) * ncell + a0],
+                                               G.metric[(long)(5 + 2 * d) * ncell + a0],
+                                               G.metric[(long)(6 + 2 * d) * ncell + a0], Fd);
+                        }
                         T sum = Sc<T>::make(0.0);
 #pragma unroll
                         for (int k = 1; k < NV; ++k) sum = sum + fbar[k] * Fd[k].d;
@@ -372,8 +450,13 @@ template <int D, int RECON>
 static hipError_t launch_vjp_t(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
                                double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
     if constexpr (D == 2) {
-        // periodic curvilinear grid, Euler physics (the only curvilinear case the adjoint accepts)
+        // periodic curvilinear grid (O-grids are refused before this point)
         if (G.metric) {
+            if (G.mu != 0.0) {
+                if (G.flux == 1)
+                    return launch_vjp_f<2, RECON, 1, true, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+                return launch_vjp_f<2, RECON, 0, true, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
+            }
             if (G.flux == 1) return launch_vjp_f<2, RECON, 1, false, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
             return launch_vjp_f<2, RECON, 0, false, 1>(G, y, v, wbar, ybar, ybar2, accumulate, gate, col, st);
         }

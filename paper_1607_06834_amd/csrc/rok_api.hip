@@ -37,12 +37,10 @@ rok_status hip_status(hipError_t e) {
 
 bool fp32(const rok_ctx* c) { return c->pb.precision == ROK_FP32_RESIDUAL; }
 
-// The adjoint kernels cover Euler and Navier-Stokes physics on Cartesian grids
-// and Euler physics on periodic curvilinear grids, in FP64.
+// The adjoint kernels cover Euler and Navier-Stokes physics on Cartesian and
+// periodic curvilinear grids, in FP64 (not O-grids).
 bool adjoint_supported(const rok_ctx* c) {
-    if (fp32(c)) return false;
-    if (!c->G.metric) return true;
-    return c->pb.physics == ROK_EULER && !c->G.ogrid;
+    return !fp32(c) && !(c->G.metric && c->G.ogrid);
 }
 
 rok::ResArgs plain_args(const double* y, void* out) {

@@ -4,8 +4,9 @@ Same bars as the Cartesian path: metrics, residual and FD products bit for
 bit (the same operation order on both sides), tangent products and exact
 steps to 1e-12, FD steps and a short vortex trajectory bit for bit.  The
 FP32 form refuses curvilinear grids; clearing the grid restores the
-Cartesian residual bit for bit.  The adjoint (Euler physics, periodic grid)
-against the oracle's reverse mode: 1e-12 for the products, 1e-10 for a step.
+Cartesian residual bit for bit.  The adjoint (periodic grids, Euler and
+Navier-Stokes physics) against the oracle's reverse mode: 1e-12 for the
+products, 1e-10 for a step; O-grids are refused.
 """
 import sys
 
@@ -112,15 +113,11 @@ def test_curvilinear_refusals_and_reset(dev):
     g32.set_grid(*nodes)
     with pytest.raises(RokError):
         g32.residual(y)
-    gn = Rok(dict(pb, physics="ns", mu=0.01))
-    gn.set_grid(*nodes)
-    with pytest.raises(RokError):   # the adjoint takes Euler physics only on curvilinear grids
-        gn.vjp(y, torch.ones_like(y))
     pbo, onodes = ri.cylinder_ogrid(16, 8, recon="muscl", flux="rusanov")
     go = Rok(pbo)
     go.set_ogrid(*onodes, ri.freestream(mach=0.3))
     yo = torch.ones(4 * 16 * 8, dtype=torch.float64, device=dev)
-    with pytest.raises(RokError):   # and periodic grids only
+    with pytest.raises(RokError):   # the adjoint takes periodic grids only
         go.vjp(yo, yo.clone())
     g = Rok(pb)
     g.set_grid(*nodes)
@@ -131,11 +128,17 @@ def test_curvilinear_refusals_and_reset(dev):
         g3.set_grid(*nodes)
 
 
-@pytest.mark.parametrize("shape,recon,flux", [((6, 5), "muscl", "rusanov"), ((37, 21), "first", "rusanov"),
-                                               ((37, 21), "muscl", "rusanov"), ((37, 21), "muscl", "roe")])
-def test_curvilinear_vjp_matches_oracle(dev, shape, recon, flux):
-    say("curvilinear vjp", shape, recon, flux)
-    pb = ri.problem(shape, (-1.0, 0.0), (2.0, 1.4), "euler", recon, flux=flux)
+VJP_CASES = [((6, 5), "muscl", "rusanov", "euler", 0.0), ((37, 21), "first", "rusanov", "euler", 0.0),
+             ((37, 21), "muscl", "rusanov", "euler", 0.0), ((37, 21), "muscl", "roe", "euler", 0.0),
+             ((6, 5), "muscl", "rusanov", "ns", 0.0), ((37, 21), "first", "rusanov", "ns", 0.0),
+             ((37, 21), "muscl", "roe", "ns", 0.38)]
+
+
+@pytest.mark.parametrize("shape,recon,flux,physics,suth", VJP_CASES)
+def test_curvilinear_vjp_matches_oracle(dev, shape, recon, flux, physics, suth):
+    say("curvilinear vjp", shape, recon, flux, physics, suth)
+    pb = ri.problem(shape, (-1.0, 0.0), (2.0, 1.4), physics, recon, flux=flux, mu=0.05 if physics == "ns" else 0.0,
+                    sutherland=suth, t_ref=0.9)
     P, g, nodes = setup(pb)
     g.set_grid(*nodes)
     y = t64(ri.smooth_random_state(pb, seed=1, amplitude=0.2))
@@ -153,12 +156,14 @@ def test_curvilinear_vjp_matches_oracle(dev, shape, recon, flux):
     assert abs(a - b) <= 1e-13 * float(torch.linalg.norm(jv) * torch.linalg.norm(wd))
 
 
-@pytest.mark.parametrize("recon,M", [("muscl", 8), ("first", 6)])
-def test_curvilinear_step_vjp_matches_oracle_gradient(dev, recon, M):
+@pytest.mark.parametrize("recon,M,physics", [("muscl", 8, "euler"), ("first", 6, "euler"), ("muscl", 6, "ns")])
+def test_curvilinear_step_vjp_matches_oracle_gradient(dev, recon, M, physics):
     from oracle import rok_ad
-    say("curvilinear step vjp", recon, M)
+    say("curvilinear step vjp", recon, M, physics)
     pb = ri.vortex_problem(12, recon)
     pb["n"] = (12, 10)
+    if physics == "ns":
+        pb = dict(pb, physics="ns", mu=0.02)
     P, g, nodes = setup(pb)
     g.set_grid(*nodes)
     c = ri.node_centres(pb, *nodes)
