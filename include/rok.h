@@ -384,9 +384,8 @@ size_t rok_adaptive_workspace_bytes(const rok_ctx* ctx, int M, int s);
  *   y_n, ybar_np1, ybar_n, y_np1: N doubles each, device memory; ybar_n and
  *               y_np1 may not alias any other argument
  *   work:       rok_step_vjp_workspace_bytes(ctx, M, tab->s) bytes
- * FP64 precision; Euler or Navier-Stokes physics, either flux, on Cartesian
- * or periodic curvilinear grids (rok_set_grid) (ROK_EUNSUPPORTED otherwise:
- * FP32, O-grids).
+ * FP64 precision only (ROK_EUNSUPPORTED in FP32); every physics, flux and
+ * grid (Cartesian, rok_set_grid, rok_set_ogrid).
  */
 rok_status rok_step_vjp(rok_ctx* ctx, const rok_tableau* tab, int M, double h, const double* y_n,
                         const double* ybar_np1, double* ybar_n, double* y_np1, void* work, size_t work_bytes,
@@ -424,10 +423,10 @@ size_t rok_step_vjp_adjoint_bytes(const rok_ctx* ctx, int M, int s);
  * Adjoint product of the residual (transposed Jacobian, Sec. 2.3 / eq. 11):
  *   ybar = J(y)^T wbar          (accumulate = 0)
  *   ybar = ybar + J(y)^T wbar   (accumulate = 1)
- * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  FP64 precision;
- * Euler or Navier-Stokes physics (constant or Sutherland viscosity), either
- * flux, on Cartesian or periodic curvilinear grids (ROK_EUNSUPPORTED
- * otherwise: FP32, O-grids).
+ * y, wbar, ybar: N doubles (ybar may not alias y or wbar).  FP64 precision
+ * only (ROK_EUNSUPPORTED in FP32); every physics (Euler, Navier-Stokes with
+ * constant or Sutherland viscosity), flux and grid (Cartesian, periodic
+ * curvilinear, O-grid with its wall and far-field faces).
  * Deterministic: each cell gathers its own contributions.
  */
 rok_status rok_residual_vjp(rok_ctx* ctx, const double* y, const double* wbar, double* ybar, int accumulate,

@@ -37,10 +37,9 @@ rok_status hip_status(hipError_t e) {
 
 bool fp32(const rok_ctx* c) { return c->pb.precision == ROK_FP32_RESIDUAL; }
 
-// The adjoint kernels cover Euler and Navier-Stokes physics on Cartesian and
-// periodic curvilinear grids, in FP64 (not O-grids).
+// The adjoint kernels cover Euler and Navier-Stokes physics on every grid, in FP64.
 bool adjoint_supported(const rok_ctx* c) {
-    return !fp32(c) && !(c->G.metric && c->G.ogrid);
+    return !fp32(c);
 }
 
 rok::ResArgs plain_args(const double* y, void* out) {
