@@ -61,6 +61,8 @@ def parse():
                     help="also run the adaptive work-precision sweep (step doubling; ERK4 vs ROK4 M = 4, 8)")
     ap.add_argument("--adaptive-cases", default="all",
                     help="comma-separated name prefixes of the adaptive sweep's cases (default: all)")
+    ap.add_argument("--adjoint-ogrid", action="store_true",
+                    help="also time the gradient through 20 steps on the viscous cylinder O-grid")
     ap.add_argument("--eigs", action="store_true",
                     help="also run the stiffness diagnostic (largest eigenvalues of J on the cylinder O-grids)")
     ap.add_argument("--chain", action="store_true",
@@ -521,6 +523,76 @@ def adaptive_leg(args):
     return out
 
 
+def adjoint_ogrid_leg(args):
+    """Gradient through a trajectory on the viscous cylinder O-grid of the adaptive
+    sweep (128 x 64, isothermal wall, Sutherland viscosity, Roe flux): K = 20
+    exact-product ROK4 steps (M = 8, h = 2e-6: the impulsive start of the
+    no-slip wall allows no larger fixed step) from the free stream, then the
+    discrete adjoint (rok_step_vjp from each stored y_n) of L = the x-momentum of
+    the wall row.  Reports forward and adjoint milliseconds per step (HIP events
+    over the whole sweep) and the directional derivative of L along a random
+    direction against central differences of the GPU forward trajectory (best of
+    a sweep of steps)."""
+    import numpy as np
+    import torch
+
+    import rok_inputs as ri
+    from paper_1607_06834_amd import Rok
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    fs = ri.freestream(mach=0.3)
+    tw = (1.4 - 1.0) * (fs[3] - 0.5 * fs[1] ** 2 / fs[0]) / fs[0]
+    nx, ny = 128, 64
+    pb, nodes = ri.cylinder_ogrid(nx, ny, radius=0.5, far=20.0, recon="first", flux="roe", cluster=10.0)
+    pb = dict(pb, physics="ns", mu=0.01, sutherland=0.4, t_ref=1.0)
+    g = Rok(pb, "fp64")
+    g.set_ogrid(*nodes, fs, t_wall=tw)
+    y0 = torch.tensor(np.tile(np.asarray(fs, dtype=np.float64)[:, None], (1, nx * ny)).reshape(-1), device=dev)
+    tab = ri.rok4_tableau()
+    K, M, h = 20, 8, 2e-6
+    c = torch.zeros_like(y0)
+    c[nx * ny:nx * ny + nx] = 1.0            # x-momentum of the wall row j = 0
+
+    def forward(y):
+        ys = [y]
+        for _ in range(K):
+            ys.append(g.step(ys[-1], h, tab, M, mode="tangent"))
+        return ys
+
+    def backward(ys):
+        yb = c.clone()
+        for k in range(K - 1, -1, -1):
+            yb = g.step_vjp(ys[k], yb, h, tab, M)
+        return yb
+
+    backward(forward(y0))                    # warm-up
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(stream)
+    ys = forward(y0)
+    e[1].record(stream)
+    grad = backward(ys)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    fwd, bwd = e[0].elapsed_time(e[1]) / K, e[1].elapsed_time(e[2]) / K
+    d = torch.tensor(ri.random_direction(g.N, seed=21), device=dev) * y0.abs()
+    exact = float(torch.dot(grad, d))
+    errs = {}
+    for eps in (1e-4, 1e-5, 1e-6):
+        lp = float(torch.dot(c, forward(y0 + eps * d)[-1]))
+        lm = float(torch.dot(c, forward(y0 - eps * d)[-1]))
+        fd = (lp - lm) / (2 * eps)
+        errs[eps] = abs(fd - exact) / abs(exact)
+    best = min(errs, key=errs.get)
+    out = {"grid": f"{nx}x{ny}", "steps": K, "M": M, "h": h, "forward_exact_ms_per_step": round(fwd, 3),
+           "step_vjp_ms_per_step": round(bwd, 3), "ratio": round(bwd / fwd, 3),
+           "directional_derivative": exact, "central_difference_relerr": float(f"{errs[best]:.3g}"),
+           "best_eps": best, "finite": bool(torch.isfinite(grad).all())}
+    print(f"[adjoint-ogrid] {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def eigs_leg(args):
     """Stiffness diagnostic (rok_eigs): the 12 largest-magnitude eigenvalues of J at
     the free stream on the cylinder O-grids of the adaptive sweep (inviscid with
@@ -598,6 +670,7 @@ def main():
     ksw = krylov_sweep_leg(args) if (args.krylov_sweep and not args.roofline_only) else None
     ada = adaptive_leg(args) if (args.adaptive and not args.roofline_only) else None
     eig = eigs_leg(args) if (args.eigs and not args.roofline_only) else None
+    adj_og = adjoint_ogrid_leg(args) if (args.adjoint_ogrid and not args.roofline_only) else None
     cpu = None if args.no_cpu_baseline else cpu_leg(args, pb, y0, w, tab, h)
     n = "x".join(str(x) for x in pb["n"])
     line = {
@@ -629,6 +702,7 @@ def main():
         "krylov_sweep": ksw,
         "adaptive": ada,
         "eigs": eig,
+        "adjoint_ogrid": adj_og,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

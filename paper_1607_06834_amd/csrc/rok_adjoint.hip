@@ -498,11 +498,13 @@ __device__ __forceinline__ void ogrid_face(const Geom& G, int kind, int j, long 
         return;
     }
     const int d = kind;
+    constexpr int A0 = (RECON == 0) ? 1 : 0, A1 = (RECON == 0) ? 2 : 3;   // patch slots the flux reads
+    constexpr int B0 = NSV ? 0 : 1, B1 = NSV ? 2 : 1;
     S q[4][3][4];   // primitives (r, u, v, p) of the patch
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = A0; a <= A1; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
+        for (int b = B0; b <= B1; ++b) {
             S vel[2];
             primitives<2>(G, P[a][b], q[a][b][0], vel, q[a][b][3]);
             q[a][b][1] = vel[0];
@@ -571,11 +573,11 @@ __device__ __forceinline__ void ogrid_face(const Geom& G, int kind, int j, long 
 
 // Adjoint on an O-grid: cell c gathers Fbar^T d(Fhat - Fv)/dU_c from every
 // (face, patch position) pair that places c in the face's patch, each by
-// forward mode (one dual direction per variable of c); Fbar of a face is
-// wbar_b / A_b - wbar_a / A_a (the wall face has only b = (i, 0), the
-// far-field face only a = (i, ny - 1)).
+// forward mode; Fbar of a face is wbar_b / A_b - wbar_a / A_a (the wall face
+// has only b = (i, 0), the far-field face only a = (i, ny - 1)).  One thread
+// per (variable m, cell c), c fastest: it seeds the one dual direction U_c[m].
 template <int RECON, bool SECOND, int FLUX, bool NSV>
-__global__ __launch_bounds__(256) void k_vjp_ogrid(Geom G, const double* y, const double* v, const double* wbar,
+__global__ __launch_bounds__(64) void k_vjp_ogrid(Geom G, const double* y, const double* v, const double* wbar,
                                                   double* ybar, double* ybar2, int accumulate, const int* gate,
                                                   int col) {
     if (gate && col >= gate[0]) return;
@@ -587,11 +589,11 @@ __global__ __launch_bounds__(256) void k_vjp_ogrid(Geom G, const double* y, cons
     constexpr int A0 = (RECON == 0) ? 1 : 0, A1 = (RECON == 0) ? 2 : 3;   // patch rows a the flux reads
     constexpr int B0 = NSV ? 0 : 1, B1 = NSV ? 2 : 1;                     // patch columns b
     const long stride = (long)gridDim.x * blockDim.x;
-    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += stride) {
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < 4 * ncell; idx += stride) {
+        const int m = (int)(idx / ncell);
+        const long c = idx - (long)m * ncell;
         const int cx = (int)(c % n0), cy = (int)(c / n0);
-        T acc[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = Sc<T>::make(0.0);
+        T acc = Sc<T>::make(0.0);
         auto load = [&](long cell, T* u) {
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -635,22 +637,19 @@ __global__ __launch_bounds__(256) void k_vjp_ogrid(Geom G, const double* y, cons
                 for (int m = 0; m < 4; ++m)
                     fbar[m] = Sc<T>::make(wbar[m * ncell + fb] * ia[fb] - wbar[m * ncell + fc] * ia[fc]);
             }
-#pragma unroll 1
-            for (int m = 0; m < 4; ++m) {
-                TT Ud[4][3][4], Fd[4];
+            TT Ud[4][3][4], Fd[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 3; ++b)
+                for (int b = 0; b < 3; ++b)
 #pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            Ud[a][b][k] = TT{base[a][b][k], Sc<T>::make((a == pa && b == pb && k == m) ? 1.0 : 0.0)};
-                ogrid_face<RECON, FLUX, NSV, TT>(G, kind, fj, fc, Ud, Fd);
-                T sum = Sc<T>::make(0.0);
+                    for (int k = 0; k < 4; ++k)
+                        Ud[a][b][k] = TT{base[a][b][k], Sc<T>::make((a == pa && b == pb && k == m) ? 1.0 : 0.0)};
+            ogrid_face<RECON, FLUX, NSV, TT>(G, kind, fj, fc, Ud, Fd);
+            T sum = Sc<T>::make(0.0);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) sum = sum + fbar[k] * Fd[k].d;
-                acc[m] = acc[m] + sum;
-            }
+            for (int k = 0; k < 4; ++k) sum = sum + fbar[k] * Fd[k].d;
+            acc = acc + sum;
         };
 #pragma nounroll
         for (int a = A0; a <= A1; ++a)
@@ -665,15 +664,11 @@ __global__ __launch_bounds__(256) void k_vjp_ogrid(Geom G, const double* y, cons
             }
         if (cy == 0) face(2, cx, 0, 1, 1);
         if (cy == ny - 1) face(3, cx, ny - 1, 1, 1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const long o = k * ncell + c;
-            if constexpr (SECOND) {
-                ybar[o] = accumulate ? ybar[o] + acc[k].v : acc[k].v;
-                ybar2[o] = accumulate ? ybar2[o] + acc[k].d : acc[k].d;
-            } else {
-                ybar[o] = accumulate ? ybar[o] + acc[k] : acc[k];
-            }
+        if constexpr (SECOND) {
+            ybar[idx] = accumulate ? ybar[idx] + acc.v : acc.v;
+            ybar2[idx] = accumulate ? ybar2[idx] + acc.d : acc.d;
+        } else {
+            ybar[idx] = accumulate ? ybar[idx] + acc : acc;
         }
     }
 }
@@ -681,13 +676,13 @@ __global__ __launch_bounds__(256) void k_vjp_ogrid(Geom G, const double* y, cons
 template <int RECON, int FLUX, bool NSV>
 static hipError_t launch_vjp_og(const Geom& G, const double* y, const double* v, const double* wbar, double* ybar,
                                 double* ybar2, int accumulate, const int* gate, int col, hipStream_t st) {
-    long g = (G.ncell + 255) / 256;
-    if (g > 16384) g = 16384;
+    long g = (4 * G.ncell + 63) / 64;   // small blocks: O-grids have few cells and much work per cell
+    if (g > 65536) g = 65536;
     if (v)
-        hipLaunchKernelGGL((k_vjp_ogrid<RECON, true, FLUX, NSV>), dim3((unsigned)g), dim3(256), 0, st, G, y, v, wbar,
+        hipLaunchKernelGGL((k_vjp_ogrid<RECON, true, FLUX, NSV>), dim3((unsigned)g), dim3(64), 0, st, G, y, v, wbar,
                            ybar, ybar2, accumulate, gate, col);
     else
-        hipLaunchKernelGGL((k_vjp_ogrid<RECON, false, FLUX, NSV>), dim3((unsigned)g), dim3(256), 0, st, G, y, v,
+        hipLaunchKernelGGL((k_vjp_ogrid<RECON, false, FLUX, NSV>), dim3((unsigned)g), dim3(64), 0, st, G, y, v,
                            wbar, ybar, ybar2, accumulate, gate, col);
     return hipGetLastError();
 }
