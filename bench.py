@@ -1,23 +1,24 @@
 """Benchmark: ROK steps per second on one MI355X.
 
-Workload (default): 2-D compressible Euler isentropic vortex on a periodic
-1024 x 1024 grid, second-order MUSCL (minmod) + Rusanov flux, FP64, four-stage
-ROK4 with Krylov dimension M = 16 and finite-difference Jacobian-vector
-products, fixed step at CFL 10.  Inputs are synthetic (seeded) and resident
-in HBM before the timed region starts.
+Workload (default): the 3-D compressible Navier-Stokes Taylor-Green vortex on
+a periodic 256^3 grid (Re 1600, Mach 0.1, N = 83.9 M unknowns), MUSCL (minmod)
++ Rusanov inviscid flux and central viscous fluxes, four-stage ROK4 with
+Krylov dimension M = 16, the plain FP64 method with finite-difference
+Jacobian-vector products, fixed step at CFL 10.  Inputs are synthetic (seeded)
+and resident in HBM before the timed region starts.
 
 Prints one JSON line with the step rate, a roofline entry for the dominant
-kernel of the step (the modified Gram-Schmidt Arnoldi column) and one for the
-FD Jacobian-vector product kernel (both timed live with HIP events on the
-launch stream), and the CPU oracle's rate on a bounded sample of the same
-workload.
-
-It also runs the precision form's equal-error comparison (FP32 residual and
-tangent products vs plain FP64 with finite-difference products, a
-work-precision sweep on a 512^2 Taylor-Green proxy).
+kernel of the step (a modified Gram-Schmidt pass; timed live with HIP events
+on the launch stream) and for the FD product and residual kernels, the
+Arnoldi share of the step against its algorithmic bytes, the precision form's
+rate on the same workload (FP32 residual and tangent products, FP64 Krylov)
+with its error, the 1024^2 MUSCL vortex as a secondary workload, the
+equal-error comparison of FP32 + tangent against FP64 + FD (work-precision
+sweeps on a 512^2 2-D and a 96^3 3-D Taylor-Green proxy), and the CPU
+oracle's rate on a bounded sample of the workload.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-equal-error]
-                    [--adjoint] [--krylov-sweep]
+                    [--no-secondary] [--adjoint] [--krylov-sweep]
 """
 from __future__ import annotations
 
@@ -42,14 +43,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="vortex1024_muscl")
+    ap.add_argument("--workload", default="tgv256_3d_fp64")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the precision form's rate and the 1024^2 vortex next to the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU oracle sample")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the roofline kernel loop and a calibration copy (for counter runs)")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_vortex1024_muscl.json"),
-                    help="JSON file with HBM bytes per launch of the roofline kernels (from counter runs)")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with counter figures per launch of the roofline kernels (default: "
+                         "profiles/traffic_<workload>.json)")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the discrete adjoint of the step (rok_step_vjp; on by default for the "
                          "differentiation workload)")
@@ -73,6 +77,7 @@ def parse():
 
 RESIDUAL_SOURCES = ("rok_residual.hip", "rok_flux.hpp", "rok_device.hpp")
 MGS_SOURCES = ("rok_mgs.hip", "rok_kernels.hpp", "rok_device.hpp")
+KRED_SOURCES = ("rok_krylov.hip", "rok_kernels.hpp", "rok_device.hpp")
 
 
 def _source_hash(names):
@@ -91,7 +96,13 @@ def _source_hash(names):
     return hashlib.sha256(data.encode()).hexdigest()[:16]
 
 
-def gpu_leg(args, pb, y0, w, tab, h):
+def _traffic_path(args):
+    if args.traffic:
+        return args.traffic
+    return os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+
+
+def gpu_leg(args, pb, y0, w, tab, h, workload=None, rooflines=True):
     import torch
 
     from paper_1607_06834_amd import Rok
@@ -124,19 +135,20 @@ def gpu_leg(args, pb, y0, w, tab, h):
     ev_ms = e0.elapsed_time(e1)
     flags, meff = g.last_status() if steps else (0, 0)
     finite = bool(torch.isfinite(yb if not args.chain else ya).all()) if steps else True
-
+    out = {"ms_per_step": ev_ms / max(steps, 1), "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite}
+    if not rooflines:
+        return out
     # calibration kernel for the HBM counters: a plain copy of one state vector (8 N bytes read, 8 N written)
     calib = torch.empty_like(ya)
     calib.copy_(ya)
     torch.cuda.synchronize()
-    mgs = _mgs_roofline(args, g, ya, M, mode, stream)
-    jvp = _jvp_roofline(args, g, ya, w, stream)
-    resid = _residual_roofline(args, g, ya, w, stream)
-    adj = None
+    del calib, yb
+    mgs, arn = _mgs_roofline(args, g, ya, M, mode, stream, out["ms_per_step"])
+    out.update(roofline=mgs, arnoldi_step=arn, roofline_jvp=_jvp_roofline(args, g, ya, w, stream),
+               roofline_residual=_residual_roofline(args, g, ya, w, stream), adjoint=None)
     if (args.adjoint or args.workload == "vortex512_adjoint") and not args.roofline_only:
-        adj = _adjoint_leg(args, g, ya, h, tab, M, stream)
-    return {"ms_per_step": ev_ms / max(steps, 1), "wall_s": wall, "flags": flags, "M_eff": meff, "finite": finite,
-            "roofline": mgs, "roofline_jvp": jvp, "roofline_residual": resid, "adjoint": adj}
+        out["adjoint"] = _adjoint_leg(args, g, ya, h, tab, M, stream)
+    return out
 
 
 def _adjoint_leg(args, g, y, h, tab, M, stream):
@@ -201,40 +213,89 @@ def _traffic(path, sources, key, field="hbm_bytes_per_launch"):
     return ent.get(field)
 
 
-def _mgs_roofline(args, g, y, M, mode, stream):
-    """Dominant kernel of the step: one modified Gram-Schmidt column (Arnoldi, a4).
+def _mgs_roofline(args, g, y, M, mode, stream, ms_step):
+    """Dominant kernel of the step: the modified Gram-Schmidt pass (Arnoldi, a4).
 
     The basis of the step's Arnoldi process at y and the products w_j = J v_j
     are prepared first; the timed loop then runs the M columns j = 0..M-1 as
-    the step does (one kernel launch per column).  Algorithmic bytes of column
-    j: w and v_0..v_j read, v_{j+1} written (when j + 1 < M)."""
+    the step does, one HIP event pair per column.
+    * Resident path (N <= 4.19 M: one cooperative kernel per column, w held
+      on chip): a launch is a column; algorithmic bytes of column j: w and
+      v_0..v_j read, v_{j+1} written.
+    * Per-pass path (larger N: w streamed): column j runs j update passes
+      (w <- w - h v_{i-1}, <v_i, w>), a first dot, a norm pass and the
+      normalisation; the time of one update pass is the slope of the column
+      time in j (least squares over j = 1..M-1), the per-launch average that
+      rocprofv3 reports for k_red<true, false>.  Algorithmic bytes of a pass:
+      24 per element (w read and written, v_i read), the figure for a
+      modified Gram-Schmidt pass whose work vector is not on chip; the kernel
+      also reads v_{i-1} (32 bytes, `kernel_bytes_per_launch`).
+    arnoldi_step: all M columns of a step against the step's Arnoldi
+    algorithmic bytes, M(M+1)/2 + M vectors (each basis vector read once per
+    pass it enters, each written once) -- the resident algorithm's traffic."""
     import torch
     N = g.N
     F = g.residual(y).to(torch.float64)
     V, H, m = g.arnoldi(y, F, M, mode)
     V = V.contiguous()
-    Ws = torch.stack([g.jvp(y, V[j], mode="fd" if mode == "fd" else "tangent", fy=F, eps=1e-7).to(torch.float64)
-                      for j in range(m)])
+    del H
+    Ws = torch.empty(m, N, dtype=torch.float64, device=y.device)
+    for j in range(m):
+        Ws[j].copy_(g.jvp(y, V[j], mode="fd" if mode == "fd" else "tangent", fy=F, eps=1e-7).to(torch.float64))
     Hs = torch.zeros(m + 1, m, dtype=torch.float64, device=y.device)
     ws = g.mgs_workspace(m)
+    wk = torch.empty(N, dtype=torch.float64, device=y.device)
+    vn = torch.empty(N, dtype=torch.float64, device=y.device)
+    resident = g.mgs_resident()
 
-    def column(j):
-        return lambda: g.mgs_column(V, j, Ws[j], Hs, ws, vnext=V[j + 1] if j + 1 < m else None)
+    def column_timed(j, reps):
+        # the copy that restores w (a column may overwrite it) is outside the events
+        ev = []
+        for _ in range(reps):
+            wk.copy_(Ws[j])
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            g.mgs_column(V, j, wk, Hs, ws, vnext=vn if j + 1 < m else None)
+            b.record(stream)
+            ev.append((a, b))
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in ev) / reps
 
     for j in range(m):
-        column(j)()
-    torch.cuda.synchronize()
+        column_timed(j, 1)
     reps = max(1, args.kernel_reps // 4)
-    ms = _timed(stream, [column(j) for _ in range(reps) for j in range(m)])
-    alg = sum((j + 2) * 8 * N + (8 * N if j + 1 < m else 0) for j in range(m)) / m
-    achieved = alg / (ms * 1e-3) / 1e9
+    col_ms = [column_timed(j, reps) for j in range(m)]
+    a4_bytes = (m * (m + 1) // 2 + m) * 8 * N
+    arn_ms = sum(col_ms)
+    arn = {"ms_per_step": round(arn_ms, 4), "share_of_step": round(arn_ms / ms_step, 4) if ms_step else None,
+           "alg_bytes_per_step": a4_bytes, "achieved": round(a4_bytes / (arn_ms * 1e-3) / 1e9, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(a4_bytes / (arn_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "what": f"the {m} Arnoldi columns of a step (HIP events per column) against M(M+1)/2 + M basis-vector "
+                   f"reads and writes"}
+    tpath = _traffic_path(args)
     traffic = None
-    if args.workload == "vortex1024_muscl":
-        traffic = _traffic(args.traffic, MGS_SOURCES, "mgs_column")
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"modified Gram-Schmidt Arnoldi column (k_mgs_resident), average over the {m} columns of a step",
-            "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": int(alg)}
+    if resident:
+        ms = sum(col_ms) / m
+        alg = sum((j + 2) * 8 * N + (8 * N if j + 1 < m else 0) for j in range(m)) / m
+        traffic = _traffic(tpath, MGS_SOURCES, "mgs_column")
+        kernel = f"modified Gram-Schmidt Arnoldi column (k_mgs_resident), average over the {m} columns of a step"
+        extra = {}
+    else:
+        js = list(range(1, m))
+        mj = sum(js) / len(js)
+        mt = sum(col_ms[j] for j in js) / len(js)
+        ms = sum((j - mj) * (col_ms[j] - mt) for j in js) / sum((j - mj) ** 2 for j in js)
+        alg = 24 * N
+        traffic = _traffic(tpath, KRED_SOURCES, "mgs_pass")
+        kernel = "modified Gram-Schmidt pass with the work vector streamed (k_red<true, false>)"
+        extra = {"kernel_bytes_per_launch": 32 * N, "timing": "slope of the column time in j (HIP events per column)"}
+    achieved = alg / (ms * 1e-3) / 1e9
+    rl = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+          "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": int(alg)}
+    rl.update(extra)
+    return rl, arn
 
 
 def _residual_roofline(args, g, y, w, stream):
@@ -249,10 +310,8 @@ def _residual_roofline(args, g, y, w, stream):
     ms = _timed(stream, [lambda: g.residual(y, out=out)] * args.kernel_reps)
     alg = (8 + out.element_size()) * N
     achieved = alg / (ms * 1e-3) / 1e9
-    traffic = valu = None
-    if args.workload == "vortex1024_muscl":
-        traffic = _traffic(args.traffic, RESIDUAL_SOURCES, "residual")
-        valu = _traffic(args.traffic, RESIDUAL_SOURCES, "residual", "valu_insts_per_launch")
+    traffic = _traffic(_traffic_path(args), RESIDUAL_SOURCES, "residual")
+    valu = _traffic(_traffic_path(args), RESIDUAL_SOURCES, "residual", "valu_insts_per_launch")
     hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
     common = {"kernel": "finite-volume residual F = f(y)", "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": alg}
@@ -281,11 +340,8 @@ def _jvp_roofline(args, g, y, w, stream):
     ms = _timed(stream, [lambda: g.jvp(y, v, "fd", fy=F, eps=1e-7, out=out)] * args.kernel_reps)
     alg = 4 * 8 * N
     achieved = alg / (ms * 1e-3) / 1e9
-    traffic = None
-    valu = None
-    if args.workload == "vortex1024_muscl":
-        traffic = _traffic(args.traffic, RESIDUAL_SOURCES, "fd_jvp")
-        valu = _traffic(args.traffic, RESIDUAL_SOURCES, "fd_jvp", "valu_insts_per_launch")
+    traffic = _traffic(_traffic_path(args), RESIDUAL_SOURCES, "fd_jvp")
+    valu = _traffic(_traffic_path(args), RESIDUAL_SOURCES, "fd_jvp", "valu_insts_per_launch")
     hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
     common = {"kernel": "FD Jacobian-vector product (residual at y + eps v, minus f(y), over eps)",
@@ -301,29 +357,38 @@ def _jvp_roofline(args, g, y, w, stream):
 
 
 
-def equal_error_leg(args):
+def equal_error_leg(args, ndim=2):
     """FP32 residual/tangent + FP64 Krylov against plain FP64 with finite-difference
     products, at equal final-time error (work-precision sweep).
 
-    Proxy of the viscous Taylor-Green workload at 512^2 (Re 100, Mach 0.1,
-    MUSCL, M = 20).  Both forms integrate to the same final time T = 10 h(CFL 4)
-    at CFL 1, 2, 4, 8; the error is ||y_N - y_ref|| / ||y_ref|| with y_ref the
-    FP64 exact-product ROK solution at CFL 1/8 (320 steps; it agrees with
-    explicit RK4 at CFL 1/4 to about 3e-12).  Trajectories are timed with HIP
-    events.  speedup_at_equal_error: for each FP32 point, the FD time at the same
-    error (log-log interpolation between the bracketing FD points) over the FP32
-    time."""
+    ndim = 2: proxy of the 2048^2 viscous Taylor-Green workload at 512^2 (Re
+    100, Mach 0.1, MUSCL, M = 20), T = 10 h(CFL 4), CFL 1, 2, 4, 8.
+    ndim = 3: proxy of the 256^3 workload at 96^3 (Re 1600, Mach 0.1, MUSCL,
+    M = 16), T = 2 h(CFL 20), CFL 2.5, 5, 10, 20.
+    Both forms integrate to the same final time; the error is
+    ||y_N - y_ref|| / ||y_ref|| with y_ref the FP64 exact-product ROK solution
+    at CFL 1/8.  Trajectories are timed with HIP events.
+    speedup_at_equal_error: for each FP32 point, the FD time at the same error
+    (log-log interpolation between the bracketing FD points) over the FP32
+    time.  fp32_floor: the smallest FP32 error reached (where its curve
+    flattens)."""
     import torch
 
     import rok_inputs as ri
     from paper_1607_06834_amd import Rok
 
     dev = torch.device("cuda", 0)
-    pb = ri.tgv_problem(512, 2)
+    if ndim == 2:
+        pb = ri.tgv_problem(512, 2)
+        M, cfls, T_cfl, T_mult = 20, (1.0, 2.0, 4.0, 8.0), 4.0, 10
+        label = "Taylor-Green 2-D, 512x512, Re 100, Mach 0.1, MUSCL, M = 20, T = 10 h(CFL 4)"
+    else:
+        pb = ri.tgv_problem(96, 3)
+        M, cfls, T_cfl, T_mult = 16, (2.5, 5.0, 10.0, 20.0), 20.0, 2
+        label = "Taylor-Green 3-D, 96^3, Re 1600, Mach 0.1, MUSCL, M = 16, T = 2 h(CFL 20)"
     y0 = ri.tgv_state(pb)
     tab = ri.rok4_tableau()
-    M = 20
-    T = 10 * ri.cfl_step(pb, y0, 4.0)
+    T = T_mult * ri.cfl_step(pb, y0, T_cfl)
     g64, g32 = Rok(pb, "fp64"), Rok(pb, "fp32")
     stream = torch.cuda.current_stream()
 
@@ -343,15 +408,18 @@ def equal_error_leg(args):
     ref, _, _ = run(g64, 0.125, "exact")
     nref = float(torch.linalg.vector_norm(ref))
     pts = {"fp64_fd": [], "fp32_tangent": []}
-    for cfl in (1.0, 2.0, 4.0, 8.0):
+    for cfl in cfls:
         for name, g, mode in (("fp64_fd", g64, "fd"), ("fp32_tangent", g32, "exact")):
             y, ms, K = run(g, cfl, mode)
             err = float(torch.linalg.vector_norm(y - ref)) / nref
-            pts[name].append({"cfl": cfl, "steps": K, "ms": round(ms, 3), "error": float(f"{err:.4e}")})
-    fd = sorted(pts["fp64_fd"], key=lambda q: q["error"])
+            err = float(f"{err:.4e}") if math.isfinite(err) else None   # None: the trajectory blew up
+            pts[name].append({"cfl": cfl, "steps": K, "ms": round(ms, 3), "error": err})
+    fd = sorted((q for q in pts["fp64_fd"] if q["error"] is not None), key=lambda q: q["error"])
     ratios = []
     for q in pts["fp32_tangent"]:
         e = q["error"]
+        if e is None:
+            continue
         for a, b in zip(fd, fd[1:]):
             if a["error"] <= e <= b["error"] and a["error"] > 0 and b["error"] > a["error"]:
                 f = (math.log(e) - math.log(a["error"])) / (math.log(b["error"]) - math.log(a["error"]))
@@ -359,8 +427,9 @@ def equal_error_leg(args):
                 ratios.append({"error": e, "fp32_ms": q["ms"], "fp64_fd_ms": round(t_fd, 3),
                                "speedup": round(t_fd / q["ms"], 3)})
                 break
-    return {"workload": "Taylor-Green 2-D, 512x512, Re 100, Mach 0.1, MUSCL, M = 20, T = 10 h(CFL 4)",
-            "reference": "FP64 exact-product ROK at CFL 1/8", "points": pts, "speedup_at_equal_error": ratios}
+    floor = min((q["error"] for q in pts["fp32_tangent"] if q["error"] is not None), default=None)
+    return {"workload": label, "reference": "FP64 exact-product ROK at CFL 1/8", "points": pts,
+            "speedup_at_equal_error": ratios, "fp32_floor": floor}
 
 
 def krylov_sweep_leg(args):
@@ -630,28 +699,134 @@ def eigs_leg(args):
     return out
 
 
-def cpu_leg(args, pb, y0, w, tab, h):
+def _oracle_step_rate(pb, w, tab, cfl, threads, budget_s):
+    """Steps/s of the oracle (as it stands) on one configuration with `threads` threads:
+    steps from the seeded state until budget_s has passed (at least one)."""
+    import numpy as np
     import torch
 
+    import rok_inputs as ri
     from oracle import fv, rok
 
-    torch.set_num_threads(torch.get_num_threads())
+    torch.set_num_threads(threads)
+    y0 = ri.tgv_state(pb) if pb["physics"] == "ns" else ri.vortex_state(pb)
+    h = ri.cfl_step(pb, y0, cfl)
     P = fv.Problem(n=pb["n"], lo=pb["lo"], hi=pb["hi"], physics=pb["physics"], recon=pb["recon"],
                    gamma=pb["gamma"], mu=pb["mu"], prandtl=pb["prandtl"])
     f, mv = rok.fv_system(P, "fd" if w["jvp"] == "fd" else "exact")
-    y = torch.tensor(y0, dtype=torch.float64)
-    steps = 0
-    t0 = time.perf_counter()
+    y = torch.from_numpy(np.asarray(y0, dtype=np.float64))
+    steps, t0 = 0, time.perf_counter()
     while True:
-        y1 = rok.rok_step(f, mv, tab, w["M"], h, y)
-        if args.chain:
-            y = y1
+        rok.rok_step(f, mv, tab, w["M"], h, y)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= args.cpu_seconds or steps >= 50:
-            break
-    return {"value": round(steps / el, 5), "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{steps} ROK step(s) of the same workload from the same initial state ({el:.1f} s)"}
+        if el >= budget_s or steps >= 50:
+            return steps, el
+
+
+def _lscpu():
+    import subprocess
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    keep = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)", "NUMA node(s)")
+    out = {}
+    for line in txt.splitlines():
+        k, _, v = line.partition(":")
+        if k.strip() in keep:
+            out[k.strip()] = v.strip()
+    try:
+        out["usable_cpus"] = len(os.sched_getaffinity(0))
+    except OSError:
+        pass
+    return out
+
+
+def cpu_leg(args, pb, y0, w, tab, h):
+    """The oracle on the host's cores.  Large grids take the oracle minutes per
+    step (256^3: about ten), so the sample is one configuration of the same
+    physics, discretisation, Krylov dimension and CFL number on a smaller grid,
+    and the rate is scaled by the ratio of unknowns (every part of the step is
+    linear in N).  All threads the process may use, then one thread on a grid
+    with half the cells per direction."""
+    import torch
+
+    import rok_inputs as ri
+
+    N = ri.size(pb)
+    threads = torch.get_num_threads()
+    D = len(pb["n"])
+    nvar = D + 2
+    # sample grid: cells per direction so that the sample has at most ~4.5 M unknowns (an oracle step
+    # then takes 10-30 s on 8-16 threads), a multiple of 8; the one-thread sample halves it
+    ns = min(int(pb["n"][0]), int((4.5e6 / nvar) ** (1.0 / D)) // 8 * 8)
+    sample = dict(pb, n=tuple([ns] * D))
+    one = dict(pb, n=tuple([ns // 2] * D))
+    steps, el = _oracle_step_rate(sample, w, tab, w["cfl"], threads, args.cpu_seconds)
+    ns = ri.size(sample)
+    s1, e1 = _oracle_step_rate(one, w, tab, w["cfl"], 1, args.cpu_seconds)
+    n1 = ri.size(one)
+    torch.set_num_threads(threads)
+    grid = "x".join(str(x) for x in sample["n"])
+    grid1 = "x".join(str(x) for x in one["n"])
+    return {"value": round(steps / el * ns / N, 6), "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} oracle ROK step(s) of the same configuration on a {grid} grid ({ns} unknowns, "
+                      f"{el:.1f} s, {threads} threads), rate scaled by {ns}/{N} unknowns",
+            "one_thread": {"value": round(s1 / e1 * n1 / N, 7), "unit": "steps/s",
+                           "sample": f"{s1} step(s) on {grid1} ({n1} unknowns, {e1:.1f} s), scaled by {n1}/{N}"},
+            "lscpu": _lscpu()}
+
+
+def fp32_leg(args, stream=None):
+    """The precision form on the headline workload: FP32 residual and tangent
+    products, FP64 Krylov, solve and accumulation; its rate (same K steps
+    from the seeded state) and one step's error against the FP64 GPU step
+    with exact products from the same state (whose full-size parity with the
+    oracle is tested at sampled indices), beside the plain FP64 + FD step's."""
+    import torch
+
+    import rok_inputs as ri
+    from paper_1607_06834_amd import Rok
+
+    pb, y0, w = ri.workload("tgv256_3d")
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, w["cfl"])
+    res = gpu_leg(args, pb, y0, w, tab, h, rooflines=False)
+    dev = torch.device("cuda", 0)
+    yd = torch.tensor(y0, device=dev)
+    g32 = Rok(pb, "fp32")
+    s32 = g32.step(yd, h, tab, w["M"], "exact").clone()
+    del g32
+    g64 = Rok(pb, "fp64")
+    ref = g64.step(yd, h, tab, w["M"], "exact").clone()
+    fd = g64.step(yd, h, tab, w["M"], "fd")
+    nref = float(torch.linalg.vector_norm(ref))
+    e32 = float(torch.linalg.vector_norm(s32 - ref)) / nref
+    efd = float(torch.linalg.vector_norm(fd - ref)) / nref
+    del g64, s32, ref, fd
+    return {"value": round(1000.0 / res["ms_per_step"], 3), "unit": "steps/s",
+            "ms_per_step": round(res["ms_per_step"], 4), "dtype": "f32-residual/f64-krylov", "jvp": "tangent",
+            "flags": res["flags"], "M_eff": res["M_eff"],
+            "step_error_vs_fp64_exact": float(f"{e32:.3e}"), "fp64_fd_step_error_vs_fp64_exact": float(f"{efd:.3e}")}
+
+
+def secondary_leg(args):
+    """The 1024^2 MUSCL vortex (M = 16, FD products, CFL 10), its rate and resident-MGS roofline."""
+    import rok_inputs as ri
+
+    pb, y0, w = ri.workload("vortex1024_muscl")
+    tab = ri.rok4_tableau()
+    h = ri.cfl_step(pb, y0, w["cfl"])
+    sub = argparse.Namespace(**vars(args))
+    sub.workload = "vortex1024_muscl"
+    sub.traffic = None
+    res = gpu_leg(sub, pb, y0, w, tab, h)
+    return {"value": round(1000.0 / res["ms_per_step"], 3), "unit": "steps/s", "ms_per_step": round(res["ms_per_step"], 4),
+            "config": {"grid": "1024x1024", "physics": "euler", "recon": "muscl", "krylov_M": 16, "jvp": "fd",
+                       "cfl": 10.0, "N": ri.size(pb)},
+            "flags": res["flags"], "roofline": res["roofline"], "arnoldi_step": res["arnoldi_step"],
+            "roofline_jvp": res["roofline_jvp"], "roofline_residual": res["roofline_residual"]}
 
 
 def main():
@@ -666,13 +841,19 @@ def main():
     tab = ri.rok4_tableau()
     h = ri.cfl_step(pb, y0, w["cfl"])
     res = gpu_leg(args, pb, y0, w, tab, h)
-    eq = None if (args.no_equal_error or args.roofline_only) else equal_error_leg(args)
+    print(f"[bench] {args.workload}: {res['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    extra = not (args.no_secondary or args.roofline_only) and args.workload == "tgv256_3d_fp64"
+    f32 = fp32_leg(args) if extra else None
+    sec = secondary_leg(args) if extra else None
+    eq = None if (args.no_equal_error or args.roofline_only) else {"2d": equal_error_leg(args, 2),
+                                                                    "3d": equal_error_leg(args, 3)}
     ksw = krylov_sweep_leg(args) if (args.krylov_sweep and not args.roofline_only) else None
     ada = adaptive_leg(args) if (args.adaptive and not args.roofline_only) else None
     eig = eigs_leg(args) if (args.eigs and not args.roofline_only) else None
     adj_og = adjoint_ogrid_leg(args) if (args.adjoint_ogrid and not args.roofline_only) else None
-    cpu = None if args.no_cpu_baseline else cpu_leg(args, pb, y0, w, tab, h)
+    cpu = None if (args.no_cpu_baseline or args.roofline_only) else cpu_leg(args, pb, y0, w, tab, h)
     n = "x".join(str(x) for x in pb["n"])
+    wl = {"tgv256_3d_fp64": "tgv256_3d"}.get(args.workload, args.workload)
     line = {
         "metric": "ROK steps/sec",
         "value": round(1000.0 / res["ms_per_step"], 3),
@@ -686,18 +867,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if w["precision"] == "fp64" else "f32-residual/f64-krylov",
         "data": "synthetic",
-        "config": {"workload": args.workload, "grid": n, "physics": pb["physics"], "recon": pb["recon"],
-                   "flux": "rusanov", "krylov_M": w["M"], "stages": tab["s"], "jvp": w["jvp"], "cfl": w["cfl"],
-                   "h": h, "N": ri.size(pb),
+        "config": {"workload": wl, "grid": n, "physics": pb["physics"], "recon": pb["recon"],
+                   "flux": "rusanov", "krylov_M": w["M"], "stages": tab["s"], "jvp": w["jvp"],
+                   "precision": w["precision"], "cfl": w["cfl"], "h": h, "N": ri.size(pb),
                    "timed_steps": ("trajectory" if args.chain else
-                                   "K full ROK steps, each from the seeded initial state (per-step work does not "
-                                   "depend on the state; ROK4 with M=16 is not stable at CFL 10 on this problem "
-                                   "over many steps)")},
+                                   "K full ROK steps, each from the seeded initial state (the per-step work does "
+                                   "not depend on the state)")},
         "status": {"flags": res["flags"], "M_eff": res["M_eff"], "finite": res["finite"]},
-        "roofline": res["roofline"],
-        "roofline_jvp": res["roofline_jvp"],
-        "roofline_residual": res["roofline_residual"],
-        "adjoint": res["adjoint"],
+        "roofline": res.get("roofline"),
+        "arnoldi_step": res.get("arnoldi_step"),
+        "roofline_jvp": res.get("roofline_jvp"),
+        "roofline_residual": res.get("roofline_residual"),
+        "fp32_tangent": f32,
+        "secondary": {"vortex1024_muscl": sec} if sec else None,
+        "adjoint": res.get("adjoint"),
         "equal_error": eq,
         "krylov_sweep": ksw,
         "adaptive": ada,

@@ -56,12 +56,19 @@ enum { ROK_RUSANOV = 0, ROK_ROE = 1 };               /* inviscid flux           
 enum { ROK_FP64 = 0, ROK_FP32_RESIDUAL = 1 };        /* precision of f and J v      */
 enum { ROK_JVP_FD = 0, ROK_JVP_TANGENT = 1 };        /* Jacobian-vector product     */
 
-/* status-word bits (rok_read_status) */
+/* status-word bits (rok_read_status).  The gas law has no positivity fix
+ * (Sec. 3.2: ideal gas, p = (gamma - 1)(E - rho |u|^2 / 2)): a non-physical
+ * state is reported, and the arithmetic goes on with it (a square root of a
+ * negative pressure gives NaN, which is reported as non-finite). */
 enum {
-    ROK_FLAG_NONFINITE = 1,   /* a NaN or Inf appeared in H, phi or lambda           */
+    ROK_FLAG_NONFINITE = 1,   /* a NaN or Inf appeared in a residual or product  */
+                              /* output (F_i, J v_j; so also from a NaN in y),    */
+                              /* in H, phi or lambda                              */
     ROK_FLAG_BREAKDOWN = 2,   /* Arnoldi stopped early: M_eff < M (invariant space) */
     ROK_FLAG_ZERO_RHS = 4,    /* f(y_n) = 0 exactly: M_eff = 0                       */
-    ROK_FLAG_BARRIER = 8      /* an in-kernel grid barrier timed out (results invalid) */
+    ROK_FLAG_BARRIER = 8,     /* an in-kernel grid barrier timed out (results invalid) */
+    ROK_FLAG_NONPHYSICAL = 16 /* a residual or product saw a cell with rho <= 0 or */
+                              /* p <= 0 (y_n, a stage state Y_i, or y_n + eps v_j) */
 };
 
 /* Implementation of the modified Gram-Schmidt passes (rok_set_mgs_path). */
@@ -250,7 +257,9 @@ rok_status rok_jvp(rok_ctx* ctx, const double* y, const double* fy, const double
  *           leading M_eff x M_eff Hessenberg block)
  *   M_eff:  one device int: the dimension reached (0 when fy = 0; < M on an
  *           invariant subspace, i.e. h_{j+1,j} <= 1e-13 ||(h_1j..h_{j+1,j})||)
- *   work:   rok_workspace_bytes(ctx, M, 0) bytes
+ *   work:   rok_workspace_bytes(ctx, M, 0) bytes; its status word
+ *           (rok_read_status) reports the products J v_j: ROK_FLAG_NONPHYSICAL
+ *           and ROK_FLAG_NONFINITE as for rok_step
  */
 rok_status rok_arnoldi(rok_ctx* ctx, const double* y, const double* fy, int M, int mode, double eps,
                        double* V, double* H, int* M_eff, void* work, size_t work_bytes, void* stream);
@@ -294,6 +303,12 @@ rok_status rok_workspace_init(rok_ctx* ctx, void* work, size_t work_bytes, int M
  *   tab:    host tableau;  M: 0..ROK_MAX_M (clamped to N);  h: step size
  *   y_n, y_np1: N doubles each (may not alias)
  *   work:   rok_workspace_bytes(ctx, M, tab->s) bytes
+ * Status word of `work` (rok_read_status), cleared at the start of the call:
+ * ROK_FLAG_NONPHYSICAL if any stage residual or product staged a cell with
+ * rho <= 0 or p <= 0 (the step is still computed, with no positivity fix),
+ * ROK_FLAG_NONFINITE if a stage residual, a product, H, phi or lambda holds
+ * a NaN or Inf (a NaN anywhere in y_n reaches F_1), plus the Arnoldi bits.
+ * rok_residual and rok_jvp take no status word and report nothing.
  */
 rok_status rok_step(rok_ctx* ctx, const rok_tableau* tab, int M, int mode, double h,
                     const double* y_n, double* y_np1, void* work, size_t work_bytes, void* stream);

@@ -129,10 +129,83 @@ def _absw(x):
     return torch.where(x >= 0, x, -x)
 
 
-def _minmod(a, b):
+# f is piecewise smooth: minmod, the |.| of the face-normal velocity and the
+# maximum of the two Rusanov wave speeds each choose between smooth branches,
+# and J jumps where a state crosses such a switch (an exact-product ROK step is
+# then discontinuous in y_n).  Inside `with branches(...)`, every one of these
+# decisions is routed through the context, in the fixed order in which one
+# evaluation of f makes them (a decision "site" = one call, elementwise over
+# the grid): a plain evaluation can record each decision's distance from its
+# switch, relative to the size of the quantities compared, and any evaluation
+# (a forward-mode product included) can take listed decisions the other way,
+# i.e. differentiate the other one-sided branch.  Outside a context nothing
+# changes.  Roe's flux and the O-grid boundary slopes are not routed.
+_BRANCHES = None
+
+
+class branches:
+    """Context: record = True stores {site: (kind, relative margin tensor)} in
+    .margins and {site: the decision taken (bool tensor)} in .decisions (plain
+    evaluations only); flip = {site: bool tensor} inverts those decisions where
+    the mask is True."""
+
+    def __init__(self, record: bool = False, flip: dict | None = None):
+        self.record = record
+        self.flip = dict(flip or {})
+        self.margins = {}
+        self.decisions = {}
+        self._site = 0
+        self._prev = None
+
+    def __enter__(self):
+        global _BRANCHES
+        self._prev = _BRANCHES
+        self._site = 0
+        _BRANCHES = self
+        return self
+
+    def __exit__(self, *exc):
+        global _BRANCHES
+        _BRANCHES = self._prev
+        return False
+
+
+def _decide(cond, kind, margin):
+    """cond: boolean tensor of one decision site; margin(): its distances from
+    the switch (called only when recording)."""
+    ctx = _BRANCHES
+    if ctx is None:
+        return cond
+    site = ctx._site
+    ctx._site += 1
+    f = ctx.flip.get(site)
+    out = cond if f is None else torch.logical_xor(cond, f)
+    if ctx.record:
+        ctx.margins[site] = (kind, margin())
+        ctx.decisions[site] = out.clone()
+    return out
+
+
+def _spread(q):
+    """Size of a field's variation (its range), the scale of its slopes' decisions."""
+    r = float(q.max() - q.min())
+    return r if r > 0.0 else 1.0
+
+
+def _minmod(a, b, q=None):
+    """mm(a, b); q (optional): the field whose slopes a, b are (sets the scale of
+    the recorded margins, else max |a|, |b|)."""
     zero = torch.zeros_like(a)
-    pick = torch.where(_absw(a) <= _absw(b), a, b)
-    return torch.where(a * b <= 0, zero, pick)
+    aa, ab = _absw(a), _absw(b)
+
+    def scale():
+        return _spread(q) if q is not None else max(float(torch.maximum(aa, ab).max()), 1e-300)
+
+    pick_a = _decide(aa <= ab, "minmod |a| <= |b|",
+                     lambda: torch.where(a * b > 0, (aa - ab).abs() / scale(), torch.full_like(a, math.inf)))
+    pick = torch.where(pick_a, a, b)
+    flat = _decide(a * b <= 0, "minmod a b <= 0", lambda: torch.minimum(aa, ab) / scale())
+    return torch.where(flat, zero, pick)
 
 
 def primitives(P: Problem, U):
@@ -178,9 +251,14 @@ def _rusanov(P: Problem, UL, rL, vL, pL, UR, rR, vR, pR, d):
     g = P.gamma
     cL = _sqrt(g * pL / rL)
     cR = _sqrt(g * pR / rR)
-    sL = _absw(vL[d]) + cL
-    sR = _absw(vR[d]) + cR
-    a = torch.where(sL >= sR, sL, sR)
+    uL, uR = vL[d], vR[d]
+
+    def speed():   # scale of the |u_n| decisions: the largest wave speed at the faces
+        return max(float(torch.maximum(uL.abs() + cL, uR.abs() + cR).max()), 1e-300)
+
+    sL = torch.where(_decide(uL >= 0, "|u_n,L|", lambda: uL.abs() / speed()), uL, -uL) + cL
+    sR = torch.where(_decide(uR >= 0, "|u_n,R|", lambda: uR.abs() / speed()), uR, -uR) + cR
+    a = torch.where(_decide(sL >= sR, "max(s_L, s_R)", lambda: (sL - sR).abs() / torch.maximum(sL, sR)), sL, sR)
     FL = _euler_flux(P, UL, vL, pL, d)
     FR = _euler_flux(P, UR, vR, pR, d)
     return [0.5 * (FL[m] + FR[m]) - 0.5 * a * (UR[m] - UL[m]) for m in range(P.nvar)]
@@ -283,8 +361,8 @@ def _face_states(P: Problem, U, r, vel, p, d):
     qL, qR = [], []
     for a in q:
         am1, ap1, ap2 = _at(a, -1, d), _at(a, 1, d), _at(a, 2, d)
-        qL.append(a + 0.5 * _minmod(a - am1, ap1 - a))
-        qR.append(ap1 - 0.5 * _minmod(ap1 - a, ap2 - ap1))
+        qL.append(a + 0.5 * _minmod(a - am1, ap1 - a, a))
+        qR.append(ap1 - 0.5 * _minmod(ap1 - a, ap2 - ap1, a))
     rL, vL, pL = qL[0], qL[1:1 + D], qL[D + 1]
     rR, vR, pR = qR[0], qR[1:1 + D], qR[D + 1]
     return (conserved(P, rL, vL, pL), rL, vL, pL), (conserved(P, rR, vR, pR), rR, vR, pR)
@@ -584,11 +662,14 @@ def _residual_curvilinear(P: Problem, y: torch.Tensor) -> torch.Tensor:
     return out.reshape(-1)
 
 
-def residual(P: Problem, y: torch.Tensor, part: str = "all") -> torch.Tensor:
+def residual(P: Problem, y: torch.Tensor, part: str = "all", terms: list | None = None) -> torch.Tensor:
     """f(y) for a flat state vector y of length P.size (float64).
 
     part = "inviscid" or "viscous" assembles f from that flux alone (the
-    split output of the residual: the two parts add up to f)."""
+    split output of the residual: the two parts add up to f).  terms: if a
+    list is given (Cartesian grids), each direction's flux difference
+    (F_{c-1/2} - F_{c+1/2}) / dx_d is appended to it, flat; f is their sum in
+    direction order."""
     if part not in ("all", "inviscid", "viscous"):
         raise ValueError(f"unknown part {part!r}")
     if P.nodes is not None:
@@ -614,8 +695,17 @@ def residual(P: Problem, y: torch.Tensor, part: str = "all") -> torch.Tensor:
             Fh = [Fh[m] - Fv[m] for m in range(P.nvar)]
         inv = P.invdx(d)
         term = torch.stack([(_at(Fh[m], -1, d) - Fh[m]) * inv for m in range(P.nvar)])
+        if terms is not None:
+            terms.append(term.reshape(-1))
         out = term if out is None else out + term
     return out.reshape(-1)
+
+
+def residual_terms(P: Problem, y: torch.Tensor) -> torch.Tensor:
+    """The D per-direction flux differences whose sum (in direction order) is f(y), as a (D, N) tensor."""
+    terms = []
+    residual(P, y, terms=terms)
+    return torch.stack(terms)
 
 
 # ---------------------------------------------------------------------------

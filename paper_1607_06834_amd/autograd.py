@@ -28,6 +28,8 @@ class _RokTrajectory(torch.autograd.Function):
     def forward(ctx, y0, rok: Rok, h: float, tableau: dict, M: int, nsteps: int, every: int):
         y = y0.detach().contiguous()
         checkpoints = {0: y.clone()}
+        if nsteps == 0:
+            y = y.clone()   # the identity map: a tensor of its own, not a view of the input
         for n in range(nsteps):
             y = rok.step(y, h, tableau, M, mode="tangent")
             if (n + 1) % every == 0 and n + 1 < nsteps:
@@ -44,6 +46,8 @@ class _RokTrajectory(torch.autograd.Function):
         starts = sorted(ctx.checkpoints, reverse=True)
         end = ctx.nsteps
         for s0 in starts:
+            if s0 >= end:   # no step in this segment (nsteps = 0): the identity
+                continue
             states = [ctx.checkpoints[s0]]
             for _ in range(s0, end - 1):   # recompute y_{s0+1} .. y_{end-1}
                 states.append(rok.step(states[-1], h, tab, M, mode="tangent"))
@@ -87,6 +91,8 @@ def rok_trajectory(rok: Rok, y0: torch.Tensor, h: float, tableau: dict, M: int, 
     (Rok.step_vjp_stored) instead of recomputing: same bits, less time, more
     memory.  Otherwise states are checkpointed every `checkpoint_every` steps.
     """
+    if int(nsteps) < 0:
+        raise ValueError("nsteps must be >= 0")
     if store_forward:
         return _RokTrajectoryStored.apply(y0, rok, float(h), tableau, int(M), int(nsteps))
     every = 1 if checkpoint_every is None else int(checkpoint_every)

@@ -51,8 +51,10 @@ rok::ResArgs plain_args(const double* y, void* out) {
 
 // w = J(y) v into a double vector (internal use).  FD reads eps from eps_dev.
 hipError_t jvp_into(const rok_ctx* c, const double* y, const double* fy, const double* v, double* w, int mode,
-                    const double* eps_dev, double eps, hipStream_t st, const int* gate = nullptr, int gate_col = 0) {
+                    const double* eps_dev, double eps, hipStream_t st, const int* gate = nullptr, int gate_col = 0,
+                    int* status = nullptr) {
     rok::ResArgs A{};
+    A.status = status;
     A.gate = gate;
     A.gate_col = gate_col;
     A.y = y;
@@ -82,7 +84,7 @@ hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, c
     if (c->mgs_path == ROK_MGS_RESIDENT && !resident) return hipErrorNotSupported;
     for (int j = 0; j < M; ++j) {
         double* vj = V + (long)j * N;
-        e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st);
+        e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st, nullptr, 0, W.ints + 2);
         if (e != hipSuccess) return e;
         double* vnext = (j + 1 < M) ? V + (long)(j + 1) * N : nullptr;
         if (resident)
@@ -104,6 +106,7 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
     if (e != hipSuccess) return e;
     {   // F_1 = f(y_n)
         rok::ResArgs A = plain_args(y_n, W.F);
+        A.status = W.ints + 2;
         e = rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st);
         if (e != hipSuccess) return e;
     }
@@ -127,6 +130,7 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
                 }
             }
             A.nterm = t;
+            A.status = W.ints + 2;
             e = rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st);
             if (e != hipSuccess) return e;
         }
@@ -352,35 +356,59 @@ rok_status rok_residual_split(rok_ctx* c, const double* y, void* F_inv, void* F_
     return ROK_OK;
 }
 
-rok_status rok_jvp(rok_ctx* c, const double* y, const double* fy, const double* v, void* w, int mode, double eps,
-                   void* work, size_t wbytes, void* stream) {
+namespace {
+
+// Validation of rok_jvp's arguments.
+rok_status jvp_args_ok(const rok_ctx* c, const double* y, const double* fy, const double* v, const void* w,
+                       int mode) {
     if (!c || !y || !v || !w || !aligned(y, 8) || !aligned(v, 8) || !aligned(w, fp32(c) ? 4 : 8)) return ROK_EINVAL;
     if (mode != ROK_JVP_FD && mode != ROK_JVP_TANGENT) return ROK_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
+    if (mode == ROK_JVP_FD) {
+        if (fp32(c)) return ROK_EUNSUPPORTED;
+        if (!fy || !aligned(fy, 8)) return ROK_EINVAL;
+    }
+    return ROK_OK;
+}
+
+// The launches of rok_jvp once the arguments are valid.  `small` is the
+// base of the small workspace layout (header, scalars, reduction
+// partials); it is touched only for a finite-difference product with the
+// default increment (eps <= 0).
+hipError_t jvp_launch(const rok_ctx* c, const double* y, const double* fy, const double* v, void* w, int mode,
+                      double eps, void* small, hipStream_t st) {
     rok::ResArgs A{};
     A.y = y;
     A.v = v;
     A.out = w;
-    if (mode == ROK_JVP_TANGENT) {
-        ROK_TRY(rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, fp32(c), 2, !fp32(c), A, st));
-        return ROK_OK;
-    }
-    if (fp32(c)) return ROK_EUNSUPPORTED;
-    if (!fy || !aligned(fy, 8)) return ROK_EINVAL;
+    if (mode == ROK_JVP_TANGENT)
+        return rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, fp32(c), 2, !fp32(c), A, st);
     A.f0 = fy;
     if (eps > 0.0) {
         A.eps = eps;
     } else {
-        size_t need = rok::work_bytes(c->G.N, 0, 0, false);
-        if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
-        rok::Work W = rok::carve(work, c->G.N, 0, 0, false);
-        ROK_TRY(rok::launch_init(W, 0, 0, st));
-        ROK_TRY(rok::launch_norm_eps(W, y, v, c->G.N, st));
+        rok::Work W = rok::carve(small, 0, 0, 0, false);
+        hipError_t e = rok::launch_init(W, 0, 0, st);
+        if (e == hipSuccess) e = rok::launch_norm_eps(W, y, v, c->G.N, st);
+        if (e != hipSuccess) return e;
         A.eps_dev = W.scal + 1;
     }
-    ROK_TRY(rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, false, 1, true, A, st));
+    return rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, false, 1, true, A, st);
+}
+
+}  // namespace
+
+rok_status rok_jvp(rok_ctx* c, const double* y, const double* fy, const double* v, void* w, int mode, double eps,
+                   void* work, size_t wbytes, void* stream) {
+    rok_status r = jvp_args_ok(c, y, fy, v, w, mode);
+    if (r != ROK_OK) return r;
+    if (mode == ROK_JVP_FD && !(eps > 0.0)) {
+        size_t need = rok::work_bytes(c->G.N, 0, 0, false);
+        if (!work || !aligned(work, 256) || wbytes < need) return ROK_EINVAL;
+    }
+    ROK_TRY(jvp_launch(c, y, fy, v, w, mode, eps, work, (hipStream_t)stream));
     return ROK_OK;
 }
+
 
 rok_status rok_arnoldi(rok_ctx* c, const double* y, const double* fy, int M, int mode, double eps, double* V,
                        double* H, int* M_eff, void* work, size_t wbytes, void* stream) {

@@ -56,6 +56,9 @@ struct ResArgs {
     int gate_col;
     // Navier-Stokes kernels: assemble the viscous part of f only
     int viscous_only;
+    // optional status word: ROK_FLAG_NONPHYSICAL is or-ed in when a staged
+    // cell has rho <= 0 or p <= 0, ROK_FLAG_NONFINITE when an output is NaN or Inf
+    int* status;
 };
 
 // ---------------------------------------------------------------------------

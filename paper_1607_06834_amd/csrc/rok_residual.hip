@@ -20,6 +20,7 @@
 // instantiations stage primitive perturbations about a reference state (the
 // tile's centre cell, taken in FP64) and use the reference-state flux, so
 // the large constant part of pressure and energy never enters FP32 sums.
+#include "rok.h"
 #include "rok_device.hpp"
 #include "rok_kernels.hpp"
 #include "rok_flux.hpp"
@@ -190,7 +191,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 
     // 1. stage the box in LDS as primitive variables.  All loads of this
     // thread's box cells are issued first, then converted: the loads overlap
-    // instead of waiting one cell at a time.
+    // instead of waiting one cell at a time.  `np` records a staged cell with
+    // rho <= 0 or p <= 0 (no positivity fix: the arithmetic goes on).
+    int np = 0;
     if constexpr (!PERT) {
         constexpr int NIT = (ST::N + kThreads - 1) / kThreads;
         S Ub[NIT][NV];
@@ -225,6 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 #pragma unroll
                 for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
                 S p = gm1 * (U[D + 1] - (half * r) * ke);
+                np |= (Sc<S>::val(r) <= (R)0 || Sc<S>::val(p) <= (R)0) ? 1 : 0;
                 if constexpr (CONS) {
 #pragma unroll
                     for (int m = 0; m < NV; ++m) sq[m][c] = U[m];
@@ -263,6 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 #pragma unroll
             for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
             SD p = G.gm1 * (U[D + 1] - (0.5 * r) * ke);
+            np |= (Sc<SD>::val(r) <= 0.0 || Sc<SD>::val(p) <= 0.0) ? 1 : 0;
             sq[0][c] = narrow<S>(r - s_refd[0]);
 #pragma unroll
             for (int d = 0; d < D; ++d) sq[1 + d][c] = narrow<S>(vel[d] - s_refd[1 + d]);
@@ -574,7 +579,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
         __syncthreads();
     }
 
-    // 4. write out
+    // 4. write out (and note a NaN or Inf in the output)
+    bool nonfin = false;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
         int cell = tid + k * kThreads;
@@ -587,15 +593,21 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 #pragma unroll
         for (int m = 0; m < NV; ++m) {
             long o = (long)m * G.ncell + gi;
+            OUT x;
             if constexpr (MODE == MODE_PLAIN) {
-                out[o] = (OUT)res[k][m];
+                x = (OUT)res[k][m];
             } else if constexpr (MODE == MODE_FD) {
-                out[o] = (OUT)((res[k][m] - A.f0[o]) / eps);
+                x = (OUT)((res[k][m] - A.f0[o]) / eps);
             } else {
-                out[o] = (OUT)res[k][m].d;
+                x = (OUT)res[k][m].d;
             }
+            out[o] = x;
+            nonfin = nonfin || !(fabs((double)x) < __builtin_inf());
         }
     }
+    // rare: only a thread that saw a non-physical cell or a non-finite output touches the status word
+    if (A.status && (np || nonfin))
+        atomicOr(A.status, (np ? (int)ROK_FLAG_NONPHYSICAL : 0) | (nonfin ? (int)ROK_FLAG_NONFINITE : 0));
 }
 
 // ---------------------------------------------------------------------------

@@ -21,7 +21,7 @@ FIRST_ORDER, MUSCL_MINMOD = 0, 1
 RUSANOV, ROE = 0, 1
 FP64, FP32_RESIDUAL = 0, 1
 JVP_FD, JVP_TANGENT = 0, 1
-FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER = 1, 2, 4, 8
+FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER, FLAG_NONPHYSICAL = 1, 2, 4, 8, 16
 MAX_STAGES, MAX_M = 8, 64
 
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
@@ -200,6 +200,7 @@ class Rok:
         _check(lib.rok_create(ctypes.byref(p), ctypes.byref(self._ctx)), "rok_create")
         self.N = int(lib.rok_state_size(self._ctx))
         _check(lib.rok_set_mgs_path(self._ctx, MGS_PATHS[mgs]), "rok_set_mgs_path")
+        self.mgs = mgs
         self._work = {}
         self.device = torch.device("cuda", torch.cuda.current_device())
 
@@ -280,6 +281,7 @@ class Rok:
         m = JVP_FD if mode == "fd" else JVP_TANGENT
         _check(_lib.rok_arnoldi(self._ctx, _ptr(y), _ptr(fy), M, m, float(eps), _ptr(V), _ptr(H), _ptr(meff),
                                 _ptr(ws), ws.numel(), _stream()), "rok_arnoldi")
+        self._last_arnoldi_ws = ws
         k = int(meff.item())
         return V[:k], H[:k, :k], k
 
@@ -458,6 +460,11 @@ class Rok:
         self._last_step_ws = rec.ws
         return yb
 
+    def mgs_resident(self) -> bool:
+        """Whether the Arnoldi columns run the resident kernel (the library's rule
+        for the default path: up to 16 elements per lane of its 2^18-lane grid)."""
+        return self.mgs != "pass" and self.N <= 16 * (1 << 18)
+
     def mgs_workspace(self, M: int) -> torch.Tensor:
         """A workspace for column-level calls, prepared for Krylov dimension M."""
         ws = self.workspace(M, 0)
@@ -478,6 +485,13 @@ class Rok:
             self._vec(vnext, "vnext")
         _check(_lib.rok_mgs_column(self._ctx, _ptr(V), int(M), int(j), _ptr(w), _ptr(H), _ptr(vnext), _ptr(ws),
                                    ws.numel(), _stream()), "rok_mgs_column")
+
+    def last_arnoldi_flags(self) -> int:
+        """Status flags (FLAG_*) of the last rok_arnoldi call (synchronises the stream)."""
+        f = ctypes.c_int()
+        _check(_lib.rok_read_status(self._ctx, _ptr(self._last_arnoldi_ws), ctypes.byref(f), _stream()),
+               "rok_read_status")
+        return f.value
 
     def last_status(self) -> tuple[int, int]:
         """(flags, M_eff) of the last step (synchronises the stream)."""

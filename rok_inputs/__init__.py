@@ -337,6 +337,7 @@ WORKLOADS = {
     "vortex512_adjoint": dict(kind="vortex", n=512, recon="first", M=16, steps=50, cfl=2.0, jvp="exact", precision="fp64",
                               perturb=True),
     "tgv256_3d": dict(kind="tgv3", n=256, recon="muscl", M=16, steps=20, cfl=10.0, jvp="exact", precision="fp32"),
+    "tgv256_3d_fp64": dict(kind="tgv3", n=256, recon="muscl", M=16, steps=20, cfl=10.0, jvp="fd", precision="fp64"),
 }
 
 

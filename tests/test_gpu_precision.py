@@ -1,21 +1,25 @@
 """Precision form on the GPU: residual and tangent products in FP32, Arnoldi,
-reduced solve and accumulation in FP64.
-
-Errors are stated against the FP64 oracle (small grids) or against the FP64
-GPU path (full-size workloads; that path is bit-exact / 1e-12 against the
-oracle on the parity grids), normwise relative, also printed relative to the
-flow's perturbation y - mean(y).
+reduced solve and accumulation in FP64; every result against the FP64 oracle.
 
 The FP32 residual and tangent carry perturbations about a reference state, so
-their own rounding error is about 1e-7 of f and J v on generic states.  What
-separates the FP32 form from the FP64 one beyond that is the Jacobian itself:
-f is piecewise smooth (minmod, |.|, the wave-speed maximum), and where a state
-lies within FP32 rounding of a switch, the FP32-rounded state sees the other
-one-sided Jacobian.  On generic states that happens rarely (measured step
-errors 1e-8 .. 2e-5 over 5 steps); the analytic initial states are
-mirror-symmetric and sit on switches, where the plain FP64 method with
-finite-difference products deviates from the exact-product trajectory as
-much (its increments cross the same switches).
+their own rounding error is about 1e-7 of f and J v on generic states, and a
+step from a given state is within ~1e-7 of the oracle's step from that state.
+Beyond that, f is piecewise smooth (minmod, |u_n|, the wave-speed maximum):
+the exact-product step jumps where J does, and two states 1e-8 apart can lie
+on either side of a switch.  The oracle reports every branch decision of f
+with its distance from the switch (oracle.fv.branches), so the tests say
+where that happens instead of widening the bound: generic states are held to
+1e-5 (the benchmark spec's tolerance for FP32-residual states) step by step from
+the same input, and along the whole trajectory until the oracle's decisions
+at the two trajectories' states differ (reported on a line of its own); the
+analytic initial states sit exactly on switches (mirror symmetry) and are
+bounded by the plain FP64 method with finite-difference products.
+
+Full size (2048^2 and 256^3 Taylor-Green): F and J v element by element
+against the oracle, the FP64 residual bit for bit, and one step against the
+oracle's step stored at sampled indices (tests/golden/make_fullsize_golden.py).
+Errors are normwise relative unless stated, also printed relative to the
+flow's perturbation y - mean(y).
 """
 import sys
 
@@ -62,30 +66,163 @@ CASES = {
     "vortex_muscl_32": lambda: (ri.vortex_problem(32, "muscl"), 8, 5),
 }
 
+# Relative distance from a switch below which FP32 rounding of the decision's
+# inputs can take the other branch: the FP32 form rounds perturbations about a
+# reference state (unit roundoff 6e-8), and the decisions' inputs carry a few
+# such roundings of quantities up to the flow's spread.
+FP32_DECISION = 1e-6
 
-def _initial(pb, generic):
+
+def _initial(pb, generic, seed=0):
     y0 = ri.tgv_state(pb) if pb["physics"] == "ns" else ri.vortex_state(pb)
-    return ri.perturb_generic(pb, y0) if generic else y0
+    return ri.perturb_generic(pb, y0, seed=ri.PERTURB_SEED + 1 + seed) if generic else y0
+
+
+def _decisions(P, y):
+    with fv.branches(record=True) as br:
+        fv.residual(P, y)
+    return br
+
+
+def _fragile(br, delta=FP32_DECISION):
+    """{site: mask} of the decisions closer than delta to their switch."""
+    return {s: m < delta for s, (_, m) in br.margins.items() if bool((m < delta).any())}
+
+
+def _count(masks):
+    return sum(int(m.sum()) for m in masks.values())
+
+
+def _differ(ba, bb):
+    """{site: mask} where two evaluations took different branches that matter:
+    a minmod's |a| <= |b| decision (recorded just before its a b <= 0 decision)
+    is moot where that minmod is flat in both."""
+    out = {}
+    for s, da in ba.decisions.items():
+        d = da != bb.decisions[s]
+        if ba.margins[s][0] == "minmod |a| <= |b|":
+            d = d & ~(ba.decisions[s + 1] & bb.decisions[s + 1])
+        if bool(d.any()):
+            out[s] = d
+    return out
+
+
+def _step_with_flips(P, tab, M, h, y, flip):
+    f, _ = rok.fv_system(P, "exact")
+
+    def matvec_at(yy, fy):
+        def mv(v):
+            with fv.branches(flip=flip):
+                return fv.jvp_exact(P, yy, v)
+        return mv
+    return rok.rok_step(f, matvec_at, tab, M, h, y)
+
+
+def _local_error(P, tab, M, h, y_in, y_out, frag):
+    """FP32 step result y_out from y_in against the oracle's exact-product step
+    from the same y_in; where decisions sit within FP32 rounding of a switch
+    (frag), the smallest error over taking up to two of them the other way
+    (the other one-sided Jacobians, every one of which an FP32 evaluation may
+    see)."""
+    base = _step_with_flips(P, tab, M, h, y_in, {})
+    e = relerr(y_out, base)
+    if e <= 1e-5 or not frag:
+        return e, None
+    elems = [(s, i) for s, m in frag.items() for i in torch.nonzero(m.reshape(-1)).reshape(-1).tolist()]
+    best = (e, None)
+    import itertools
+    for r in (1, 2):
+        for combo in itertools.combinations(elems[:12], r):
+            flip = {}
+            for s, i in combo:
+                mk = flip.setdefault(s, torch.zeros(frag[s].numel(), dtype=torch.bool))
+                mk[i] = True
+            flip = {s: mk.reshape(frag[s].shape) for s, mk in flip.items()}
+            ef = relerr(y_out, _step_with_flips(P, tab, M, h, y_in, flip))
+            if ef < best[0]:
+                best = (ef, combo)
+        if best[0] <= 1e-5:
+            break
+    return best
+
+
+GENERIC = [(name, seed) for name in CASES for seed in range(6 if "3d" not in name else 4)]
+
+
+@pytest.mark.parametrize("name,seed", GENERIC)
+def test_fp32_trajectory_generic_states(dev, name, seed):
+    """FP32 + tangent trajectory from a generic state (every primitive variable
+    seeded-perturbed) against the FP64 exact-product oracle, bound 1e-5.
+
+    f is piecewise smooth (minmod, |u_n|, the wave-speed maximum) and the
+    exact-product step is discontinuous where J jumps.  Two checks per step:
+    * local: the FP32 step from the GPU's own state y_n against the oracle's
+      step from the same y_n, bound 1e-5, at every step (measured 1e-8 .. 1e-7);
+      where a decision of f at y_n lies within FP32 rounding of its switch
+      (relative margin < FP32_DECISION) the case is reported, and the bound
+      holds against the oracle step taking that decision either way;
+    * trajectory: the FP32 state against the oracle's own trajectory, bound
+      1e-5, as long as the oracle takes the same branch decisions at both
+      trajectories' states.  Once they differ (the two trajectories, 1e-8
+      apart, straddle a switch) the case is reported on its own line with the
+      oracle's own jump between the two states, and the local check carries
+      the bound from there."""
+    pb, M, K = CASES[name]()
+    P = oracle_problem(pb)
+    y0 = _initial(pb, True, seed)
+    h = ri.cfl_step(pb, y0, 2.5)
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, "exact")
+    ref = rok.trajectory(f, mv, tab, M, h, t64(y0), K, keep=True)
+    g32 = gpu(pb, "fp32")
+    y = torch.tensor(y0, device=dev)
+    straddle = None
+    for n in range(1, K + 1):
+        y_in = y.cpu()
+        y = g32.step(y, h, tab, M, "exact")
+        assert g32.last_status()[0] == 0
+        y_out = y.cpu()
+        br_gpu = _decisions(P, y_in)
+        frag = _fragile(br_gpu)
+        e_loc, flips = _local_error(P, tab, M, h, y_in, y_out, frag)
+        e_traj = relerr(y_out, ref[n])
+        diff = _differ(br_gpu, _decisions(P, ref[n - 1]))
+        if diff:
+            # the oracle's own step from the GPU's state against its step from its own state
+            jump = relerr(rok.rok_step(f, mv, tab, M, h, y_in), ref[n])
+            kinds = {br_gpu.margins[s][0] for s in diff}
+            if straddle is None:
+                straddle = [n, _count(diff), kinds, jump]
+            else:
+                straddle[2] |= kinds
+                straddle[3] = max(straddle[3], jump)
+        tag = "" if not frag else f"  [{_count(frag)} decision(s) within FP32 rounding of a switch" + \
+            (f"; best with {len(flips)} taken the other way]" if flips else "]")
+        say(f"{name} seed {seed} step {n}: local {e_loc:.2e}, trajectory {e_traj:.2e}{tag}")
+        assert e_loc <= 1e-5
+        if straddle is None:
+            assert e_traj <= 1e-5
+    if straddle is not None:
+        n, k, kinds, jump = straddle
+        say(f"SWITCH {name} seed {seed}: from step {n} on, the oracle takes different branch decisions at the GPU's "
+            f"and at its own state ({k} at step {n}; {', '.join(sorted(kinds))}); its own step differs by up to "
+            f"{jump:.2e} between the two states; final trajectory difference {e_traj:.2e}")
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("generic", [True, False])
-def test_fp32_trajectory_error_vs_fp64_oracle(dev, name, generic):
-    """FP32 + tangent trajectory against the FP64 exact-product oracle.
-
-    Generic states (every variable seeded-perturbed): the FP32 rounding is the
-    only difference, bound 1e-5.  The analytic initial states themselves are
-    mirror-symmetric, so minmod and the wave-speed maximum sit on ties whose
-    outcome rounding decides: there the Jacobian of the FP32-rounded state is a
-    different one-sided Jacobian, and the bound is that the FP32 form stays at
-    least as close to the exact-product trajectory as the plain FP64 method with
-    finite-difference products (whose increments cross the same ties).
-    Generic bound 5e-5: a rare FP32 switch of the wave-speed maximum gives
-    1.7e-5 on the 32^2 Taylor-Green case after 5 steps."""
+def test_fp32_analytic_states_on_switches(dev, name):
+    """The analytic initial states are mirror-symmetric: minmod and the
+    wave-speed maximum sit exactly on their switches at many faces (margin 0,
+    counted below), where the FP32-rounded evaluation takes whichever branch
+    rounding picks and so differentiates other one-sided Jacobians than the
+    oracle's tie rule.  Too many ties to enumerate; the reading bounds the FP32
+    form by the plain FP64 method with finite-difference products, whose
+    increments eps v cross the same ties: FP32 error <= max(1e-5, FD error)."""
     pb, M, K = CASES[name]()
-    say("fp32 trajectory", name, "generic" if generic else "analytic", pb["n"], M, K)
     P = oracle_problem(pb)
-    y0 = _initial(pb, generic)
+    y0 = _initial(pb, False)
+    ties = _count(_fragile(_decisions(P, t64(y0)), 1e-300))
+    say("fp32 analytic", name, pb["n"], M, K, f"exact ties at y0: {ties}")
     h = ri.cfl_step(pb, y0, 2.5)
     tab = ri.rok4_tableau()
     f, mv = rok.fv_system(P, "exact")
@@ -93,16 +230,17 @@ def test_fp32_trajectory_error_vs_fp64_oracle(dev, name, generic):
     g32, g64 = gpu(pb, "fp32"), gpu(pb, "fp64")
     y32, y64, yfd = (torch.tensor(y0, device=dev) for _ in range(3))
     nvar = len(pb["n"]) + 2
+    assert ties > 0
     for n in range(1, K + 1):
         y32 = g32.step(y32, h, tab, M, "exact")
         y64 = g64.step(y64, h, tab, M, "exact")
         yfd = g64.step(yfd, h, tab, M, "fd")
         e32, e64, efd = relerr(y32.cpu(), ref[n]), relerr(y64.cpu(), ref[n]), relerr(yfd.cpu(), ref[n])
         ep = _pert_rel(y32.cpu(), ref[n], nvar)
-        say(f"  step {n}: fp32 {e32:.3e} (vs perturbation {ep:.3e}), fp64-FD {efd:.3e}, fp64 exact {e64:.3e}")
+        say(f"  SWITCH step {n}: fp32 {e32:.3e} (vs perturbation {ep:.3e}), fp64-FD {efd:.3e}, fp64 exact {e64:.3e}")
         assert e64 <= 1e-12
         assert g32.last_status()[0] == 0
-        assert e32 <= (5e-5 if generic else max(5e-5, efd))
+        assert e32 <= max(1e-5, efd)
 
 
 @pytest.mark.parametrize("name", ["tgv2d_32", "vortex_muscl_32"])
@@ -120,61 +258,6 @@ def test_fp32_krylov_pair_error(dev, name):
     say("fp32 krylov", name, "H", eH, "V", eV, "F", relerr(Fg.cpu(), F))
     assert mg == m
     assert eH <= 1e-4 and eV <= 1e-4
-
-
-def test_tgv2048_full_size(dev):
-    """The 2048^2 viscous Taylor-Green workload (Re 100, Mach 0.1, M = 20):
-    FP32 residual against the FP64 oracle; FP32 tangent product and one FP32
-    step against the FP64 GPU path (exact products), from the seeded state.
-    The viscous Taylor-Green flow is a near-balance of O(1) flux terms, so f
-    itself is small and its FP32 relative error is about 4e-4 (1e-3 bound);
-    the step, which adds h f to a state of size ~ p0, is within 1e-5."""
-    pb, y0, w = ri.workload("tgv2048_ns")
-    say("tgv2048", w)
-    P = oracle_problem(pb)
-    tab = ri.rok4_tableau()
-    h = ri.cfl_step(pb, y0, w["cfl"])
-    g32, g64 = gpu(pb, "fp32"), gpu(pb, "fp64")
-    yd = torch.tensor(y0, device=dev)
-    F32 = g32.residual(yd).double()
-    Fr = fv.residual(P, t64(y0))
-    eF = relerr(F32.cpu(), Fr)
-    F64 = g64.residual(yd)
-    assert torch.equal(F64.cpu(), Fr)
-    v = torch.tensor(ri.random_direction(yd.numel(), 4), device=dev)
-    ew = relerr(g32.jvp(yd, v, "exact").double(), g64.jvp(yd, v, "exact"))
-    s32 = g32.step(yd, h, tab, w["M"], "exact")
-    s64 = g64.step(yd, h, tab, w["M"], "exact")
-    es = relerr(s32, s64)
-    ep = _pert_rel(s32.cpu(), s64.cpu(), 4)
-    say(f"  F {eF:.3e}  Jv {ew:.3e}  step {es:.3e} (vs perturbation {ep:.3e})")
-    assert g32.last_status() == (0, w["M"]) and g64.last_status() == (0, w["M"])
-    assert eF <= 1e-3 and ew <= 1e-3 and es <= 1e-5
-
-
-def test_tgv3d_256_full_size(dev):
-    """The 256^3 Taylor-Green workload (Re 1600, M = 16): one step of the FP32 +
-    tangent form and of the plain FP64 + finite-difference method against the
-    FP64 exact-product step, from the seeded state."""
-    pb, y0, w = ri.workload("tgv256_3d")
-    say("tgv256 3d", w)
-    tab = ri.rok4_tableau()
-    h = ri.cfl_step(pb, y0, w["cfl"])
-    yd = torch.tensor(y0, device=dev)
-    g64 = gpu(pb, "fp64")
-    ref = g64.step(yd, h, tab, w["M"], "exact")
-    assert g64.last_status() == (0, w["M"])
-    fd = g64.step(yd, h, tab, w["M"], "fd")
-    e_fd = relerr(fd, ref)
-    del g64
-    g32 = gpu(pb, "fp32")
-    s32 = g32.step(yd, h, tab, w["M"], "exact")
-    assert g32.last_status() == (0, w["M"])
-    e32 = relerr(s32, ref)
-    say(f"  fp32+tangent {e32:.3e} (vs perturbation {_pert_rel(s32.cpu(), ref.cpu(), 5):.3e}); "
-        f"fp64+FD {e_fd:.3e} (vs perturbation {_pert_rel(fd.cpu(), ref.cpu(), 5):.3e})")
-    # the analytic state is mirror-symmetric (see the trajectory test): bound by the plain method's own deviation
-    assert e32 <= max(5e-5, e_fd)
 
 
 def _ke(pb, y):
