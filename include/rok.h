@@ -246,6 +246,23 @@ rok_status rok_jvp(rok_ctx* ctx, const double* y, const double* fy, const double
                    int mode, double eps, void* work, size_t work_bytes, void* stream);
 
 /*
+ * rok_jvp for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same product with the same arguments and
+ * results, bit for bit, without `work`.  The default finite-difference
+ * increment (mode ROK_JVP_FD, eps <= 0) needs two grid-wide norms; their
+ * reduction partials live in a library-owned device array of 64 KiB, one per
+ * device, held until the process ends (its need does not grow with N; a
+ * layout that outgrew it would return ROK_EINVAL).  The call uses the array
+ * of the current device, so `stream` must belong to the current device.  It
+ * allocates nothing and clears what it needs with a kernel (no memset).
+ * Calls that overlap in time on one device share that array and race: order
+ * them on one stream or synchronise between them.
+ */
+rok_status rok_jvp_noalloc(rok_ctx* ctx, const double* y, const double* fy, const double* v, void* w, int mode,
+                           double eps, void* stream);
+
+/*
  * Modified Arnoldi (Sec. 2.2.2): orthonormal basis V of K_M(J(y), fy) and
  * H = V^T J V (upper Hessenberg).
  *   y, fy:  N doubles (fy = f(y) as a double vector)

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -358,7 +359,7 @@ rok_status rok_residual_split(rok_ctx* c, const double* y, void* F_inv, void* F_
 
 namespace {
 
-// Validation of rok_jvp's arguments.
+// Validation shared by rok_jvp and rok_jvp_noalloc.
 rok_status jvp_args_ok(const rok_ctx* c, const double* y, const double* fy, const double* v, const void* w,
                        int mode) {
     if (!c || !y || !v || !w || !aligned(y, 8) || !aligned(v, 8) || !aligned(w, fp32(c) ? 4 : 8)) return ROK_EINVAL;
@@ -409,6 +410,54 @@ rok_status rok_jvp(rok_ctx* c, const double* y, const double* fy, const double* 
     return ROK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free rok_jvp.  The default finite-difference increment needs two
+// grid-wide norms, whose reduction partials, header and scalars live in a
+// caller workspace in rok_jvp; rok_jvp_noalloc keeps them in `scratch`, a
+// file-scope device array of fixed size (every device the library runs on
+// holds one copy until the process ends).  In host code `scratch` names a
+// host-side stand-in, so its device address is looked up once per device,
+// with that device current, and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kJvpScratchBytes = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[kJvpScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];   // device address of `scratch` per device (null until looked up)
+
+// The current device's copy of `scratch` (looked up on its first use on that device).
+hipError_t current_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+rok_status rok_jvp_noalloc(rok_ctx* c, const double* y, const double* fy, const double* v, void* w, int mode,
+                           double eps, void* stream) {
+    rok_status r = jvp_args_ok(c, y, fy, v, w, mode);
+    if (r != ROK_OK) return r;
+    void* base = nullptr;
+    if (mode == ROK_JVP_FD && !(eps > 0.0)) {
+        if (rok::work_small_bytes(0, 0) > kJvpScratchBytes) return ROK_EINVAL;
+        ROK_TRY(current_scratch(&base));
+    }
+    ROK_TRY(jvp_launch(c, y, fy, v, w, mode, eps, base, (hipStream_t)stream));
+    return ROK_OK;
+}
 
 rok_status rok_arnoldi(rok_ctx* c, const double* y, const double* fy, int M, int mode, double eps, double* V,
                        double* H, int* M_eff, void* work, size_t wbytes, void* stream) {

@@ -25,7 +25,7 @@ FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER, FLAG_NONPHYSICAL = 
 MAX_STAGES, MAX_M = 8, 64
 
 SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
-           "rok_jvp", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
+           "rok_jvp", "rok_jvp_noalloc", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
            "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
            "rok_eigs", "rok_eigs_workspace_bytes", "rok_set_grid", "rok_grid_metric_bytes", "rok_set_ogrid",
            "rok_ogrid_metric_bytes", "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     lib.rok_residual_split.restype = i
     lib.rok_jvp.argtypes = [vp, vp, vp, vp, vp, i, d, vp, sz, vp]
     lib.rok_jvp.restype = i
+    lib.rok_jvp_noalloc.argtypes = [vp, vp, vp, vp, vp, i, d, vp]
+    lib.rok_jvp_noalloc.restype = i
     lib.rok_arnoldi.argtypes = [vp, vp, vp, i, i, d, vp, vp, vp, vp, sz, vp]
     lib.rok_arnoldi.restype = i
     lib.rok_step.argtypes = [vp, ctypes.POINTER(RokTableau), i, i, d, vp, vp, vp, sz, vp]
@@ -267,6 +269,21 @@ class Rok:
         ws = self.workspace(0, 0)
         _check(_lib.rok_jvp(self._ctx, _ptr(y), _ptr(fy), _ptr(v), _ptr(w), m, float(eps), _ptr(ws), ws.numel(),
                             _stream()), "rok_jvp")
+        return w
+
+    def jvp_noalloc(self, y, v, mode: str = "fd", fy=None, eps: float = 0.0, out=None) -> torch.Tensor:
+        """rok_jvp_noalloc: the product of `jvp` without a workspace (the library's
+        own per-device scratch array holds the reductions of the default FD increment)."""
+        self._vec(y, "y")
+        self._vec(v, "v")
+        m = JVP_FD if mode == "fd" else JVP_TANGENT
+        if m == JVP_FD:
+            if fy is None:
+                raise ValueError("the finite-difference product needs fy = f(y)")
+            self._vec(fy, "fy")
+        w = out if out is not None else torch.empty(self.N, dtype=self._out_dtype(), device=y.device)
+        _check(_lib.rok_jvp_noalloc(self._ctx, _ptr(y), _ptr(fy), _ptr(v), _ptr(w), m, float(eps), _stream()),
+               "rok_jvp_noalloc")
         return w
 
     def arnoldi(self, y, fy, M: int, mode: str = "fd", eps: float = 0.0):
