@@ -154,6 +154,8 @@ class branches:
         self.flip = dict(flip or {})
         self.margins = {}
         self.decisions = {}
+        self.axes = {}      # site -> direction d of the faces it decides (element c: the face c + 1/2)
+        self.axis = None
         self._site = 0
         self._prev = None
 
@@ -183,6 +185,7 @@ def _decide(cond, kind, margin):
     if ctx.record:
         ctx.margins[site] = (kind, margin())
         ctx.decisions[site] = out.clone()
+        ctx.axes[site] = ctx.axis
     return out
 
 
@@ -683,6 +686,8 @@ def residual(P: Problem, y: torch.Tensor, part: str = "all", terms: list | None 
     r, vel, p = primitives(P, U)
     out = None
     for d in range(P.ndim):
+        if _BRANCHES is not None:
+            _BRANCHES.axis = d
         (UL, rL, vL, pL), (UR, rR, vR, pR) = _face_states(P, U, r, vel, p, d)
         if part == "viscous":
             Fh = [torch.zeros_like(r) for _ in range(P.nvar)]
@@ -699,6 +704,20 @@ def residual(P: Problem, y: torch.Tensor, part: str = "all", terms: list | None 
             terms.append(term.reshape(-1))
         out = term if out is None else out + term
     return out.reshape(-1)
+
+
+def cells_near_switches(P: Problem, y: torch.Tensor, delta: float) -> torch.Tensor:
+    """Cells (a boolean tensor of the grid's shape) whose value of f contains a
+    face flux with a branch decision closer than delta to its switch: both
+    cells c and c + 1 of such a face c + 1/2 (Cartesian grids)."""
+    with branches(record=True) as br:
+        residual(P, y)
+    mask = torch.zeros(P.shape[1:], dtype=torch.bool)
+    for site, (_, m) in br.margins.items():
+        near = m < delta
+        if bool(near.any()):
+            mask |= near | _at(near, -1, br.axes[site])
+    return mask
 
 
 def residual_terms(P: Problem, y: torch.Tensor) -> torch.Tensor:

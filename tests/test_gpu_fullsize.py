@@ -1,0 +1,238 @@
+"""The workloads at their full sizes against the oracle (through the C-ABI).
+
+* 2048^2 and 256^3 viscous Taylor-Green: the FP64 residual bit for bit and the
+  FP64 exact product to 1e-12, element by element against oracle/fv.py; the
+  FP32 residual and tangent product against the same oracle values;
+* one ROK step at full size against the oracle's step, which takes the oracle
+  minutes to a quarter of an hour and is therefore stored at 8192 seeded
+  sample indices plus each variable's sum and sum of squares over the whole
+  vector (tests/golden/make_fullsize_golden.py, which calls only the oracle):
+  the plain FP64 method with FD products at 256^3 (the benchmark's
+  configuration) and on the density-perturbed 1024^2 vortex bit for bit at
+  the samples; FP64 exact products to 1e-12 and the FP32 form to 1e-5 on
+  generic states at 2048^2 and 256^3.
+
+FP32 readings (normwise relative errors, printed):
+* on generic states (every primitive variable seeded-perturbed) F is within
+  1e-5 of the oracle; so is J v away from the cells whose value contains a
+  face with a branch decision of f within FP32 rounding of its switch
+  (relative margin < 1e-6; oracle.fv.cells_near_switches): there the FP32
+  evaluation differentiates whichever one-sided branch rounding picks (at
+  full size, with a seeded perturbation in every cell, a few per cent of the
+  cells); those cells are counted and their error printed;
+* at the analytic (mirror-symmetric) Taylor-Green state f is a near-balance:
+  its per-direction flux differences cancel to a small fraction of their size
+  (kappa = ||sum_d |term_d| || / ||f||, printed), and FP32 rounding is relative
+  to those terms, so the bound is 64 u32 kappa (u32 = 2^-24);
+* the analytic state also sits exactly on switches of minmod and the
+  wave-speed maximum (counted), where the FP32 tangent differentiates whichever
+  one-sided branch rounding picks: it is bounded by the FP64 finite-difference
+  product's own deviation from the exact one there.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import rok_inputs as ri
+from oracle import fv
+from tests._util import oracle_problem, relerr, t64
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+U32 = 2.0 ** -24
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1607_06834_amd import load_library
+    load_library()
+    return torch.device("cuda", 0)
+
+
+def gpu(pb, precision="fp64"):
+    from paper_1607_06834_amd import Rok
+    return Rok(pb, precision)
+
+
+def _elementwise(a, b):
+    """max |a - b| / max |b|"""
+    return float((a - b).abs().max()) / max(float(b.abs().max()), 1e-300)
+
+
+WORKLOADS = ["tgv2048_ns", "tgv256_3d"]
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_fp64_residual_and_tangent_full_size(dev, name):
+    pb, y0, _ = ri.workload(name)
+    say("fp64 full size", name, pb["n"])
+    P = oracle_problem(pb)
+    y = t64(y0)
+    g = gpu(pb)
+    yd = y.to(dev)
+    F = fv.residual(P, y)
+    Fg = g.residual(yd).cpu()
+    say(f"  residual bitwise: {torch.equal(Fg, F)}")
+    assert torch.equal(Fg, F)
+    del F, Fg
+    v = torch.tensor(ri.random_direction(y.numel(), 4))
+    Jv = fv.jvp_exact(P, y, v)
+    Jg = g.jvp(yd, v.to(dev), "tangent").cpu()
+    e = relerr(Jg, Jv)
+    say(f"  tangent product {e:.2e} (element-wise {_elementwise(Jg, Jv):.2e})")
+    assert e <= 1e-12
+
+
+FP32_DECISION = 1e-6   # relative margin within which FP32 rounding can take a decision of f the other way
+
+
+def _split_by_switches(P, y, a, b):
+    """(error away from near-switch cells, error at them, number of such cells):
+    normwise, both relative to ||b|| over all cells."""
+    near = fv.cells_near_switches(P, y, FP32_DECISION).reshape(-1).repeat(P.nvar)
+    nb = float(b.norm())
+    d = a - b
+    return float(d[~near].norm()) / nb, float(d[near].norm()) / nb, int(near.sum()) // P.nvar
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_fp32_generic_state_full_size(dev, name):
+    """FP32 residual and tangent on the full-size generic state: 1e-5 (the
+    product away from near-switch cells)."""
+    pb, y0, _ = ri.workload(name)
+    P = oracle_problem(pb)
+    y = t64(ri.perturb_generic(pb, y0))
+    say("fp32 generic full size", name, pb["n"])
+    g = gpu(pb, "fp32")
+    yd = y.to(dev)
+    F = fv.residual(P, y)
+    Fg = g.residual(yd).double().cpu()
+    eF = relerr(Fg, F)
+    say(f"  F {eF:.2e} (element-wise {_elementwise(Fg, F):.2e})")
+    del F, Fg
+    v = torch.tensor(ri.random_direction(y.numel(), 4))
+    Jv = fv.jvp_exact(P, y, v)
+    Jg = g.jvp(yd, v.to(dev), "tangent").double().cpu()
+    eJ = relerr(Jg, Jv)
+    e_away, e_near, ncells = _split_by_switches(P, y, Jg, Jv)
+    say(f"  J v {eJ:.2e}: away from switches {e_away:.2e}; SWITCH at the {ncells} cells "
+        f"({ncells / P.ncell:.1%}) next to a decision within FP32 rounding of its switch {e_near:.2e}")
+    assert eF <= 1e-5 and e_away <= 1e-5
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_fp32_analytic_state_full_size(dev, name):
+    """FP32 residual and tangent at the seeded (analytic) state, bounded by the
+    readings of the module docstring: cancellation for F, the switches for J v."""
+    pb, y0, _ = ri.workload(name)
+    P = oracle_problem(pb)
+    y = t64(y0)
+    g32, g64 = gpu(pb, "fp32"), gpu(pb, "fp64")
+    yd = y.to(dev)
+    T = fv.residual_terms(P, y)
+    F = T.sum(0) if T.shape[0] == 2 else (T[0] + T[1]) + T[2]
+    kappa = float(T.abs().sum(0).norm()) / float(F.norm())
+    del T
+    Fg = g32.residual(yd).double().cpu()
+    eF = relerr(Fg, F)
+    with fv.branches(record=True) as br:
+        fv.residual(P, y)
+    ties = sum(int((m == 0).sum()) for _, m in br.margins.values())
+    del br
+    say(f"fp32 analytic full size {name}: F {eF:.2e}, cancellation kappa {kappa:.0f}, "
+        f"bound 64 u32 kappa = {64 * U32 * kappa:.2e}; exact ties of f's switches: {ties}")
+    assert eF <= 64 * U32 * kappa
+    del F, Fg
+    v = torch.tensor(ri.random_direction(y.numel(), 4))
+    Jv = fv.jvp_exact(P, y, v)
+    Jg = g32.jvp(yd, v.to(dev), "tangent").double().cpu()
+    eJ = relerr(Jg, Jv)
+    e_away, e_near, ncells = _split_by_switches(P, y, Jg, Jv)
+    F64 = g64.residual(yd)
+    Jfd = g64.jvp(yd, v.to(dev), "fd", fy=F64).cpu()
+    efd = relerr(Jfd, Jv)
+    say(f"  SWITCH J v: fp32 tangent {eJ:.2e} (away from the {ncells} near-switch cells {e_away:.2e}), "
+        f"fp64 FD product {efd:.2e}")
+    assert ties > 0
+    assert eJ <= max(1e-5, efd) and e_away <= 1e-5
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"fullsize_{name}.json")
+    if not os.path.exists(path):
+        pytest.fail(f"{path} is missing: run tests/golden/make_fullsize_golden.py {name}")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _case_input(name):
+    sys.path.insert(0, GOLDEN)
+    from make_fullsize_golden import case_input
+    return case_input(name)
+
+
+def _against_golden(gold, y1, nvar):
+    idx = torch.tensor(gold["index"], dtype=torch.long)
+    ref = torch.tensor(gold["y1"], dtype=torch.float64)
+    got = y1.cpu()[idx]
+    per = y1.reshape(nvar, -1)
+    sums = [float(per[v].sum()) for v in range(nvar)]
+    sumsq = [float((per[v] * per[v]).sum()) for v in range(nvar)]
+    n = y1.numel() // nvar
+    # a different summation order: compare the sums on the scale of sqrt(n sum of squares)
+    esum = max(abs(a - b) / max(1e-300, (n * c) ** 0.5) for a, b, c in zip(sums, gold["var_sum"], gold["var_sumsq"]))
+    esq = max(abs(a - b) / max(b, 1e-300) for a, b in zip(sumsq, gold["var_sumsq"]))
+    return got, ref, esum, esq
+
+
+@pytest.mark.parametrize("name", ["vortex1024_pert_fd", "tgv256_3d_fd"])
+def test_fd_step_full_size_vs_oracle(dev, name):
+    """The plain FP64 method (FD products) at full size, one step, in the
+    launch configuration the benchmark times: bit for bit at the samples."""
+    gold = _golden(name)
+    pb, y0, h, c = _case_input(name)
+    assert h == gold["h"]
+    say("fd step full size", name, pb["n"], c)
+    g = gpu(pb)
+    y1 = g.step(torch.tensor(y0, device=torch.device("cuda", 0)), h, ri.rok4_tableau(), c["M"], "fd")
+    flags, meff = g.last_status()
+    got, ref, esum, esq = _against_golden(gold, y1, len(pb["n"]) + 2)
+    say(f"  samples bitwise {torch.equal(got, ref)} ({relerr(got, ref):.2e}); variable sums {esum:.1e}, "
+        f"sums of squares {esq:.1e}; M_eff {meff}, flags {flags}")
+    assert meff == gold["M_eff"] and flags == 0
+    assert torch.equal(got, ref)
+    assert esum <= 1e-13 and esq <= 1e-13
+
+
+@pytest.mark.parametrize("name", ["tgv2048_exact_g", "tgv256_3d_exact_g"])
+def test_exact_step_full_size_vs_oracle(dev, name):
+    """One exact-product step on the full-size generic state: FP64 to 1e-12 and
+    the FP32 form to 1e-5 against the oracle's step (samples and sums)."""
+    gold = _golden(name)
+    pb, y0, h, c = _case_input(name)
+    assert h == gold["h"]
+    nvar = len(pb["n"]) + 2
+    yd = torch.tensor(y0, device=torch.device("cuda", 0))
+    say("exact step full size", name, pb["n"], c)
+    for prec, bound in (("fp64", 1e-12), ("fp32", 1e-5)):
+        g = gpu(pb, prec)
+        y1 = g.step(yd, h, ri.rok4_tableau(), c["M"], "exact")
+        flags, meff = g.last_status()
+        got, ref, esum, esq = _against_golden(gold, y1, nvar)
+        e = relerr(got, ref)
+        say(f"  {prec}: samples {e:.2e}, variable sums {esum:.1e}, sums of squares {esq:.1e}; M_eff {meff}")
+        assert meff == gold["M_eff"] and flags == 0
+        assert e <= bound and esq <= bound
+        del g, y1

@@ -102,3 +102,26 @@ def test_flip_gives_the_other_one_sided_product(var):
     e_plain = relerr(J_near, J_far)
     assert e_flip < 1e-6, (e_flip, e_plain)
     assert e_plain > 1e3 * max(e_flip, 1e-16)
+
+
+def test_cells_near_switches():
+    """The mask holds exactly the two cells of each face with a near-switch
+    decision: a uniform flow (every slope 0 and every face's two wave speeds
+    equal) is near a switch everywhere; a slope put 1e-9 of the spread from its
+    sign switch marks the cells of the faces whose reconstruction uses it."""
+    pb = ri.vortex_problem(8, "muscl")
+    P = oracle_problem(pb)
+    uni = t64(ri.uniform_state(pb, 1.0, [0.3, 0.2], 1.0))
+    assert bool(fv.cells_near_switches(P, uni, 1e-6).all())
+    pb, P, y = _setup(n=10)
+    far = fv.cells_near_switches(P, y, 1e-12)
+    n = pb["n"][0]
+    cell = 4 * n + 5
+    U = y.reshape(P.nvar, -1)
+    r, vel, p = fv.primitives(P, [U[m] for m in range(P.nvar)])
+    spread = float(r.max() - r.min())
+    y_near = _move_across(P, y, cell, 0, float(r[cell - 1]) + 1e-9 * spread - float(r[cell]))
+    m = fv.cells_near_switches(P, y_near, 1e-8) & ~far
+    # the slope r[cell] - r[cell-1] enters the x-faces (cell-2)+1/2 .. cell+1/2: cells cell-2 .. cell+1 of row 4
+    got = sorted(int(j) * n + int(i) for j, i in torch.nonzero(m).tolist())
+    assert set(got) <= {cell - 2, cell - 1, cell, cell + 1} and {cell - 1, cell} <= set(got)
