@@ -214,7 +214,7 @@ def _traffic(path, sources, key, field="hbm_bytes_per_launch"):
 
 
 def _mgs_roofline(args, g, y, M, mode, stream, ms_step):
-    """Dominant kernel of the step: the modified Gram-Schmidt pass (Arnoldi, a4).
+    """The Arnoldi columns (a4), as the step runs them.
 
     The basis of the step's Arnoldi process at y and the products w_j = J v_j
     are prepared first; the timed loop then runs the M columns j = 0..M-1 as
@@ -222,7 +222,12 @@ def _mgs_roofline(args, g, y, M, mode, stream, ms_step):
     * Resident path (N <= 4.19 M: one cooperative kernel per column, w held
       on chip): a launch is a column; algorithmic bytes of column j: w and
       v_0..v_j read, v_{j+1} written.
-    * Per-pass path (larger N: w streamed): column j runs j update passes
+    * One-reduce path (the default for larger N: w does not fit on chip):
+      a launch is a column of four kernels (dots against w and the Gram row,
+      the small solve, the update with the norm's partial sums, the
+      normalisation); algorithmic bytes as for the resident column, the
+      kernels themselves read the basis twice (`kernel_bytes_per_launch`).
+    * Per-pass path (modified Gram-Schmidt forced, larger N): column j runs j update passes
       (w <- w - h v_{i-1}, <v_i, w>), a first dot, a norm pass and the
       normalisation; the time of one update pass is the slope of the column
       time in j (least squares over j = 1..M-1), the per-launch average that
@@ -246,7 +251,7 @@ def _mgs_roofline(args, g, y, M, mode, stream, ms_step):
     ws = g.mgs_workspace(m)
     wk = torch.empty(N, dtype=torch.float64, device=y.device)
     vn = torch.empty(N, dtype=torch.float64, device=y.device)
-    resident = g.mgs_resident()
+    path = g.arnoldi_path(m)
 
     def column_timed(j, reps):
         # the copy that restores w (a column may overwrite it) is outside the events
@@ -275,12 +280,21 @@ def _mgs_roofline(args, g, y, M, mode, stream, ms_step):
                    f"reads and writes"}
     tpath = _traffic_path(args)
     traffic = None
-    if resident:
+    col_alg = sum((j + 2) * 8 * N + (8 * N if j + 1 < m else 0) for j in range(m)) / m
+    if path == "resident":
         ms = sum(col_ms) / m
-        alg = sum((j + 2) * 8 * N + (8 * N if j + 1 < m else 0) for j in range(m)) / m
+        alg = col_alg
         traffic = _traffic(tpath, MGS_SOURCES, "mgs_column")
         kernel = f"modified Gram-Schmidt Arnoldi column (k_mgs_resident), average over the {m} columns of a step"
         extra = {}
+    elif path == "one_reduce":
+        ms = sum(col_ms) / m
+        alg = col_alg
+        kb = sum((2 * j + 4) * 8 * N + (16 * N if j + 1 < m else 0) for j in range(m)) / m
+        kernel = (f"one-reduce Gram-Schmidt Arnoldi column (k_ls_dots, k_ls_solve, k_ls_update, k_normalize), "
+                  f"average over the {m} columns of a step")
+        extra = {"kernel_bytes_per_launch": int(kb),
+                 "timing": "one HIP event pair per column (its four launches)"}
     else:
         js = list(range(1, m))
         mj = sum(js) / len(js)
@@ -825,8 +839,29 @@ def secondary_leg(args):
     return {"value": round(1000.0 / res["ms_per_step"], 3), "unit": "steps/s", "ms_per_step": round(res["ms_per_step"], 4),
             "config": {"grid": "1024x1024", "physics": "euler", "recon": "muscl", "krylov_M": 16, "jvp": "fd",
                        "cfl": 10.0, "N": ri.size(pb)},
-            "flags": res["flags"], "roofline": res["roofline"], "arnoldi_step": res["arnoldi_step"],
+            "flags": res["flags"], "roofline": _dominant(res, w, tab), "arnoldi_step": res["arnoldi_step"],
             "roofline_jvp": res["roofline_jvp"], "roofline_residual": res["roofline_residual"]}
+
+
+def _dominant(res, w, tab):
+    """The roofline entry of the kernel that takes the most time per step: the
+    Arnoldi unit (per-pass kernel x passes, or the columns), the product kernel
+    (M launches) or the residual (s launches), by their live launch times."""
+    if not res.get("roofline"):
+        return None
+    M, s = w["M"], tab["s"]
+    cands = []
+    arn = res["roofline"]
+    if "slope" in arn.get("timing", ""):
+        cands.append((arn["avg_launch_ms"] * M * (M - 1) / 2, arn))
+    else:
+        cands.append((arn["avg_launch_ms"] * M, arn))
+    for key, count in (("roofline_jvp", M), ("roofline_residual", s)):
+        ent = res.get(key)
+        if ent:
+            cands.append((ent["avg_launch_ms"] * count, ent))
+    ms, ent = max(cands, key=lambda c: c[0])
+    return dict(ent, ms_per_step=round(ms, 3), share_of_step=round(ms / res["ms_per_step"], 4))
 
 
 def main():
@@ -842,6 +877,7 @@ def main():
     h = ri.cfl_step(pb, y0, w["cfl"])
     res = gpu_leg(args, pb, y0, w, tab, h)
     print(f"[bench] {args.workload}: {res['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    dominant = _dominant(res, w, tab)
     extra = not (args.no_secondary or args.roofline_only) and args.workload == "tgv256_3d_fp64"
     f32 = fp32_leg(args) if extra else None
     sec = secondary_leg(args) if extra else None
@@ -874,7 +910,8 @@ def main():
                                    "K full ROK steps, each from the seeded initial state (the per-step work does "
                                    "not depend on the state)")},
         "status": {"flags": res["flags"], "M_eff": res["M_eff"], "finite": res["finite"]},
-        "roofline": res.get("roofline"),
+        "roofline": dominant,
+        "roofline_arnoldi": res.get("roofline"),
         "arnoldi_step": res.get("arnoldi_step"),
         "roofline_jvp": res.get("roofline_jvp"),
         "roofline_residual": res.get("roofline_residual"),

@@ -71,8 +71,8 @@ enum {
                               /* p <= 0 (y_n, a stage state Y_i, or y_n + eps v_j) */
 };
 
-/* Implementation of the modified Gram-Schmidt passes (rok_set_mgs_path). */
-enum { ROK_MGS_AUTO = 0, ROK_MGS_PER_PASS = 1, ROK_MGS_RESIDENT = 2 };
+/* Orthogonalisation of the Arnoldi columns (rok_set_mgs_path). */
+enum { ROK_MGS_AUTO = 0, ROK_MGS_PER_PASS = 1, ROK_MGS_RESIDENT = 2, ROK_MGS_ONE_REDUCE = 3 };
 
 #define ROK_MAX_STAGES 8
 #define ROK_MAX_M 64
@@ -140,10 +140,31 @@ void rok_destroy(rok_ctx* ctx);
  * allow it.  Both produce bit-identical results.  The setting also selects
  * the reverse of the Arnoldi columns in rok_step_vjp: one resident kernel per
  * column for N up to 8 * 2^18 = 2097152 unless ROK_MGS_PER_PASS is set
- * (per-pass kernels otherwise; bit-identical as well).  Changes the context:
- * not to be called while other calls on the same context are being made.
- * ROK_EINVAL for an unknown path. */
+ * (per-pass kernels otherwise; bit-identical as well).
+ * ROK_MGS_ONE_REDUCE (M <= 24) computes the same coefficients from sums
+ * against the original work vector, h = (I + L)^{-1} V^T w with L the
+ * strictly lower part of V^T V (modified Gram-Schmidt's coefficients in
+ * exact arithmetic, written in its inverse compact WY form): two sweeps over
+ * the basis per column instead of one per pass, rounded differently (V, H and
+ * steps within 1e-12 of modified Gram-Schmidt; with finite-difference
+ * products the step is no longer the same bits, since the quotient divides
+ * the basis' last-bit differences by eps: see the library's tests for the
+ * measured level).  ROK_MGS_AUTO takes it when the resident kernel cannot
+ * hold the work vector (N above 4194304) and M <= 24; ROK_MGS_PER_PASS keeps
+ * modified Gram-Schmidt pass by pass there (the same bits as the resident
+ * kernel and the library's reference arithmetic).  The forward recomputed by
+ * rok_step_vjp always takes modified Gram-Schmidt (its reverse is that of
+ * modified Gram-Schmidt); rok_step_vjp_stored returns ROK_EUNSUPPORTED where
+ * rok_step would have taken the one-reduce form.
+ * Changes the context: not to be called while other calls on the same
+ * context are being made.  ROK_EINVAL for an unknown path. */
 rok_status rok_set_mgs_path(rok_ctx* ctx, int path);
+
+/* The orthogonalisation rok_arnoldi, rok_step and rok_mgs_column take on this
+ * context for Krylov dimension M (1..ROK_MAX_M): ROK_MGS_PER_PASS,
+ * ROK_MGS_RESIDENT or ROK_MGS_ONE_REDUCE; ROK_EUNSUPPORTED if the path set
+ * with rok_set_mgs_path is not available, ROK_EINVAL for a bad argument. */
+int rok_arnoldi_path(const rok_ctx* ctx, int M);
 
 /*
  * Curvilinear grids (2-D, n[0], n[1] >= 2): the box [lo, hi] becomes a periodic
@@ -286,8 +307,12 @@ rok_status rok_arnoldi(rok_ctx* ctx, const double* y, const double* fy, int M, i
  * against v_0..v_j by modified Gram-Schmidt, h_ij = <v_i, w>, w <- w - h_ij v_i
  * (i = 0..j, in order), then, when j + 1 < M, h_{j+1,j} = ||w|| and
  * v_{j+1} = w / h_{j+1,j} unless the breakdown test of rok_arnoldi holds.
- * Sums are taken in the library's fixed order, so a sequence of calls
- * j = 0..M-1 reproduces rok_arnoldi's V and H bit for bit.
+ * The column is orthogonalised the way rok_arnoldi does on this context
+ * (rok_arnoldi_path: pass by pass, resident, or the one-reduce form, which
+ * keeps the strictly lower Gram part of V^T V in the workspace from one
+ * column to the next).  Sums are taken in the library's fixed order, so a
+ * sequence of calls j = 0..M-1 on one workspace reproduces rok_arnoldi's V
+ * and H bit for bit.
  *   V:      N x M doubles, column c at V + c*N; columns 0..j are read
  *   M, j:   1 <= M <= min(ROK_MAX_M, N), 0 <= j < M
  *   w:      N doubles holding J v_j; its contents are undefined on return

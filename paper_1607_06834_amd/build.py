@@ -19,8 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librok.so")
 
-SOURCES = ["rok_residual.hip", "rok_krylov.hip", "rok_mgs.hip", "rok_adjoint.hip", "rok_step_adjoint.hip", "rok_eigs.hip",
-           "rok_api.hip"]
+SOURCES = ["rok_residual.hip", "rok_krylov.hip", "rok_mgs.hip", "rok_lowsync.hip", "rok_adjoint.hip",
+           "rok_step_adjoint.hip", "rok_eigs.hip", "rok_api.hip"]
 
 # -ffp-contract=off: no fused multiply-add contraction, so every formula keeps
 # the rounding of its written operation order (bit-reproducible FP64).

@@ -53,9 +53,10 @@ rok::ResArgs plain_args(const double* y, void* out) {
 // w = J(y) v into a double vector (internal use).  FD reads eps from eps_dev.
 hipError_t jvp_into(const rok_ctx* c, const double* y, const double* fy, const double* v, double* w, int mode,
                     const double* eps_dev, double eps, hipStream_t st, const int* gate = nullptr, int gate_col = 0,
-                    int* status = nullptr) {
+                    int* status = nullptr, const int* stop = nullptr) {
     rok::ResArgs A{};
     A.status = status;
+    A.stop = stop;
     A.gate = gate;
     A.gate_col = gate_col;
     A.y = y;
@@ -68,11 +69,35 @@ hipError_t jvp_into(const rok_ctx* c, const double* y, const double* fy, const d
     return rok::launch_residual(c->G, c->pb.recon, c->pb.physics == ROK_NS, fp32(c), kind, true, A, st);
 }
 
-// Modified Gram-Schmidt Arnoldi into V (N x M columns), H inside W.
+// How the Arnoldi columns are orthogonalised: modified Gram-Schmidt pass by
+// pass or with w resident on chip (the same bits), or the one-reduce form
+// (w too large for the chip; M <= 24).  `mgs_only`: a forward
+// that the step adjoint differentiates (the adjoint is that of modified
+// Gram-Schmidt).  -1: the requested path is not available.
+enum { ORTHO_PASS = 0, ORTHO_RESIDENT = 1, ORTHO_ONE_REDUCE = 2 };
+
+int pick_ortho(const rok_ctx* c, int M, bool mgs_only) {
+    const long N = c->G.N;
+    const bool resident_ok = rok::mgs_resident_per(N) > 0 && rok::mgs_resident_available();
+    if (mgs_only) return (c->mgs_path != ROK_MGS_PER_PASS && resident_ok) ? ORTHO_RESIDENT : ORTHO_PASS;
+    switch (c->mgs_path) {
+        case ROK_MGS_PER_PASS: return ORTHO_PASS;
+        case ROK_MGS_RESIDENT: return resident_ok ? ORTHO_RESIDENT : -1;
+        case ROK_MGS_ONE_REDUCE: return rok::lowsync_supported(M) ? ORTHO_ONE_REDUCE : -1;
+        default:
+            if (resident_ok) return ORTHO_RESIDENT;
+            if (rok::lowsync_supported(M)) return ORTHO_ONE_REDUCE;
+            return ORTHO_PASS;
+    }
+}
+
+// Arnoldi (Sec. 2.2.2) into V (N x M columns), H inside W.
 hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, const double* fy, int M, int mode,
-                        double eps, double* V, hipStream_t st) {
+                        double eps, double* V, hipStream_t st, bool mgs_only = false) {
     const long N = c->G.N;
     const double* epsp = nullptr;
+    const int ortho = pick_ortho(c, M, mgs_only);
+    if (ortho < 0) return hipErrorNotSupported;
     hipError_t e;
     if (mode == ROK_JVP_FD && !(eps > 0.0)) {
         e = rok::launch_norm_eps(W, y, nullptr, N, st);  // unit Arnoldi vectors: ||v_j|| = 1
@@ -81,15 +106,16 @@ hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, c
     }
     e = rok::launch_start_basis(W, fy, N, V, st);
     if (e != hipSuccess) return e;
-    bool resident = c->mgs_path != ROK_MGS_PER_PASS && rok::mgs_resident_per(N) > 0 && rok::mgs_resident_available();
-    if (c->mgs_path == ROK_MGS_RESIDENT && !resident) return hipErrorNotSupported;
     for (int j = 0; j < M; ++j) {
         double* vj = V + (long)j * N;
-        e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st, nullptr, 0, W.ints + 2);
+        // after a breakdown (stop word set) column j was never written: the product is skipped
+        e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st, nullptr, 0, W.ints + 2, W.ints + 1);
         if (e != hipSuccess) return e;
         double* vnext = (j + 1 < M) ? V + (long)(j + 1) * N : nullptr;
-        if (resident)
+        if (ortho == ORTHO_RESIDENT)
             e = rok::launch_mgs_resident(W, W.w, V, N, M, j, vnext, st);
+        else if (ortho == ORTHO_ONE_REDUCE)
+            e = rok::launch_ls_column(W, W.w, V, N, M, j, vnext, st);
         else
             e = rok::launch_mgs_column(W, W.w, V, N, M, j, vnext, st);
         if (e != hipSuccess) return e;
@@ -99,7 +125,7 @@ hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, c
 
 // The launch sequence of one ROK step into the carved workspace W.
 hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, double h, const double* y_n,
-                     double* y_np1, const rok::Work& W, hipStream_t st) {
+                     double* y_np1, const rok::Work& W, hipStream_t st, bool mgs_only = false) {
     const int s = tab->s;
     const long N = c->G.N;
     const bool ns = c->pb.physics == ROK_NS;
@@ -112,7 +138,7 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
         if (e != hipSuccess) return e;
     }
     if (M > 0) {
-        e = arnoldi_core(c, W, y_n, W.F, M, mode, 0.0, W.V, st);
+        e = arnoldi_core(c, W, y_n, W.F, M, mode, 0.0, W.V, st, mgs_only);
         if (e != hipSuccess) return e;
         e = rok::launch_lu(W, M, h * tab->gamma, st);
         if (e != hipSuccess) return e;
@@ -316,7 +342,9 @@ rok_status rok_set_ogrid(rok_ctx* c, const double* xn, const double* yn, const d
 }
 
 rok_status rok_set_mgs_path(rok_ctx* c, int path) {
-    if (!c || (path != ROK_MGS_AUTO && path != ROK_MGS_PER_PASS && path != ROK_MGS_RESIDENT)) return ROK_EINVAL;
+    if (!c || (path != ROK_MGS_AUTO && path != ROK_MGS_PER_PASS && path != ROK_MGS_RESIDENT &&
+               path != ROK_MGS_ONE_REDUCE))
+        return ROK_EINVAL;
     c->mgs_path = path;
     return ROK_OK;
 }
@@ -838,7 +866,7 @@ rok_status rok_step_vjp(rok_ctx* c, const rok_tableau* tab, int M, double h, con
     hipStream_t st = (hipStream_t)stream;
     rok::Work W = rok::carve(work, N, M, s, true);
     rok::AdjWork A = rok::adj_carve((char*)work + fwd, N, M, s);
-    ROK_TRY(step_core(c, tab, M, ROK_JVP_TANGENT, h, y_n, y_np1 ? y_np1 : A.Yt, W, st));
+    ROK_TRY(step_core(c, tab, M, ROK_JVP_TANGENT, h, y_n, y_np1 ? y_np1 : A.Yt, W, st, true));
     ROK_TRY(step_adjoint(c, tab, M, h, y_n, ybar_np1, ybar_n, W, A, st));
     return ROK_OK;
 }
@@ -864,6 +892,8 @@ rok_status rok_step_vjp_stored(rok_ctx* c, const rok_tableau* tab, int M, double
     const long N = c->G.N;
     if (!fwd_work || !aligned(fwd_work, 256) || fwd_bytes < rok::work_bytes(N, M, s, true)) return ROK_EINVAL;
     if (!adj_work || !aligned(adj_work, 256) || adj_bytes < rok::adj_bytes(N, M, s)) return ROK_EINVAL;
+    // the forward rok_step of this context orthogonalised its basis by the one-reduce form, whose reverse is not built
+    if (M > 0 && pick_ortho(c, M, false) == ORTHO_ONE_REDUCE) return ROK_EUNSUPPORTED;
     rok::Work W = rok::carve(fwd_work, N, M, s, true);
     rok::AdjWork A = rok::adj_carve(adj_work, N, M, s);
     ROK_TRY(step_adjoint(c, tab, M, h, y_n, ybar_np1, ybar_n, W, A, (hipStream_t)stream));
@@ -891,15 +921,27 @@ rok_status rok_mgs_column(rok_ctx* c, const double* V, int M, int j, double* w, 
     rok::Work W = rok::carve(work, N, M, 0, false);
     W.H = H;
     hipStream_t st = (hipStream_t)stream;
-    const bool resident =
-        c->mgs_path != ROK_MGS_PER_PASS && rok::mgs_resident_per(N) > 0 && rok::mgs_resident_available();
-    if (c->mgs_path == ROK_MGS_RESIDENT && !resident) return ROK_EUNSUPPORTED;
+    const int ortho = pick_ortho(c, M, false);   // the orthogonalisation rok_arnoldi takes
+    if (ortho < 0) return ROK_EUNSUPPORTED;
     double* vn = (j + 1 < M) ? vnext : nullptr;
-    if (resident)
+    if (ortho == ORTHO_RESIDENT)
         ROK_TRY(rok::launch_mgs_resident(W, w, V, N, M, j, vn, st));
+    else if (ortho == ORTHO_ONE_REDUCE)
+        ROK_TRY(rok::launch_ls_column(W, w, V, N, M, j, vn, st));
     else
         ROK_TRY(rok::launch_mgs_column(W, w, V, N, M, j, vn, st));
     return ROK_OK;
+}
+
+int rok_arnoldi_path(const rok_ctx* c, int M) {
+    if (!c || M < 1 || M > ROK_MAX_M) return ROK_EINVAL;
+    if ((long)M > c->G.N) M = (int)c->G.N;
+    switch (pick_ortho(c, M, false)) {
+        case ORTHO_PASS: return ROK_MGS_PER_PASS;
+        case ORTHO_RESIDENT: return ROK_MGS_RESIDENT;
+        case ORTHO_ONE_REDUCE: return ROK_MGS_ONE_REDUCE;
+        default: return ROK_EUNSUPPORTED;
+    }
 }
 
 rok_status rok_residual_vjp(rok_ctx* c, const double* y, const double* wbar, double* ybar, int accumulate,

@@ -59,6 +59,9 @@ struct ResArgs {
     // optional status word: ROK_FLAG_NONPHYSICAL is or-ed in when a staged
     // cell has rho <= 0 or p <= 0, ROK_FLAG_NONFINITE when an output is NaN or Inf
     int* status;
+    // optional: do nothing once *stop is set (a finished Arnoldi process: the
+    // basis column this product would read was never written)
+    const int* stop;
 };
 
 // ---------------------------------------------------------------------------

@@ -33,6 +33,7 @@ struct Work {
     double* phi;      // s x M
     double* lam;      // s x M
     int* perm;        // M
+    double* L;        // M x M: strictly lower Gram part of the one-reduce Gram-Schmidt (leading dimension M)
     double* partials; // npart x kRedBlocks reduction partials
     int npart;
     double* gpart;    // 2 x kRedBlocks partials exchanged inside the resident MGS kernel
@@ -62,6 +63,13 @@ hipError_t launch_error_norm(const Work& W, const double* y, const double* a, co
 hipError_t launch_start_basis(const Work& W, const double* f, long n, double* v0, hipStream_t st);
 hipError_t launch_mgs_column(const Work& W, double* w, const double* V, long n, int M, int j, double* vnext,
                              hipStream_t st);
+// v = w / ||w|| with ||w||^2 finished from `partials`, after the breakdown test of column j (H[j+1][j] = ||w||)
+hipError_t launch_normalize(const Work& W, const double* w, const double* partials, int M, int j, double* v, long n,
+                            hipStream_t st);
+// One-reduce Gram-Schmidt for one Arnoldi column (rok_lowsync.hip); M <= 24.
+bool lowsync_supported(int M);
+hipError_t launch_ls_column(const Work& W, const double* w, const double* V, long n, int M, int j, double* vnext,
+                            hipStream_t st);
 // Resident-w MGS for one column (rok_mgs.hip).
 int mgs_resident_per(long n);
 bool mgs_resident_available();

@@ -408,7 +408,21 @@ __global__ __launch_bounds__(256) void k_recover(const double* V, const double* 
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int npart(int M) { return (M > 0 ? M : 1) + 3; }  // projection columns + three MGS buffers
+// Partial columns: the projections (M) and three rotating MGS buffers, or the one-reduce Gram-Schmidt's
+// r and s columns (twice the compiled width of its widest column) and its norm column, whichever is more.
+static int npart(int M) {
+    const int Mm = M > 0 ? M : 1;
+    int ls = 0;
+    if (lowsync_supported(Mm)) {
+        static const int b[] = {1, 2, 4, 8, 12, 16, 20, 24};
+        for (int x : b)
+            if (Mm <= x) {
+                ls = 2 * x + 1;
+                break;
+            }
+    }
+    return Mm + 3 > ls ? Mm + 3 : ls;
+}
 
 size_t work_small_bytes(int M, int s) {
     int Mm = M > 0 ? M : 1;
@@ -419,6 +433,7 @@ size_t work_small_bytes(int M, int s) {
     b += al256(sizeof(double) * ss * Mm);                        // phi
     b += al256(sizeof(double) * ss * Mm);                        // lam
     b += al256(sizeof(int) * Mm);                                // perm
+    b += al256(sizeof(double) * Mm * Mm);                        // L
     b += al256(sizeof(double) * (size_t)npart(M) * kRedBlocks);  // partials
     b += al256(sizeof(double) * 2 * kRedBlocks);                 // gpart
     b += al256(sizeof(unsigned) * kBarWords);                    // barrier
@@ -446,6 +461,7 @@ Work carve(void* base, long N, int M, int s, bool step) {
     W.phi = (double*)p;      p += al256(sizeof(double) * ss * Mm);
     W.lam = (double*)p;      p += al256(sizeof(double) * ss * Mm);
     W.perm = (int*)p;        p += al256(sizeof(int) * Mm);
+    W.L = (double*)p;        p += al256(sizeof(double) * Mm * Mm);
     W.partials = (double*)p; p += al256(sizeof(double) * (size_t)npart(M) * kRedBlocks);
     W.npart = npart(M);
     W.gpart = (double*)p;    p += al256(sizeof(double) * 2 * kRedBlocks);
@@ -563,6 +579,13 @@ hipError_t launch_mgs_column(const Work& W, double* w, const double* V, long n, 
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedThreads), 0, st, mgs_part(W, j), (int)FIN_STORE,
                            W.H + (long)j * M + j, W.scal, W.ints, 0);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const Work& W, const double* w, const double* partials, int M, int j, double* v, long n,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, kRedThreads)), dim3(kRedThreads), 0, st, w, partials, W.H, M, j,
+                       v, n, W.ints, W.scal);
     return hipGetLastError();
 }
 

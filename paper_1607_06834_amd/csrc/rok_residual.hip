@@ -138,6 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     __shared__ S fb[NV][T::NFMAX];
 
     if (A.gate && A.gate_col + 1 < *A.gate) return;
+    if (A.stop && *A.stop) return;
     const int tid = threadIdx.x;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int x0 = (b % nt0) * TX;

@@ -24,12 +24,12 @@ JVP_FD, JVP_TANGENT = 0, 1
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_ZERO_RHS, FLAG_BARRIER, FLAG_NONPHYSICAL = 1, 2, 4, 8, 16
 MAX_STAGES, MAX_M = 8, 64
 
-SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
+SYMBOLS = ["rok_create", "rok_destroy", "rok_set_mgs_path", "rok_arnoldi_path", "rok_state_size", "rok_workspace_bytes", "rok_residual", "rok_residual_split",
            "rok_jvp", "rok_jvp_noalloc", "rok_arnoldi", "rok_step", "rok_residual_vjp", "rok_residual_vjp2", "rok_step_vjp",
            "rok_step_vjp_workspace_bytes", "rok_step_vjp_stored", "rok_step_vjp_adjoint_bytes", "rok_mgs_column",
            "rok_eigs", "rok_eigs_workspace_bytes", "rok_set_grid", "rok_grid_metric_bytes", "rok_set_ogrid",
            "rok_ogrid_metric_bytes", "rok_error_norm", "rok_integrate_adaptive", "rok_adaptive_workspace_bytes", "rok_workspace_init", "rok_read_status", "rok_read_meff", "rok_strerror"]
-MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2}
+MGS_PATHS = {"auto": 0, "pass": 1, "resident": 2, "one_reduce": 3}
 
 
 class RokProblem(ctypes.Structure):
@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH):
     lib.rok_destroy.restype = None
     lib.rok_set_mgs_path.argtypes = [vp, i]
     lib.rok_set_mgs_path.restype = i
+    lib.rok_arnoldi_path.argtypes = [vp, i]
+    lib.rok_arnoldi_path.restype = i
     lib.rok_state_size.argtypes = [vp]
     lib.rok_state_size.restype = sz
     lib.rok_workspace_bytes.argtypes = [vp, i, i]
@@ -477,10 +479,14 @@ class Rok:
         self._last_step_ws = rec.ws
         return yb
 
-    def mgs_resident(self) -> bool:
-        """Whether the Arnoldi columns run the resident kernel (the library's rule
-        for the default path: up to 16 elements per lane of its 2^18-lane grid)."""
-        return self.mgs != "pass" and self.N <= 16 * (1 << 18)
+    def arnoldi_path(self, M: int) -> str:
+        """How the Arnoldi columns are orthogonalised on this context for Krylov
+        dimension M (rok_arnoldi_path): "pass", "resident" or "one_reduce"."""
+        r = int(_lib.rok_arnoldi_path(self._ctx, int(M)))
+        names = {v: k for k, v in MGS_PATHS.items()}
+        if r not in names or r == 0:
+            raise RokError(f"rok_arnoldi_path: {r}")
+        return names[r]
 
     def mgs_workspace(self, M: int) -> torch.Tensor:
         """A workspace for column-level calls, prepared for Krylov dimension M."""

@@ -7,9 +7,10 @@
   minutes to a quarter of an hour and is therefore stored at 8192 seeded
   sample indices plus each variable's sum and sum of squares over the whole
   vector (tests/golden/make_fullsize_golden.py, which calls only the oracle):
-  the plain FP64 method with FD products at 256^3 (the benchmark's
-  configuration) and on the density-perturbed 1024^2 vortex bit for bit at
-  the samples; FP64 exact products to 1e-12 and the FP32 form to 1e-5 on
+  the plain FP64 method with FD products on the density-perturbed 1024^2
+  vortex bit for bit at the samples, and at 256^3 (the benchmark's
+  configuration) within 1e-12 with the one-reduce basis the automatic path
+  takes there and bit for bit pass by pass; FP64 exact products to 1e-12 and the FP32 form to 1e-5 on
   generic states at 2048^2 and 256^3.
 
 FP32 readings (normwise relative errors, printed):
@@ -61,9 +62,9 @@ def dev():
     return torch.device("cuda", 0)
 
 
-def gpu(pb, precision="fp64"):
+def gpu(pb, precision="fp64", mgs="auto"):
     from paper_1607_06834_amd import Rok
-    return Rok(pb, precision)
+    return Rok(pb, precision, mgs)
 
 
 def _elementwise(a, b):
@@ -197,22 +198,35 @@ def _against_golden(gold, y1, nvar):
     return got, ref, esum, esq
 
 
-@pytest.mark.parametrize("name", ["vortex1024_pert_fd", "tgv256_3d_fd"])
-def test_fd_step_full_size_vs_oracle(dev, name):
-    """The plain FP64 method (FD products) at full size, one step, in the
-    launch configuration the benchmark times: bit for bit at the samples."""
+@pytest.mark.parametrize("name,mgs", [("vortex1024_pert_fd", "auto"), ("tgv256_3d_fd", "auto"),
+                                      ("tgv256_3d_fd", "pass")])
+def test_fd_step_full_size_vs_oracle(dev, name, mgs):
+    """The plain FP64 method (FD products) at full size, one step.  In the
+    launch configuration the benchmark times ("auto"): at 1024^2 the resident
+    modified Gram-Schmidt, bit for bit at the samples; at 256^3 the one-reduce
+    form (the work vector does not fit on chip), within 1e-12 of the oracle's
+    state and 1e-10 of its increment y_1 - y_0 (the FD quotient divides the
+    basis' last-bit differences by eps).  Modified Gram-Schmidt pass by pass
+    at 256^3 ("pass"): bit for bit."""
     gold = _golden(name)
     pb, y0, h, c = _case_input(name)
     assert h == gold["h"]
-    say("fd step full size", name, pb["n"], c)
-    g = gpu(pb)
-    y1 = g.step(torch.tensor(y0, device=torch.device("cuda", 0)), h, ri.rok4_tableau(), c["M"], "fd")
+    say("fd step full size", name, pb["n"], c, mgs)
+    g = gpu(pb, mgs=mgs)
+    yd = torch.tensor(y0, device=torch.device("cuda", 0))
+    y1 = g.step(yd, h, ri.rok4_tableau(), c["M"], "fd")
     flags, meff = g.last_status()
     got, ref, esum, esq = _against_golden(gold, y1, len(pb["n"]) + 2)
-    say(f"  samples bitwise {torch.equal(got, ref)} ({relerr(got, ref):.2e}); variable sums {esum:.1e}, "
+    y0s = yd.cpu()[torch.tensor(gold["index"], dtype=torch.long)]
+    e, ei = relerr(got, ref), relerr(got - y0s, ref - y0s)
+    bitwise = torch.equal(got, ref)
+    say(f"  samples bitwise {bitwise} ({e:.2e}; increment {ei:.2e}); variable sums {esum:.1e}, "
         f"sums of squares {esq:.1e}; M_eff {meff}, flags {flags}")
     assert meff == gold["M_eff"] and flags == 0
-    assert torch.equal(got, ref)
+    if name == "tgv256_3d_fd" and mgs == "auto":
+        assert e <= 1e-12 and ei <= 1e-10
+    else:
+        assert bitwise
     assert esum <= 1e-13 and esq <= 1e-13
 
 
