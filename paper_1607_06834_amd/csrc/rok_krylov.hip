@@ -356,9 +356,10 @@ struct BRow {
 // last stage, which writes y_{n+1} = y + sum_i b_i k_i instead of k
 // (sum in stage order, terms with b_i = 0 skipped).
 template <int MB, bool FINAL>
-__global__ __launch_bounds__(256) void k_recover(const double* V, const double* F, long n, const int* ints,
-                                                const double* lam, const double* phi, double h, double* k,
-                                                const double* y, const double* K, int s, BRow br) {
+__global__ __launch_bounds__(256) void k_recover(const double* __restrict__ V, const double* __restrict__ F, long n,
+                                                const int* ints, const double* lam, const double* phi, double h,
+                                                double* __restrict__ k, const double* __restrict__ y,
+                                                const double* __restrict__ K, int s, BRow br) {
     const int m = ints[0];
     double lm[MB], ph[MB];
     if (m == MB) {

@@ -112,10 +112,13 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_solve(const double* partials
 }
 
 // Sweep B of column j: w' = w - h_0 q_0 - ... - h_j q_j into `out` (the next
-// basis column), partials of ||w'||^2 at `partials`.
+// basis column, distinct from V's columns 0..j and from w), partials of
+// ||w'||^2 at `partials`.  Two elements of a lane per iteration, both loaded
+// before either is stored (the lane's sum keeps index order).
 template <int MB>
-__global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* V, const double* w, const double* H, long n,
-                                                          int j, int M, double* out, const int* ints,
+__global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* __restrict__ V,
+                                                          const double* __restrict__ w, const double* H, long n,
+                                                          int j, int M, double* __restrict__ out, const int* ints,
                                                           double* partials) {
     __shared__ double s[kRedThreads];
     __shared__ double sh[MB];
@@ -127,14 +130,31 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* V, cons
     for (int c = 0; c < MB; ++c) h[c] = sh[c];
     double acc = 0.0;
     const long stride = (long)kRedBlocks * kRedThreads;
-    for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
-        double q[MB];
+    long e = (long)blockIdx.x * kRedThreads + threadIdx.x;
+    for (; e + stride < n; e += 2 * stride) {
+        double q0[MB], q1[MB];
 #pragma unroll
-        for (int c = 0; c < MB; ++c) q[c] = (c <= j) ? V[(long)c * n + e] : 0.0;
+        for (int c = 0; c < MB; ++c) {
+            q0[c] = (c <= j) ? V[(long)c * n + e] : 0.0;
+            q1[c] = (c <= j) ? V[(long)c * n + e + stride] : 0.0;
+        }
+        double x0 = w[e], x1 = w[e + stride];
+#pragma unroll
+        for (int c = 0; c < MB; ++c)
+            if (c <= j) {
+                x0 = x0 - h[c] * q0[c];
+                x1 = x1 - h[c] * q1[c];
+            }
+        out[e] = x0;
+        out[e + stride] = x1;
+        acc = acc + x0 * x0;
+        acc = acc + x1 * x1;
+    }
+    if (e < n) {
         double x = w[e];
 #pragma unroll
         for (int c = 0; c < MB; ++c)
-            if (c <= j) x = x - h[c] * q[c];
+            if (c <= j) x = x - h[c] * V[(long)c * n + e];
         out[e] = x;
         acc = acc + x * x;
     }

@@ -127,15 +127,35 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     constexpr int OFF_VEL = CONS ? NV : 1;
     constexpr int OFF_P = OFF_VEL + D;
     constexpr int OFF_T = OFF_P + 1;
-    constexpr int NP = OFF_P + 1 + (NSV ? 1 : 0);
     constexpr int CPT = T::CELLS / kThreads;
     static_assert(T::CELLS % kThreads == 0, "tile must be a multiple of the block size");
     using ST = Stage<D, TX, TY, TZ, T::H, NSV>;
     const auto& cells = kStageCells<D, TX, TY, TZ, T::H, NSV>;
+    // 3-D: only the box cells the stencil reads are staged, packed in the order
+    // of the staging list (s_slot maps a box cell to its slot), which keeps the
+    // LDS of a block small enough for three blocks per CU
+    constexpr bool PACKED = ST::LIST;
+    // the temperature p / rho is staged, except in packed FP64 boxes: there the
+    // two staged values of a face's cells are divided where it is needed (the
+    // same division of the same values: the same bits)
+    constexpr bool TSTAGED = NSV && (PERT || !PACKED);
+    constexpr int NP = OFF_P + 1 + (TSTAGED ? 1 : 0);
+    constexpr int NSLOT = PACKED ? ST::N : T::BOX;
     constexpr int kFaceUnroll = (D == 2 && sizeof(S) == 8 && !PERT && FLUX == 0) ? 2 : 1;
 
-    __shared__ S sq[NP][T::BOX];
+    __shared__ S sq[NP][NSLOT];
     __shared__ S fb[NV][T::NFMAX];
+    __shared__ unsigned short s_slot[PACKED ? T::BOX : 1];
+    // staged slot of box cell c (every cell the stencil reads is staged)
+    auto slot = [&](int c) -> int {
+        if constexpr (PACKED) return (int)s_slot[c];
+        else return c;
+    };
+    // temperature of the cell in slot q
+    auto temp = [&](int q) -> S {
+        if constexpr (TSTAGED) return sq[OFF_T][q];
+        else return sq[OFF_P][q] / sq[0][q];
+    };
 
     if (A.gate && A.gate_col + 1 < *A.gate) return;
     if (A.stop && *A.stop) return;
@@ -218,6 +238,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             const int i = tid + it * kThreads;
             if (it + 1 < NIT || i < ST::N) {
                 const int c = ST::LIST ? (int)cells.c[i] : i;
+                const int q = PACKED ? i : c;
+                if constexpr (PACKED) s_slot[c] = (unsigned short)i;
                 S* U = Ub[it];
                 const R gm1 = (R)G.gm1;
                 const R half = (R)0.5;
@@ -232,14 +254,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 np |= (Sc<S>::val(r) <= (R)0 || Sc<S>::val(p) <= (R)0) ? 1 : 0;
                 if constexpr (CONS) {
 #pragma unroll
-                    for (int m = 0; m < NV; ++m) sq[m][c] = U[m];
+                    for (int m = 0; m < NV; ++m) sq[m][q] = U[m];
                 } else {
-                    sq[0][c] = r;
+                    sq[0][q] = r;
                 }
 #pragma unroll
-                for (int d = 0; d < D; ++d) sq[OFF_VEL + d][c] = vel[d];
-                sq[OFF_P][c] = p;
-                if constexpr (NSV) sq[OFF_T][c] = p / r;
+                for (int d = 0; d < D; ++d) sq[OFF_VEL + d][q] = vel[d];
+                sq[OFF_P][q] = p;
+                if constexpr (TSTAGED) sq[OFF_T][q] = p / r;
             }
         }
         __syncthreads();
@@ -249,6 +271,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
         // reference state is rounded to float
         for (int i = tid; i < ST::N; i += kThreads) {
             const int c = ST::LIST ? (int)cells.c[i] : i;
+            const int q = PACKED ? i : c;
+            if constexpr (PACKED) s_slot[c] = (unsigned short)i;
             int bx = c % T::BX;
             int by = (c / T::BX) % T::BY;
             int bz = c / (T::BX * T::BY);
@@ -269,11 +293,11 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             for (int d = 1; d < D; ++d) ke = ke + vel[d] * vel[d];
             SD p = G.gm1 * (U[D + 1] - (0.5 * r) * ke);
             np |= (Sc<SD>::val(r) <= 0.0 || Sc<SD>::val(p) <= 0.0) ? 1 : 0;
-            sq[0][c] = narrow<S>(r - s_refd[0]);
+            sq[0][q] = narrow<S>(r - s_refd[0]);
 #pragma unroll
-            for (int d = 0; d < D; ++d) sq[1 + d][c] = narrow<S>(vel[d] - s_refd[1 + d]);
-            sq[OFF_P][c] = narrow<S>(p - s_refd[D + 1]);
-            if constexpr (NSV) sq[OFF_T][c] = narrow<S>(p * inv - s_refd[D + 2]);
+            for (int d = 0; d < D; ++d) sq[1 + d][q] = narrow<S>(vel[d] - s_refd[1 + d]);
+            sq[OFF_P][q] = narrow<S>(p - s_refd[D + 1]);
+            if constexpr (TSTAGED) sq[OFF_T][q] = narrow<S>(p * inv - s_refd[D + 2]);
         }
         __syncthreads();
     }
@@ -295,6 +319,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             int fz = f / (FX * FY);
             int cb = ((fz + ((D == 3) ? T::H : 0)) * T::BY + (fy + T::H)) * T::BX + (fx + T::H);
             int ca = cb - sd;
+            const int ia = slot(ca), ib = slot(cb);   // staged slots of the face's two cells
             S Fh[NV];
             S UL[NV], UR[NV], vL[D], vR[D];
             S rL, rR, pL, pR;
@@ -302,12 +327,13 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 S qL[NV], qR[NV];
                 if constexpr (FO) {
 #pragma unroll
-                    for (int k = 0; k < NV; ++k) { qL[k] = sq[k][ca]; qR[k] = sq[k][cb]; }
+                    for (int k = 0; k < NV; ++k) { qL[k] = sq[k][ia]; qR[k] = sq[k][ib]; }
                 } else {
                     const R half = (R)0.5;
+                    const int im = slot(ca - sd), ip = slot(cb + sd);
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
-                        S am1 = sq[k][ca - sd], a0 = sq[k][ca], ap1 = sq[k][cb], ap2 = sq[k][cb + sd];
+                        S am1 = sq[k][im], a0 = sq[k][ia], ap1 = sq[k][ib], ap2 = sq[k][ip];
                         qL[k] = a0 + half * minmod(a0 - am1, ap1 - a0);
                         qR[k] = ap1 - half * minmod(ap1 - a0, ap2 - ap1);
                     }
@@ -315,13 +341,13 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 num_flux_ref<D, FLUX>(G, s_ref, d, qL, qR, Fh);
             } else if constexpr (FO) {
 #pragma unroll
-                for (int m = 0; m < NV; ++m) { UL[m] = sq[m][ca]; UR[m] = sq[m][cb]; }
+                for (int m = 0; m < NV; ++m) { UL[m] = sq[m][ia]; UR[m] = sq[m][ib]; }
                 rL = UL[0];
                 rR = UR[0];
 #pragma unroll
-                for (int e = 0; e < D; ++e) { vL[e] = sq[OFF_VEL + e][ca]; vR[e] = sq[OFF_VEL + e][cb]; }
-                pL = sq[OFF_P][ca];
-                pR = sq[OFF_P][cb];
+                for (int e = 0; e < D; ++e) { vL[e] = sq[OFF_VEL + e][ia]; vR[e] = sq[OFF_VEL + e][ib]; }
+                pL = sq[OFF_P][ia];
+                pR = sq[OFF_P][ib];
             } else {
                 const R half = (R)0.5;
                 S qL[NV], qR[NV];
@@ -333,9 +359,10 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                         flatR = (y0 + fy == n1 - 1);
                     }
                 }
+                const int im = slot(ca - sd), ip = slot(cb + sd);
 #pragma unroll
                 for (int k = 0; k < NV; ++k) {
-                    S am1 = sq[k][ca - sd], a0 = sq[k][ca], ap1 = sq[k][cb], ap2 = sq[k][cb + sd];
+                    S am1 = sq[k][im], a0 = sq[k][ia], ap1 = sq[k][ib], ap2 = sq[k][ip];
                     const S sl = flatL ? Sc<S>::make(0.0) : minmod(a0 - am1, ap1 - a0);
                     const S sr = flatR ? Sc<S>::make(0.0) : minmod(ap1 - a0, ap2 - ap1);
                     qL[k] = a0 + half * sl;
@@ -511,18 +538,29 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 }
                 const R half = (R)0.5;
                 const R mu = (R)G.mu, c23mu = (R)G.c23mu, kappa = (R)G.kappa;
+                // staged slots of the tangential neighbours of both cells, per direction
+                int tap[D], tam[D], tbp[D], tbm[D];
+#pragma unroll
+                for (int bb = 0; bb < D; ++bb) {
+                    if (bb != d) {
+                        const int st = T::stride(bb);
+                        tap[bb] = slot(ca + st);
+                        tam[bb] = slot(ca - st);
+                        tbp[bb] = slot(cb + st);
+                        tbm[bb] = slot(cb - st);
+                    }
+                }
                 S Gr[D][D];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
 #pragma unroll
                     for (int bb = 0; bb < D; ++bb) {
                         if (bb == d) {
-                            Gr[a][bb] = (sq[OFF_VEL + a][cb] - sq[OFF_VEL + a][ca]) * (R)G.invdx[d];
+                            Gr[a][bb] = (sq[OFF_VEL + a][ib] - sq[OFF_VEL + a][ia]) * (R)G.invdx[d];
                         } else {
-                            const int st = T::stride(bb);
                             const R h = (R)G.hinv[bb];
-                            S gca = (sq[OFF_VEL + a][ca + st] - sq[OFF_VEL + a][ca - st]) * h;
-                            S gcb = (sq[OFF_VEL + a][cb + st] - sq[OFF_VEL + a][cb - st]) * h;
+                            S gca = (sq[OFF_VEL + a][tap[bb]] - sq[OFF_VEL + a][tam[bb]]) * h;
+                            S gcb = (sq[OFF_VEL + a][tbp[bb]] - sq[OFF_VEL + a][tbm[bb]]) * h;
                             Gr[a][bb] = half * (gca + gcb);
                         }
                     }
@@ -536,17 +574,17 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
                         S tau = (a == d) ? mu_ * (Gr[a][d] + Gr[d][a]) - c23mu_ * div : mu_ * (Gr[a][d] + Gr[d][a]);
-                        S uf = half * (sq[OFF_VEL + a][ca] + sq[OFF_VEL + a][cb]);
+                        S uf = half * (sq[OFF_VEL + a][ia] + sq[OFF_VEL + a][ib]);
                         if constexpr (PERT) uf = s_ref.u0[a] + uf;   // perturbations staged: add the reference
                         work = (a == 0) ? uf * tau : work + uf * tau;
                         Fh[1 + a] = Fh[1 + a] - tau;
                     }
-                    S dTdn = (sq[OFF_T][cb] - sq[OFF_T][ca]) * (R)G.invdx[d];
+                    S dTdn = (temp(ib) - temp(ia)) * (R)G.invdx[d];
                     Fh[D + 1] = Fh[D + 1] - (work + kappa_ * dTdn);
                 };
                 if (G.suth) {
                     // Sutherland's law at the face temperature (T_a + T_b) / 2
-                    S Tf = half * (sq[OFF_T][ca] + sq[OFF_T][cb]);
+                    S Tf = half * (temp(ia) + temp(ib));
                     if constexpr (PERT) Tf = (R)s_refd[D + 2] + Tf;
                     const S th = Tf / (R)G.t_ref;
                     const S muf = mu * th * Sc<S>::sqrt_(th) * (R)G.suth_one_s / (th + (R)G.suth_s);
