@@ -60,9 +60,9 @@ __global__ __launch_bounds__(kRedThreads) void k_red(double* w, const double* vp
     const long stride = (long)kRedBlocks * kRedThreads;
     long e = (long)blockIdx.x * kRedThreads + threadIdx.x;
     for (; e + stride < n; e += 2 * stride) {
-        double w0 = w[e], w1 = w[e + stride];
+        double w0 = ld_stream(w + e), w1 = ld_stream(w + e + stride);
         if constexpr (UPD) {
-            double a0 = vprev[e], a1 = vprev[e + stride];
+            double a0 = ld_stream(vprev + e), a1 = ld_stream(vprev + e + stride);
             w0 = w0 - h * a0;
             w1 = w1 - h * a1;
             w[e] = w0;
@@ -73,20 +73,20 @@ __global__ __launch_bounds__(kRedThreads) void k_red(double* w, const double* vp
             b0 = w0;
             b1 = w1;
         } else {
-            b0 = vcur[e];
-            b1 = vcur[e + stride];
+            b0 = ld_stream(vcur + e);
+            b1 = ld_stream(vcur + e + stride);
         }
         acc = acc + b0 * w0;
         acc = acc + b1 * w1;
     }
     if (e < n) {
-        double we = w[e];
+        double we = ld_stream(w + e);
         if constexpr (UPD) {
-            we = we - h * vprev[e];
+            we = we - h * ld_stream(vprev + e);
             w[e] = we;
         }
         if constexpr (SELF) acc = acc + we * we;
-        else acc = acc + vcur[e] * we;
+        else acc = acc + ld_stream(vcur + e) * we;
     }
     double bs = block_sum(acc, s);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kRedThreads) void k_normalize(const double* w, cons
         if (brk) return;
     }
     const long stride = (long)gridDim.x * blockDim.x;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) v[e] = w[e] / hn;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) v[e] = ld_stream(w + e) / hn;
 }
 
 __global__ void k_init(double* H, int nh, double* phi, double* lam, int nsm, double* scal, int* ints, int meff0,
@@ -324,19 +324,19 @@ __global__ __launch_bounds__(kRedThreads) void k_project(const double* V, const 
     const long stride = (long)kRedBlocks * kRedThreads;
     if (m == MB) {
         for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
-            double fe = F[e];
+            double fe = ld_stream(F + e);
             double vc[MB];
 #pragma unroll
-            for (int c = 0; c < MB; ++c) vc[c] = V[(long)c * n + e];
+            for (int c = 0; c < MB; ++c) vc[c] = ld_stream(V + (long)c * n + e);
 #pragma unroll
             for (int c = 0; c < MB; ++c) acc[c] = acc[c] + vc[c] * fe;
         }
     } else {
         for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
-            double fe = F[e];
+            double fe = ld_stream(F + e);
 #pragma unroll
             for (int c = 0; c < MB; ++c)
-                if (c < m) acc[c] = acc[c] + V[(long)c * n + e] * fe;
+                if (c < m) acc[c] = acc[c] + ld_stream(V + (long)c * n + e) * fe;
         }
     }
 #pragma unroll
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_recover(const double* __restrict__ V, c
         if (m == MB) {
             double vc[MB];
 #pragma unroll
-            for (int c = 0; c < MB; ++c) vc[c] = V[(long)c * n + e];
+            for (int c = 0; c < MB; ++c) vc[c] = ld_stream(V + (long)c * n + e);
 #pragma unroll
             for (int c = 0; c < MB; ++c) {
                 a = a + vc[c] * lm[c];
@@ -383,16 +383,16 @@ __global__ __launch_bounds__(256) void k_recover(const double* __restrict__ V, c
             }
         } else {
             for (int c = 0; c < m; ++c) {
-                double vc = V[(long)c * n + e];
+                double vc = ld_stream(V + (long)c * n + e);
                 a = a + vc * lam[c];
                 b = b + vc * phi[c];
             }
         }
-        double ke = a + h * (F[e] - b);
+        double ke = a + h * (ld_stream(F + e) - b);
         if constexpr (FINAL) {
-            double acc = y[e];
+            double acc = ld_stream(y + e);
             for (int i = 0; i < s - 1; ++i)
-                if (br.b[i] != 0.0) acc = acc + br.b[i] * K[(long)i * n + e];
+                if (br.b[i] != 0.0) acc = acc + br.b[i] * ld_stream(K + (long)i * n + e);
             if (br.b[s - 1] != 0.0) acc = acc + br.b[s - 1] * ke;
             k[e] = acc;
         } else {

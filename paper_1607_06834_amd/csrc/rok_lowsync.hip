@@ -48,10 +48,10 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_dots(const double* V, const 
     }
     const long stride = (long)kRedBlocks * kRedThreads;
     for (long e = (long)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
-        const double we = w[e];
+        const double we = ld_stream(w + e);
         double q[MB];
 #pragma unroll
-        for (int c = 0; c < MB; ++c) q[c] = (c <= j) ? V[(long)c * n + e] : 0.0;
+        for (int c = 0; c < MB; ++c) q[c] = (c <= j) ? ld_stream(V + (long)c * n + e) : 0.0;
         double qj = 0.0;
 #pragma unroll
         for (int c = 0; c < MB; ++c) qj = (c == j) ? q[c] : qj;
@@ -135,10 +135,10 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* __restr
         double q0[MB], q1[MB];
 #pragma unroll
         for (int c = 0; c < MB; ++c) {
-            q0[c] = (c <= j) ? V[(long)c * n + e] : 0.0;
-            q1[c] = (c <= j) ? V[(long)c * n + e + stride] : 0.0;
+            q0[c] = (c <= j) ? ld_stream(V + (long)c * n + e) : 0.0;
+            q1[c] = (c <= j) ? ld_stream(V + (long)c * n + e + stride) : 0.0;
         }
-        double x0 = w[e], x1 = w[e + stride];
+        double x0 = ld_stream(w + e), x1 = ld_stream(w + e + stride);
 #pragma unroll
         for (int c = 0; c < MB; ++c)
             if (c <= j) {
@@ -151,10 +151,10 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* __restr
         acc = acc + x1 * x1;
     }
     if (e < n) {
-        double x = w[e];
+        double x = ld_stream(w + e);
 #pragma unroll
         for (int c = 0; c < MB; ++c)
-            if (c <= j) x = x - h[c] * V[(long)c * n + e];
+            if (c <= j) x = x - h[c] * ld_stream(V + (long)c * n + e);
         out[e] = x;
         acc = acc + x * x;
     }
