@@ -160,7 +160,7 @@ constexpr int kBufWord3 = 0x00020000;
 // condition (no exec-masked branches, whose joins would make the compiler
 // wait for every outstanding load, prefetches included).  All offsets are in
 // the lane's offset register, which is what the range check covers.
-template <int PER>
+template <int PER, int AUX = 0>
 __device__ __forceinline__ void load_lane(const double* __restrict__ src, long n, int t, double (&x)[PER]) {
     constexpr int T = kPB * kPT;
     const __amdgpu_buffer_rsrc_t r =
@@ -171,7 +171,7 @@ __device__ __forceinline__ void load_lane(const double* __restrict__ src, long n
     asm volatile("" : "+v"(off));
 #pragma unroll
     for (int k = 0; k < PER; ++k)
-        x[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off + k * T * 8, 0, 0));
+        x[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off + k * T * 8, 0, AUX));
 }
 
 // dst[t + k T] = x[k] for the chunks of lane t below n (raw buffer stores
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
         for (int k = 0; k < PER; ++k) w.set(k, x[k]);
     }
     double A[PER], B[PER];
-    load_lane<PER>(V, n, t, A);
+    load_lane<PER, 2>(V, n, t, A);
     __shared__ double s_hcol[kMaxM + 1];
     __shared__ double s_gs[kPT / kRedThreads];
     int phase = 0;
@@ -260,11 +260,11 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
         // waits for every outstanding load, the prefetch included
         asm volatile("" : "+v"(acc) : : "memory");
         const bool more = i < j;
-        if (more && prefetch) load_lane<PER>(V + (long)(i + 1) * n, n, t, prev);
+        if (more && prefetch) load_lane<PER, 2>(V + (long)(i + 1) * n, n, t, prev);
         publish(acc, s, s_gs);
         // unconditional (v_j again after the last pass, 64 lanes' worth), so
         // that the sum's waits count exactly these loads behind the partials
-        auto wave0_prefetch = [&] { load_lane<PER>(V + (long)(more ? i + 1 : j) * n, n, t, prev); };
+        auto wave0_prefetch = [&] { load_lane<PER, 2>(V + (long)(more ? i + 1 : j) * n, n, t, prev); };
         if (!collect(part, phase, bar, s_gs, &h, wave0_prefetch)) {
             failed = true;
             return;
