@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--traffic", default=None,
                     help="JSON file with counter figures per launch of the roofline kernels (default: "
                          "profiles/traffic_<workload>.json)")
+    ap.add_argument("--traffic-from", default=None, metavar="DIR",
+                    help="write profiles/traffic_<workload>.json from the three counter runs under DIR "
+                         "(pmc_<workload>_FETCH_SIZE, _WRITE_SIZE, _SQ_INSTS_VALU_SQ_WAVES; see build_traffic) "
+                         "and exit; needs no GPU")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the discrete adjoint of the step (rok_step_vjp; on by default for the "
                          "differentiation workload)")
@@ -78,6 +82,7 @@ def parse():
 RESIDUAL_SOURCES = ("rok_residual.hip", "rok_flux.hpp", "rok_device.hpp")
 MGS_SOURCES = ("rok_mgs.hip", "rok_kernels.hpp", "rok_device.hpp")
 KRED_SOURCES = ("rok_krylov.hip", "rok_kernels.hpp", "rok_device.hpp")
+LS_SOURCES = ("rok_lowsync.hip", "rok_krylov.hip", "rok_kernels.hpp", "rok_device.hpp")
 
 
 def _source_hash(names):
@@ -290,6 +295,7 @@ def _mgs_roofline(args, g, y, M, mode, stream, ms_step):
     elif path == "one_reduce":
         ms = sum(col_ms) / m
         alg = col_alg
+        traffic = _traffic(tpath, LS_SOURCES, "ls_column")
         kb = sum((2 * j + 4) * 8 * N + (16 * N if j + 1 < m else 0) for j in range(m)) / m
         kernel = (f"one-reduce Gram-Schmidt Arnoldi column (k_ls_dots, k_ls_solve, k_ls_update, k_normalize), "
                   f"average over the {m} columns of a step")
@@ -864,8 +870,114 @@ def _dominant(res, w, tab):
     return dict(ent, ms_per_step=round(ms, 3), share_of_step=round(ms / res["ms_per_step"], 4))
 
 
+PMC_SETS = ("FETCH_SIZE", "WRITE_SIZE", "SQ_INSTS_VALU SQ_WAVES")
+
+
+def build_traffic(workload, cdir, out_path):
+    """Counter figures per launch of the roofline kernels from three rocprofv3
+    runs of `bench.py --workload W --roofline-only --no-cpu-baseline
+    --kernel-reps 4`, one per entry of PMC_SETS, written to
+    cdir/pmc_<W>_<set>/run_counter_collection.csv.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read
+    for the run's calibration copy of one state vector (8 N bytes read and
+    written; the copy kernel reads twice what it moves), averaged over the
+    dispatches of each kernel.  An Arnoldi column of the one-reduce path is its
+    four kernels (k_ls_dots, k_ls_solve, k_ls_update, k_normalize): their
+    bytes summed over the run and divided by the number of columns (one
+    k_ls_solve per column).  Each entry carries the hash of the kernel sources
+    (run this on the tree the counters were taken on); bench.py reports no
+    traffic for a kernel changed since."""
+    import collections
+    import csv
+
+    import rok_inputs as ri
+    pb, _, w = ri.workload(workload)
+    N = ri.size(pb)
+
+    def load(tag):
+        agg = collections.defaultdict(list)
+        path = os.path.join(cdir, f"pmc_{workload}_{tag.replace(' ', '_')}", "run_counter_collection.csv")
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+        return agg
+
+    F, W, V = (load(t) for t in PMC_SETS)
+
+    def vals(agg, prefix, counter):
+        out = []
+        for (k, c), v in agg.items():
+            if k.startswith(prefix) and c == counter:
+                out += v
+        return out
+
+    cf = vals(F, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    cw = vals(W, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    cf, cw = sum(cf) / len(cf), sum(cw) / len(cw)
+    vec_kib = 8 * N / 1024
+    fs, ws = vec_kib / cf, vec_kib / cw
+    cmd = ("timeout -s KILL 240 rocprofv3 --pmc {} --output-format csv -d gpurun_out/pmc_{}_{} -o run -- "
+           "python bench.py --workload {} --roofline-only --no-cpu-baseline --kernel-reps 4")
+    rec = {"workload": workload, "N": N,
+           "method": "rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, one counter per run, KiB per dispatch averaged "
+                     "over the dispatches, each scaled by what it reads for a copy of one state vector (8 N bytes "
+                     "read, 8 N written) in the same run; SQ_INSTS_VALU and SQ_WAVES in a third run; written by "
+                     f"python bench.py --workload {workload} --traffic-from gpurun_out",
+           "commands": [cmd.format(t, workload, t.replace(" ", "_"), workload) for t in PMC_SETS],
+           "calibration": {"kernel": f"__amd_rocclr_copyBuffer, {8 * N / 2 ** 20:.0f} MiB",
+                           "fetch_kib": round(cf, 2), "write_kib": round(cw, 2),
+                           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
+           "source_hash": "sha256 of the listed kernel sources with comments and white space removed "
+                          "(bench._source_hash)"}
+    m = w["M"]
+    col_alg = sum((j + 2) * 8 * N + (8 * N if j + 1 < m else 0) for j in range(m)) / m
+    D = len(pb["n"])
+    ns = "true" if pb["physics"] == "ns" else "false"
+    single = {"mgs_pass": ("void rok::k_red<true, false>", KRED_SOURCES, 24 * N),
+              "mgs_column": (f"void rok::k_mgs_resident<{m}>", MGS_SOURCES, col_alg),
+              "fd_jvp": (f"void rok::k_residual<{D}, 1, {ns}, 0, 0, double, 1, double", RESIDUAL_SOURCES, 32 * N),
+              "residual": (f"void rok::k_residual<{D}, 1, {ns}, 0, 0, double, 0, double", RESIDUAL_SOURCES,
+                           16 * N)}
+    for key, (kn, src, alg) in single.items():
+        f = vals(F, kn, "FETCH_SIZE")
+        if not f:
+            continue
+        wr, vi, wv = vals(W, kn, "WRITE_SIZE"), vals(V, kn, "SQ_INSTS_VALU"), vals(V, kn, "SQ_WAVES")
+        fa, wa = sum(f) / len(f), sum(wr) / len(wr)
+        hbm = fa * 1024 * fs + wa * 1024 * ws
+        rec[key] = {"kernel": kn, "dispatches": len(f), "fetch_kib_avg": round(fa, 1), "write_kib_avg": round(wa, 1),
+                    "hbm_bytes_per_launch": int(hbm), "alg_bytes_per_launch": int(alg),
+                    "over_algorithmic": round(hbm / alg - 1, 4), "source_sha256_16": _source_hash(src),
+                    "valu_insts_per_launch": int(sum(vi) / len(vi)), "waves_per_launch": int(sum(wv) / len(wv))}
+    ncol = len(vals(F, "rok::k_ls_solve", "FETCH_SIZE"))
+    if ncol:
+        parts = ("void rok::k_ls_dots<", "rok::k_ls_solve", "void rok::k_ls_update<", "rok::k_normalize")
+        tf = sum(sum(vals(F, k, "FETCH_SIZE")) for k in parts)
+        tw = sum(sum(vals(W, k, "WRITE_SIZE")) for k in parts)
+        tv = sum(sum(vals(V, k, "SQ_INSTS_VALU")) for k in parts)
+        hbm = (tf * 1024 * fs + tw * 1024 * ws) / ncol
+        kb = sum((2 * j + 4) * 8 * N + (16 * N if j + 1 < m else 0) for j in range(m)) / m
+        rec["ls_column"] = {"kernel": "one-reduce Gram-Schmidt column: " + ", ".join(p.split("::")[-1].rstrip("<")
+                                                                                      for p in parts),
+                            "columns": ncol, "fetch_kib_avg": round(tf / ncol, 1), "write_kib_avg": round(tw / ncol, 1),
+                            "hbm_bytes_per_launch": int(hbm), "alg_bytes_per_launch": int(col_alg),
+                            "kernel_bytes_per_launch": int(kb), "over_algorithmic": round(hbm / col_alg - 1, 4),
+                            "over_kernel_bytes": round(hbm / kb - 1, 4), "source_sha256_16": _source_hash(LS_SOURCES),
+                            "valu_insts_per_launch": int(tv / ncol)}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    return rec
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        out = _traffic_path(args)
+        build_traffic(args.workload, args.traffic_from, out)
+        print(f"wrote {out}")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the path has no multi-GPU form",
               file=sys.stderr)

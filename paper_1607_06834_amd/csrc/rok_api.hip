@@ -53,8 +53,9 @@ rok::ResArgs plain_args(const double* y, void* out) {
 // w = J(y) v into a double vector (internal use).  FD reads eps from eps_dev.
 hipError_t jvp_into(const rok_ctx* c, const double* y, const double* fy, const double* v, double* w, int mode,
                     const double* eps_dev, double eps, hipStream_t st, const int* gate = nullptr, int gate_col = 0,
-                    int* status = nullptr, const int* stop = nullptr) {
+                    int* status = nullptr, const int* stop = nullptr, const double* vscale = nullptr) {
     rok::ResArgs A{};
+    A.vscale = vscale;
     A.status = status;
     A.stop = stop;
     A.gate = gate;
@@ -91,13 +92,17 @@ int pick_ortho(const rok_ctx* c, int M, bool mgs_only) {
     }
 }
 
-// Arnoldi (Sec. 2.2.2) into V (N x M columns), H inside W.
+// Arnoldi (Sec. 2.2.2) into V (N x M columns), H inside W.  deferred: with
+// the one-reduce form, the columns after the first are left unnormalised,
+// column c holding v_c / W.sig[c] (the caller applies the scales; rok_step's
+// own basis), which saves a pass over each new column.
 hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, const double* fy, int M, int mode,
-                        double eps, double* V, hipStream_t st, bool mgs_only = false) {
+                        double eps, double* V, hipStream_t st, bool mgs_only = false, bool deferred = false) {
     const long N = c->G.N;
     const double* epsp = nullptr;
     const int ortho = pick_ortho(c, M, mgs_only);
     if (ortho < 0) return hipErrorNotSupported;
+    deferred = deferred && ortho == ORTHO_ONE_REDUCE;
     hipError_t e;
     if (mode == ROK_JVP_FD && !(eps > 0.0)) {
         e = rok::launch_norm_eps(W, y, nullptr, N, st);  // unit Arnoldi vectors: ||v_j|| = 1
@@ -109,13 +114,14 @@ hipError_t arnoldi_core(const rok_ctx* c, const rok::Work& W, const double* y, c
     for (int j = 0; j < M; ++j) {
         double* vj = V + (long)j * N;
         // after a breakdown (stop word set) column j was never written: the product is skipped
-        e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st, nullptr, 0, W.ints + 2, W.ints + 1);
+        e = jvp_into(c, y, fy, vj, W.w, mode, epsp, eps, st, nullptr, 0, W.ints + 2, W.ints + 1,
+                     deferred ? W.sig + j : nullptr);
         if (e != hipSuccess) return e;
         double* vnext = (j + 1 < M) ? V + (long)(j + 1) * N : nullptr;
         if (ortho == ORTHO_RESIDENT)
             e = rok::launch_mgs_resident(W, W.w, V, N, M, j, vnext, st);
         else if (ortho == ORTHO_ONE_REDUCE)
-            e = rok::launch_ls_column(W, W.w, V, N, M, j, vnext, st);
+            e = rok::launch_ls_column(W, W.w, V, N, M, j, vnext, st, deferred);
         else
             e = rok::launch_mgs_column(W, W.w, V, N, M, j, vnext, st);
         if (e != hipSuccess) return e;
@@ -137,8 +143,11 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
         e = rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st);
         if (e != hipSuccess) return e;
     }
+    // the one-reduce basis is kept unnormalised (scales W.sig) inside the step
+    const bool deferred = M > 0 && pick_ortho(c, M, mgs_only) == ORTHO_ONE_REDUCE;
+    const double* sig = deferred ? W.sig : nullptr;
     if (M > 0) {
-        e = arnoldi_core(c, W, y_n, W.F, M, mode, 0.0, W.V, st, mgs_only);
+        e = arnoldi_core(c, W, y_n, W.F, M, mode, 0.0, W.V, st, mgs_only, deferred);
         if (e != hipSuccess) return e;
         e = rok::launch_lu(W, M, h * tab->gamma, st);
         if (e != hipSuccess) return e;
@@ -166,13 +175,13 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
             if (e != hipSuccess) return e;
             double grow[ROK_MAX_STAGES];
             for (int j = 0; j < ROK_MAX_STAGES; ++j) grow[j] = (j < i) ? tab->gam[i * ROK_MAX_STAGES + j] : 0.0;
-            e = rok::launch_lambda(W, M, i, grow, h, st);
+            e = rok::launch_lambda(W, M, i, grow, h, st, sig);
             if (e != hipSuccess) return e;
         }
         if (i + 1 < s)
-            e = rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, nullptr, nullptr, 0, nullptr, st);
+            e = rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, nullptr, nullptr, 0, nullptr, st, sig);
         else
-            e = rok::launch_recover(W, W.V, Fi, N, M, i, h, y_np1, y_n, W.K, s, tab->b, st);
+            e = rok::launch_recover(W, W.V, Fi, N, M, i, h, y_np1, y_n, W.K, s, tab->b, st, sig);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

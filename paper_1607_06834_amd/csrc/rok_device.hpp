@@ -62,6 +62,10 @@ struct ResArgs {
     // optional: do nothing once *stop is set (a finished Arnoldi process: the
     // basis column this product would read was never written)
     const int* stop;
+    // optional (products): the direction is (*vscale) v, for a basis column
+    // stored before its normalisation (FD: the increment eps (*vscale) is
+    // applied to v; tangent: the tangent is v (*vscale))
+    const double* vscale;
 };
 
 // ---------------------------------------------------------------------------

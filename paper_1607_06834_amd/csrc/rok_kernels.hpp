@@ -34,6 +34,7 @@ struct Work {
     double* lam;      // s x M
     int* perm;        // M
     double* L;        // M x M: strictly lower Gram part of the one-reduce Gram-Schmidt (leading dimension M)
+    double* sig;      // M + 1 basis scales: column c of V holds v_c / sig[c] (1 unless normalisation is deferred)
     double* partials; // npart x kRedBlocks reduction partials
     int npart;
     double* gpart;    // 2 x kRedBlocks partials exchanged inside the resident MGS kernel
@@ -67,9 +68,14 @@ hipError_t launch_mgs_column(const Work& W, double* w, const double* V, long n, 
 hipError_t launch_normalize(const Work& W, const double* w, const double* partials, int M, int j, double* v, long n,
                             hipStream_t st);
 // One-reduce Gram-Schmidt for one Arnoldi column (rok_lowsync.hip); M <= 24.
+// deferred: the next column is stored as the orthogonalised w, unnormalised,
+// with its scale 1 / ||w|| in W.sig[j + 1]; the columns' scales apply
+// throughout (W.sig; products take it as ResArgs.vscale).
 bool lowsync_supported(int M);
 hipError_t launch_ls_column(const Work& W, const double* w, const double* V, long n, int M, int j, double* vnext,
-                            hipStream_t st);
+                            hipStream_t st, bool deferred = false);
+// H[j+1][j] = ||w||, finished from `partials`, the breakdown test of column j and sig[j+1] = 1 / ||w|| (one block)
+hipError_t launch_norm_scale(const Work& W, const double* partials, int M, int j, hipStream_t st);
 // Resident-w MGS for one column (rok_mgs.hip).
 int mgs_resident_per(long n);
 bool mgs_resident_available();
@@ -85,11 +91,14 @@ double ritz_residual(int m, const double* H, int ldh, double hlast, double tre, 
 hipError_t launch_copy_h(const Work& W, int M, double* Hout, int* meff_out, hipStream_t st);
 hipError_t launch_lu(const Work& W, int M, double hg, hipStream_t st);
 hipError_t launch_project(const Work& W, const double* V, const double* F, long n, int M, hipStream_t st);
-hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, double h, hipStream_t st);
+// sig: the basis scales (W.sig) when V holds unnormalised columns, else null
+hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, double h, hipStream_t st,
+                         const double* sig = nullptr);
 // k_i = V lambda_i + h (F_i - V phi_i) into k; if y is non-null (last stage)
 // writes y_{n+1} = y + sum_{q<s} b_q k_q into k instead, K holding k_0..k_{s-2}.
 hipError_t launch_recover(const Work& W, const double* V, const double* F, long n, int M, int i, double h, double* k,
-                          const double* y, const double* K, int s, const double* b, hipStream_t st);
+                          const double* y, const double* K, int s, const double* b, hipStream_t st,
+                          const double* sig = nullptr);
 
 // Discrete adjoint of the ROK step (rok_step_adjoint.hip).  Carved after the
 // forward step's workspace; lambar, phibar are s x M, Hbar (M+1) x M, Abar

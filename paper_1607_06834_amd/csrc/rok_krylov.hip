@@ -155,10 +155,34 @@ __global__ __launch_bounds__(kRedThreads) void k_normalize(const double* w, cons
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) v[e] = ld_stream(w + e) / hn;
 }
 
+// The normalisation's bookkeeping without the division: h_{j+1,j} = sqrt(w.w)
+// from `partials`, the breakdown test of k_normalize, and sig[j+1] =
+// 1 / h_{j+1,j}, the scale of the unnormalised column (one block).
+__global__ __launch_bounds__(kRedThreads) void k_norm_scale(const double* partials, double* H, int M, int j,
+                                                           int* ints, double* sig) {
+    __shared__ double s[kRedThreads];
+    if (ints[1]) return;
+    const double hn = sqrt(final_sum(partials, s));
+    if (threadIdx.x != 0) return;
+    double c = 0.0;
+    for (int i = 0; i <= j; ++i) c = c + H[i * M + j] * H[i * M + j];
+    c = c + hn * hn;
+    H[(j + 1) * M + j] = hn;
+    if (hn <= kBreakdownTol * sqrt(c)) {
+        ints[0] = j + 1;
+        ints[1] = 1;
+        ints[2] |= ROK_FLAG_BREAKDOWN;
+    } else {
+        sig[j + 1] = 1.0 / hn;
+    }
+    if (nonfinite(hn)) ints[2] |= ROK_FLAG_NONFINITE;
+}
+
 __global__ void k_init(double* H, int nh, double* phi, double* lam, int nsm, double* scal, int* ints, int meff0,
-                       unsigned* bar) {
+                       unsigned* bar, double* sig, int nsig) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int e = t; e < kBarWords; e += gridDim.x * blockDim.x) bar[e] = 0u;
+    for (int e = t; e < nsig; e += gridDim.x * blockDim.x) sig[e] = 1.0;
     for (int e = t; e < nh; e += gridDim.x * blockDim.x) H[e] = 0.0;
     for (int e = t; e < nsm; e += gridDim.x * blockDim.x) {
         phi[e] = 0.0;
@@ -241,7 +265,7 @@ struct GamRow {
 // lambda_i = LU^{-1} (h phi_i + h H sum_{j<i} gamma_ij lambda_j) on the same block.
 __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const double* LU, const int* perm, int M,
                                                        int i, GamRow gr, double h, const double* partials,
-                                                       double* phi, double* lam, int* ints) {
+                                                       double* phi, double* lam, int* ints, const double* sig) {
     __shared__ double s[16][kRedThreads];
     __shared__ double sphi[kMaxM];
     const int m = ints[0];
@@ -259,7 +283,8 @@ __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const d
                 for (int c = 0; c < nc; ++c) s[c][tid] = s[c][tid] + s[c][tid + st];
             __syncthreads();
         }
-        if (tid < nc) sphi[c0 + tid] = s[tid][0];
+        // a column stored unnormalised: <v_c, F> = sig_c <V_c, F>
+        if (tid < nc) sphi[c0 + tid] = sig ? s[tid][0] * sig[c0 + tid] : s[tid][0];
         __syncthreads();
     }
     // The reduced solve.  H, LU, the pivots and the earlier lambdas are staged
@@ -359,14 +384,17 @@ template <int MB, bool FINAL>
 __global__ __launch_bounds__(256) void k_recover(const double* __restrict__ V, const double* __restrict__ F, long n,
                                                 const int* ints, const double* lam, const double* phi, double h,
                                                 double* __restrict__ k, const double* __restrict__ y,
-                                                const double* __restrict__ K, int s, BRow br) {
+                                                const double* __restrict__ K, int s, BRow br, const double* sig) {
     const int m = ints[0];
+    // columns stored unnormalised (v_c = sig_c V_c): the scales go into the coefficients
+    auto lamc = [&](int c) { return sig ? lam[c] * sig[c] : lam[c]; };
+    auto phic = [&](int c) { return sig ? phi[c] * sig[c] : phi[c]; };
     double lm[MB], ph[MB];
     if (m == MB) {
 #pragma unroll
         for (int c = 0; c < MB; ++c) {
-            lm[c] = lam[c];
-            ph[c] = phi[c];
+            lm[c] = lamc(c);
+            ph[c] = phic(c);
         }
     }
     const long stride = (long)gridDim.x * blockDim.x;
@@ -384,8 +412,8 @@ __global__ __launch_bounds__(256) void k_recover(const double* __restrict__ V, c
         } else {
             for (int c = 0; c < m; ++c) {
                 double vc = ld_stream(V + (long)c * n + e);
-                a = a + vc * lam[c];
-                b = b + vc * phi[c];
+                a = a + vc * lamc(c);
+                b = b + vc * phic(c);
             }
         }
         double ke = a + h * (ld_stream(F + e) - b);
@@ -435,6 +463,7 @@ size_t work_small_bytes(int M, int s) {
     b += al256(sizeof(double) * ss * Mm);                        // lam
     b += al256(sizeof(int) * Mm);                                // perm
     b += al256(sizeof(double) * Mm * Mm);                        // L
+    b += al256(sizeof(double) * (Mm + 1));                       // sig
     b += al256(sizeof(double) * (size_t)npart(M) * kRedBlocks);  // partials
     b += al256(sizeof(double) * 2 * kRedBlocks);                 // gpart
     b += al256(sizeof(unsigned) * kBarWords);                    // barrier
@@ -463,6 +492,7 @@ Work carve(void* base, long N, int M, int s, bool step) {
     W.lam = (double*)p;      p += al256(sizeof(double) * ss * Mm);
     W.perm = (int*)p;        p += al256(sizeof(int) * Mm);
     W.L = (double*)p;        p += al256(sizeof(double) * Mm * Mm);
+    W.sig = (double*)p;      p += al256(sizeof(double) * (Mm + 1));
     W.partials = (double*)p; p += al256(sizeof(double) * (size_t)npart(M) * kRedBlocks);
     W.npart = npart(M);
     W.gpart = (double*)p;    p += al256(sizeof(double) * 2 * kRedBlocks);
@@ -525,7 +555,7 @@ hipError_t launch_init(const Work& W, int M, int s, hipStream_t st) {
     int Mm = M > 0 ? M : 1;
     int ss = s > 0 ? s : 1;
     hipLaunchKernelGGL(k_init, dim3(16), dim3(256), 0, st, W.H, (Mm + 1) * Mm, W.phi, W.lam, ss * Mm, W.scal, W.ints,
-                       M, W.bar);
+                       M, W.bar, W.sig, Mm + 1);
     return hipGetLastError();
 }
 
@@ -590,6 +620,11 @@ hipError_t launch_normalize(const Work& W, const double* w, const double* partia
     return hipGetLastError();
 }
 
+hipError_t launch_norm_scale(const Work& W, const double* partials, int M, int j, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(kRedThreads), 0, st, partials, W.H, M, j, W.ints, W.sig);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy_h(const Work& W, int M, double* Hout, int* meff_out, hipStream_t st) {
     hipLaunchKernelGGL(k_copy_h, dim3(grid_for((long)M * M, 256)), dim3(256), 0, st, W.H, M, Hout, W.ints, meff_out);
     return hipGetLastError();
@@ -631,16 +666,18 @@ hipError_t launch_project(const Work& W, const double* V, const double* F, long 
     return hipGetLastError();
 }
 
-hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, double h, hipStream_t st) {
+hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, double h, hipStream_t st,
+                         const double* sig) {
     GamRow gr{};
     for (int j = 0; j < kMaxStages; ++j) gr.g[j] = (j < i) ? gam_row[j] : 0.0;
     hipLaunchKernelGGL(k_lambda, dim3(1), dim3(kRedThreads), 0, st, W.H, W.LU, W.perm, M, i, gr, h, W.partials,
-                       W.phi, W.lam, W.ints);
+                       W.phi, W.lam, W.ints, sig);
     return hipGetLastError();
 }
 
 hipError_t launch_recover(const Work& W, const double* V, const double* F, long n, int M, int i, double h, double* k,
-                          const double* y, const double* K, int s, const double* b, hipStream_t st) {
+                          const double* y, const double* K, int s, const double* b, hipStream_t st,
+                          const double* sig) {
     int Mm = M > 0 ? M : 1;
     BRow br{};
     for (int q = 0; q < kMaxStages; ++q) br.b[q] = (b && q < s) ? b[q] : 0.0;
@@ -649,9 +686,9 @@ hipError_t launch_recover(const Work& W, const double* V, const double* F, long 
     const unsigned g = grid_for(n, 256);
 #define ROK_REC(MB)                                                                                             \
     if (y) hipLaunchKernelGGL((k_recover<MB, true>), dim3(g), dim3(256), 0, st, V, F, n, W.ints, lam, phi, h, k, \
-                              y, K, s, br);                                                                     \
+                              y, K, s, br, sig);                                                                \
     else hipLaunchKernelGGL((k_recover<MB, false>), dim3(g), dim3(256), 0, st, V, F, n, W.ints, lam, phi, h, k,  \
-                            y, K, s, br)
+                            y, K, s, br, sig)
     ROK_MB_SWITCH(mbucket(M > 0 ? M : 1), ROK_REC)
 #undef ROK_REC
     return hipGetLastError();

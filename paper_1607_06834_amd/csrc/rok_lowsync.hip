@@ -21,6 +21,14 @@
 // the breakdown decision and divides.  The last column (j = M - 1) needs only
 // H's column: sweep A and the solve.
 //
+// Deferred normalisation (the basis a ROK step keeps for itself): the division
+// pass is dropped.  Column j + 1 stays w' and its scale sig_{j+1} = 1 / ||w'||
+// is kept on the device; the product J v_{j+1} takes the scale on its
+// direction, the sums of sweep A are scaled after summation and sweep B, the
+// projection and the recovery fold the scales into their coefficients.  In
+// exact arithmetic nothing changes; one pass over a state vector less per
+// column.
+//
 // Sums follow the canonical lane order of the other reductions (lane t of
 // kRedBlocks x kRedThreads adds the elements t, t + T, ... in order, block
 // trees, finished in order by one block), so results are deterministic; they
@@ -79,8 +87,11 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_dots(const double* V, const 
 // One block: finish r and s (canonical final sums), store the Gram row in L
 // (row j, leading dimension M), solve (I + L) h = r by forward substitution in
 // index order and write h into column j of H.  NONFINITE on a non-finite h.
+// sig (non-null): the columns are stored unnormalised, q_c = sig_c V_c, and the
+// sums over the stored columns are scaled: r_c = sig_c <V_c, w>,
+// s_c = (sig_j sig_c) <V_j, V_c>.
 __global__ __launch_bounds__(kRedThreads) void k_ls_solve(const double* partials, int MB, int j, int M, double* L,
-                                                         double* H, int* ints) {
+                                                         double* H, int* ints, const double* sig) {
     __shared__ double s[kRedThreads];
     __shared__ double sr[kMaxM], ss[kMaxM];
     if (ints[1]) return;
@@ -89,14 +100,14 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_solve(const double* partials
         double a = 0.0;
         for (int b = tid; b < kRedBlocks; b += kRedThreads) a = a + partials[(long)c * kRedBlocks + b];
         const double t = tree256(a, s);
-        if (tid == 0) sr[c] = t;
+        if (tid == 0) sr[c] = sig ? t * sig[c] : t;
         __syncthreads();
     }
     for (int c = 0; c < j; ++c) {
         double a = 0.0;
         for (int b = tid; b < kRedBlocks; b += kRedThreads) a = a + partials[(long)(MB + c) * kRedBlocks + b];
         const double t = tree256(a, s);
-        if (tid == 0) ss[c] = t;
+        if (tid == 0) ss[c] = sig ? t * (sig[j] * sig[c]) : t;
         __syncthreads();
     }
     if (tid != 0) return;
@@ -114,16 +125,20 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_solve(const double* partials
 // Sweep B of column j: w' = w - h_0 q_0 - ... - h_j q_j into `out` (the next
 // basis column, distinct from V's columns 0..j and from w), partials of
 // ||w'||^2 at `partials`.  Two elements of a lane per iteration, both loaded
-// before either is stored (the lane's sum keeps index order).
+// before either is stored (the lane's sum keeps index order).  With sig, the
+// coefficient of stored column c is h_c sig_c.
 template <int MB>
 __global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* __restrict__ V,
                                                           const double* __restrict__ w, const double* H, long n,
                                                           int j, int M, double* __restrict__ out, const int* ints,
-                                                          double* partials) {
+                                                          double* partials, const double* sig) {
     __shared__ double s[kRedThreads];
     __shared__ double sh[MB];
     if (ints[1]) return;
-    if (threadIdx.x < MB) sh[threadIdx.x] = (threadIdx.x <= j) ? H[threadIdx.x * M + j] : 0.0;
+    if (threadIdx.x < MB) {
+        const int c = threadIdx.x;
+        sh[c] = (c <= j) ? (sig ? H[c * M + j] * sig[c] : H[c * M + j]) : 0.0;
+    }
     __syncthreads();
     double h[MB];
 #pragma unroll
@@ -173,7 +188,8 @@ static int ls_bucket(int cols) {
 bool lowsync_supported(int M) { return M >= 1 && ls_bucket(M) > 0; }
 
 hipError_t launch_ls_column(const Work& W, const double* w, const double* V, long n, int M, int j, double* vnext,
-                            hipStream_t st) {
+                            hipStream_t st, bool deferred) {
+    const double* sig = deferred ? W.sig : nullptr;
     const int MB = ls_bucket(j + 1);
     if (MB == 0 || 2 * MB + 1 > W.npart) return hipErrorInvalidValue;   // r, s and the norm's partial columns
     double* part = W.partials;
@@ -190,12 +206,12 @@ hipError_t launch_ls_column(const Work& W, const double* w, const double* V, lon
         default: ROK_LS_DOTS(24); break;
     }
 #undef ROK_LS_DOTS
-    hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(kRedThreads), 0, st, part, MB, j, M, W.L, W.H, W.ints);
+    hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(kRedThreads), 0, st, part, MB, j, M, W.L, W.H, W.ints, sig);
     if (j + 1 < M) {
         double* npart = W.partials + (long)(W.npart - 1) * kRedBlocks;   // the last partial column
 #define ROK_LS_UPD(B)                                                                                            \
     hipLaunchKernelGGL((k_ls_update<B>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, w, W.H, n, j, M, vnext, \
-                       W.ints, npart)
+                       W.ints, npart, sig)
         switch (MB) {
             case 1: ROK_LS_UPD(1); break;
             case 2: ROK_LS_UPD(2); break;
@@ -207,8 +223,10 @@ hipError_t launch_ls_column(const Work& W, const double* w, const double* V, lon
             default: ROK_LS_UPD(24); break;
         }
 #undef ROK_LS_UPD
-        // ||w'|| finished in every block, breakdown test, v_{j+1} = w' / ||w'|| in place
-        launch_normalize(W, vnext, npart, M, j, vnext, n, st);
+        if (deferred)   // ||w'||, breakdown test, sig_{j+1} = 1 / ||w'||; the column stays w'
+            launch_norm_scale(W, npart, M, j, st);
+        else            // ||w'|| finished in every block, breakdown test, v_{j+1} = w' / ||w'|| in place
+            launch_normalize(W, vnext, npart, M, j, vnext, n, st);
     }
     return hipGetLastError();
 }

@@ -31,7 +31,7 @@ enum { MODE_PLAIN = 0, MODE_FD = 1, MODE_TAN = 2 };
 
 // Conserved state of one cell of the stage input.
 template <int MODE, int NV, typename S>
-__device__ __forceinline__ void load_state(const ResArgs& A, long ncell, long gi, double eps, S* U) {
+__device__ __forceinline__ void load_state(const ResArgs& A, long ncell, long gi, double eps, S* U, double vs = 1.0) {
     using R = typename Sc<S>::R;
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
@@ -43,7 +43,7 @@ __device__ __forceinline__ void load_state(const ResArgs& A, long ncell, long gi
         } else if constexpr (MODE == MODE_FD) {
             U[m] = Sc<S>::make(A.y[k] + eps * A.v[k]);
         } else {
-            U[m] = S{(R)A.y[k], (R)A.v[k]};
+            U[m] = S{(R)A.y[k], (R)(A.vscale ? A.v[k] * vs : A.v[k])};
         }
     }
 }
@@ -168,6 +168,12 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 
     double eps = 0.0;
     if constexpr (MODE == MODE_FD) eps = A.eps_dev ? *A.eps_dev : A.eps;
+    // a stored (not yet normalised) basis column: direction vs v
+    double vs = 1.0;
+    if constexpr (MODE != MODE_PLAIN) {
+        if (A.vscale) vs = *A.vscale;
+    }
+    const double eps_st = (MODE == MODE_FD && A.vscale) ? eps * vs : eps;   // increment applied to v
 
     // FP32: reference state = the primitive state of the box's centre cell,
     // rounded to float; the same float values (as doubles) are subtracted in
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
                 int gy = wrap(y0 - T::H + by, n1);
                 int gz = (D == 3) ? wrap(z0 - T::H + bz, n2) : 0;
                 long gi = ((long)gz * n1 + gy) * n0 + gx;
-                load_state<MODE, NV, S>(A, G.ncell, gi, eps, Ub[it]);
+                load_state<MODE, NV, S>(A, G.ncell, gi, eps_st, Ub[it], vs);
             }
         }
 #pragma unroll
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             long gi = ((long)gz * n1 + gy) * n0 + gx;
             using SD = typename Wide<S>::type;
             SD U[NV];
-            load_state<MODE, NV, SD>(A, G.ncell, gi, eps, U);
+            load_state<MODE, NV, SD>(A, G.ncell, gi, eps_st, U, vs);
             const SD r = U[0];
             const SD inv = recip(r);
             SD vel[D];
