@@ -8,8 +8,9 @@ Jacobian-vector products, fixed step at CFL 10.  Inputs are synthetic (seeded)
 and resident in HBM before the timed region starts.
 
 Prints one JSON line with the step rate, a roofline entry for the dominant
-kernel of the step (a modified Gram-Schmidt pass; timed live with HIP events
-on the launch stream) and for the FD product and residual kernels, the
+kernel of the step (the Arnoldi column by the one-reduce Gram-Schmidt, whose
+work vector does not fit on chip at this size; timed live with HIP events on
+the launch stream) and for the FD product and residual kernels, the
 Arnoldi share of the step against its algorithmic bytes, the precision form's
 rate on the same workload (FP32 residual and tangent products, FP64 Krylov)
 with its error, the 1024^2 MUSCL vortex as a secondary workload, the
@@ -205,6 +206,16 @@ def _timed(stream, launches):
     return sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
 
+def _ls_column_bytes(N, m):
+    """Bytes the kernels of a one-reduce column move, averaged over the m
+    columns of a basis (as rok_mgs_column runs them): k_ls_dots reads
+    v_0..v_j and w (j + 2 vectors), k_ls_update reads them again and writes
+    the next column (j + 3), k_normalize reads and writes it (2); the last
+    column runs k_ls_dots alone.  Inside rok_step the normalisation pass is
+    deferred (2j + 5 per column)."""
+    return sum(((j + 2) + ((j + 3) + 2 if j + 1 < m else 0)) * 8 * N for j in range(m)) / m
+
+
 def _traffic(path, sources, key, field="hbm_bytes_per_launch"):
     """A counter figure per launch (HBM bytes by default) stored for `key`, or None."""
     if not path or not os.path.exists(path):
@@ -296,11 +307,12 @@ def _mgs_roofline(args, g, y, M, mode, stream, ms_step):
         ms = sum(col_ms) / m
         alg = col_alg
         traffic = _traffic(tpath, LS_SOURCES, "ls_column")
-        kb = sum((2 * j + 4) * 8 * N + (16 * N if j + 1 < m else 0) for j in range(m)) / m
+        kb = _ls_column_bytes(N, m)
         kernel = (f"one-reduce Gram-Schmidt Arnoldi column (k_ls_dots, k_ls_solve, k_ls_update, k_normalize), "
                   f"average over the {m} columns of a step")
         extra = {"kernel_bytes_per_launch": int(kb),
-                 "timing": "one HIP event pair per column (its four launches)"}
+                 "timing": "one HIP event pair per column of rok_mgs_column (its four launches, the normalisation "
+                           "included; rok_step defers that pass)"}
     else:
         js = list(range(1, m))
         mj = sum(js) / len(js)
@@ -344,28 +356,36 @@ def _residual_roofline(args, g, y, w, stream):
 
 
 def _jvp_roofline(args, g, y, w, stream):
-    """The FD Jacobian-vector product kernel: reads y, v, f(y), writes w (32 B per element)."""
+    """The product kernel of the workload.  FP64: the FD Jacobian-vector
+    product, reads y, v, f(y), writes w (32 B per element).  FP32 form: the
+    exact (tangent) product in FP32, reads y and v, writes w in FP32 (20 B per
+    element; inside rok_step the same kernel writes FP64 for the Krylov side)."""
     import torch
-    if w["precision"] != "fp64":
-        return None
     N = g.N
     dev = y.device
-    F = g.residual(y)
     v = torch.randn(N, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
     v /= torch.linalg.vector_norm(v)
-    out = torch.empty(N, dtype=torch.float64, device=dev)
+    if w["precision"] == "fp64":
+        F = g.residual(y)
+        out = torch.empty(N, dtype=torch.float64, device=dev)
+        launch = lambda: g.jvp(y, v, "fd", fy=F, eps=1e-7, out=out)
+        alg, key = 4 * 8 * N, "fd_jvp"
+        kernel = "FD Jacobian-vector product (residual at y + eps v, minus f(y), over eps)"
+    else:
+        out = torch.empty(N, dtype=torch.float32, device=dev)
+        launch = lambda: g.jvp(y, v, "tangent", out=out)
+        alg, key = (8 + 8 + 4) * N, "tangent"
+        kernel = "exact (tangent) Jacobian-vector product, FP32 dual numbers in reference-state form"
     for _ in range(3):
-        g.jvp(y, v, "fd", fy=F, eps=1e-7, out=out)
+        launch()
     torch.cuda.synchronize()
-    ms = _timed(stream, [lambda: g.jvp(y, v, "fd", fy=F, eps=1e-7, out=out)] * args.kernel_reps)
-    alg = 4 * 8 * N
+    ms = _timed(stream, [launch] * args.kernel_reps)
     achieved = alg / (ms * 1e-3) / 1e9
-    traffic = _traffic(_traffic_path(args), RESIDUAL_SOURCES, "fd_jvp")
-    valu = _traffic(_traffic_path(args), RESIDUAL_SOURCES, "fd_jvp", "valu_insts_per_launch")
+    traffic = _traffic(_traffic_path(args), RESIDUAL_SOURCES, key)
+    valu = _traffic(_traffic_path(args), RESIDUAL_SOURCES, key, "valu_insts_per_launch")
     hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
-    common = {"kernel": "FD Jacobian-vector product (residual at y + eps v, minus f(y), over eps)",
-              "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": alg}
+    common = {"kernel": kernel, "avg_launch_ms": round(ms, 5), "alg_bytes_per_launch": alg}
     if valu is None:
         return dict(hbm, **common)
     # the binding roof: wave-level VALU instructions issued per second (SQ_INSTS_VALU per launch, counter run)
@@ -935,10 +955,14 @@ def build_traffic(workload, cdir, out_path):
     D = len(pb["n"])
     ns = "true" if pb["physics"] == "ns" else "false"
     single = {"mgs_pass": ("void rok::k_red<true, false>", KRED_SOURCES, 24 * N),
-              "mgs_column": (f"void rok::k_mgs_resident<{m}>", MGS_SOURCES, col_alg),
-              "fd_jvp": (f"void rok::k_residual<{D}, 1, {ns}, 0, 0, double, 1, double", RESIDUAL_SOURCES, 32 * N),
-              "residual": (f"void rok::k_residual<{D}, 1, {ns}, 0, 0, double, 0, double", RESIDUAL_SOURCES,
-                           16 * N)}
+              "mgs_column": (f"void rok::k_mgs_resident<{m}>", MGS_SOURCES, col_alg)}
+    res = f"void rok::k_residual<{D}, 1, {ns}, 0, 0, "
+    if w["precision"] == "fp64":
+        single["fd_jvp"] = (res + "double, 1, double", RESIDUAL_SOURCES, 32 * N)
+        single["residual"] = (res + "double, 0, double", RESIDUAL_SOURCES, 16 * N)
+    else:   # the API's FP32 products and residual write FP32
+        single["tangent"] = (res + "rok::Dual<float>, 2, float", RESIDUAL_SOURCES, 20 * N)
+        single["residual"] = (res + "float, 0, float", RESIDUAL_SOURCES, 12 * N)
     for key, (kn, src, alg) in single.items():
         f = vals(F, kn, "FETCH_SIZE")
         if not f:
@@ -957,7 +981,7 @@ def build_traffic(workload, cdir, out_path):
         tw = sum(sum(vals(W, k, "WRITE_SIZE")) for k in parts)
         tv = sum(sum(vals(V, k, "SQ_INSTS_VALU")) for k in parts)
         hbm = (tf * 1024 * fs + tw * 1024 * ws) / ncol
-        kb = sum((2 * j + 4) * 8 * N + (16 * N if j + 1 < m else 0) for j in range(m)) / m
+        kb = _ls_column_bytes(N, m)
         rec["ls_column"] = {"kernel": "one-reduce Gram-Schmidt column: " + ", ".join(p.split("::")[-1].rstrip("<")
                                                                                       for p in parts),
                             "columns": ncol, "fetch_kib_avg": round(tf / ncol, 1), "write_kib_avg": round(tw / ncol, 1),

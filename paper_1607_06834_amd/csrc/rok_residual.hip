@@ -135,10 +135,12 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     // of the staging list (s_slot maps a box cell to its slot), which keeps the
     // LDS of a block small enough for three blocks per CU
     constexpr bool PACKED = ST::LIST;
-    // the temperature p / rho is staged, except in packed FP64 boxes: there the
-    // two staged values of a face's cells are divided where it is needed (the
-    // same division of the same values: the same bits)
-    constexpr bool TSTAGED = NSV && (PERT || !PACKED);
+    // the temperature p / rho is staged, except in packed (3-D) boxes: there it
+    // is formed where a face needs it, in FP64 as the same division of the same
+    // staged values (the same bits), in the FP32 form as the perturbation
+    // T - T0 = (r0 p' - p0 rho') / (r0 (r0 + rho')) of the staged perturbations
+    // (no cancellation beyond that of T - T0 itself)
+    constexpr bool TSTAGED = NSV && !PACKED;
     constexpr int NP = OFF_P + 1 + (TSTAGED ? 1 : 0);
     constexpr int NSLOT = PACKED ? ST::N : T::BOX;
     constexpr int kFaceUnroll = (D == 2 && sizeof(S) == 8 && !PERT && FLUX == 0) ? 2 : 1;
@@ -146,6 +148,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     __shared__ S sq[NP][NSLOT];
     __shared__ S fb[NV][T::NFMAX];
     __shared__ unsigned short s_slot[PACKED ? T::BOX : 1];
+    // FP32 form: the tile's reference state (float, and as doubles)
+    __shared__ RefState<D, R> s_ref;
+    __shared__ double s_refd[D + 3];   // r0, u0[D], p0, T0 = p0 / r0
     // staged slot of box cell c (every cell the stencil reads is staged)
     auto slot = [&](int c) -> int {
         if constexpr (PACKED) return (int)s_slot[c];
@@ -153,8 +158,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     };
     // temperature of the cell in slot q
     auto temp = [&](int q) -> S {
-        if constexpr (TSTAGED) return sq[OFF_T][q];
-        else return sq[OFF_P][q] / sq[0][q];
+        if constexpr (TSTAGED) {
+            return sq[OFF_T][q];
+        } else if constexpr (PERT) {
+            const S rp = sq[0][q], pp = sq[OFF_P][q];
+            return (s_ref.r0 * pp - s_ref.p0 * rp) / (s_ref.r0 * (s_ref.r0 + rp));
+        } else {
+            return sq[OFF_P][q] / sq[0][q];
+        }
     };
 
     if (A.gate && A.gate_col + 1 < *A.gate) return;
@@ -178,8 +189,6 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     // FP32: reference state = the primitive state of the box's centre cell,
     // rounded to float; the same float values (as doubles) are subtracted in
     // FP64 below, so q0 + q' is consistent.
-    __shared__ RefState<D, R> s_ref;
-    __shared__ double s_refd[D + 3];   // r0, u0[D], p0, T0 = p0 / r0
     if constexpr (PERT) {
         if (tid == 0) {
             const int gx = wrap(x0 - T::H + T::BX / 2, n0);
