@@ -66,6 +66,7 @@ struct Tile {
 };
 
 constexpr int kThreads = 256;
+constexpr int kBandY = 4;   // 3-D tile order: rows of tiles along y per band
 
 // The box cells a tile reads: up to HW cells past the tile along one axis
 // (the reconstruction stencil of a face), and, for the viscous terms, one
@@ -172,9 +173,23 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     if (A.stop && *A.stop) return;
     const int tid = threadIdx.x;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int x0 = (b % nt0) * TX;
-    const int y0 = ((b / nt0) % nt1) * TY;
-    const int z0 = (D == 3) ? (b / (nt0 * nt1)) * TZ : 0;
+    int x0, y0, z0;
+    if (D == 3 && nt1 % kBandY == 0) {
+        // bands of kBandY tile rows along y, z running inside a band: the tiles
+        // above and below a tile (its z halo) are read about nt0 * kBandY tiles
+        // apart, within an XCD's L2, instead of a whole tile layer apart
+        const int nt2 = gridDim.x / (nt0 * nt1);
+        int r = b / nt0;
+        x0 = (b % nt0) * TX;
+        const int ty = r % kBandY;
+        r /= kBandY;
+        z0 = (r % nt2) * TZ;
+        y0 = ((r / nt2) * kBandY + ty) * TY;
+    } else {
+        x0 = (b % nt0) * TX;
+        y0 = ((b / nt0) % nt1) * TY;
+        z0 = (D == 3) ? (b / (nt0 * nt1)) * TZ : 0;
+    }
     const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
 
     double eps = 0.0;
