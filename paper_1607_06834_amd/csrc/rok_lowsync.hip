@@ -84,30 +84,41 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_dots(const double* V, const 
     }
 }
 
+constexpr int kSolveThreads = 4 * kRedThreads;   // four of the column's sums finished at once
+
 // One block: finish r and s (canonical final sums), store the Gram row in L
 // (row j, leading dimension M), solve (I + L) h = r by forward substitution in
 // index order and write h into column j of H.  NONFINITE on a non-finite h.
 // sig (non-null): the columns are stored unnormalised, q_c = sig_c V_c, and the
 // sums over the stored columns are scaled: r_c = sig_c <V_c, w>,
 // s_c = (sig_j sig_c) <V_j, V_c>.
-__global__ __launch_bounds__(kRedThreads) void k_ls_solve(const double* partials, int MB, int j, int M, double* L,
-                                                         double* H, int* ints, const double* sig) {
-    __shared__ double s[kRedThreads];
+__global__ __launch_bounds__(kSolveThreads) void k_ls_solve(const double* partials, int MB, int j, int M, double* L,
+                                                           double* H, int* ints, const double* sig) {
+    __shared__ double s[kSolveThreads];
     __shared__ double sr[kMaxM], ss[kMaxM];
     if (ints[1]) return;
     const int tid = threadIdx.x;
-    for (int c = 0; c <= j; ++c) {
+    const int grp = tid / kRedThreads, lane = tid % kRedThreads;
+    // sums q = 0..j are r_q (partial column q), q = j+1..2j are s_{q-j-1}
+    // (partial column MB + q - j - 1); each 256-thread group finishes one in
+    // the canonical order
+    const int nsum = 2 * j + 1;
+    for (int q0 = 0; q0 < nsum; q0 += kSolveThreads / kRedThreads) {
+        const int q = q0 + grp;
         double a = 0.0;
-        for (int b = tid; b < kRedBlocks; b += kRedThreads) a = a + partials[(long)c * kRedBlocks + b];
+        if (q < nsum) {
+            const long col = (q <= j) ? q : MB + (q - j - 1);
+            for (int b = lane; b < kRedBlocks; b += kRedThreads) a = a + partials[col * kRedBlocks + b];
+        }
         const double t = tree256(a, s);
-        if (tid == 0) sr[c] = sig ? t * sig[c] : t;
-        __syncthreads();
-    }
-    for (int c = 0; c < j; ++c) {
-        double a = 0.0;
-        for (int b = tid; b < kRedBlocks; b += kRedThreads) a = a + partials[(long)(MB + c) * kRedBlocks + b];
-        const double t = tree256(a, s);
-        if (tid == 0) ss[c] = sig ? t * (sig[j] * sig[c]) : t;
+        if (lane == 0 && q < nsum) {
+            if (q <= j) {
+                sr[q] = sig ? t * sig[q] : t;
+            } else {
+                const int c = q - j - 1;
+                ss[c] = sig ? t * (sig[j] * sig[c]) : t;
+            }
+        }
         __syncthreads();
     }
     if (tid != 0) return;
@@ -206,7 +217,7 @@ hipError_t launch_ls_column(const Work& W, const double* w, const double* V, lon
         default: ROK_LS_DOTS(24); break;
     }
 #undef ROK_LS_DOTS
-    hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(kRedThreads), 0, st, part, MB, j, M, W.L, W.H, W.ints, sig);
+    hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(kSolveThreads), 0, st, part, MB, j, M, W.L, W.H, W.ints, sig);
     if (j + 1 < M) {
         double* npart = W.partials + (long)(W.npart - 1) * kRedBlocks;   // the last partial column
 #define ROK_LS_UPD(B)                                                                                            \
