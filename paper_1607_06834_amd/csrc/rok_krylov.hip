@@ -272,10 +272,23 @@ __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const d
     const int tid = threadIdx.x;
     for (int c0 = 0; c0 < m; c0 += 16) {
         const int nc = (m - c0) < 16 ? (m - c0) : 16;
-        for (int c = 0; c < nc; ++c) {
-            double acc = 0.0;
-            for (int b = tid; b < kRedBlocks; b += kRedThreads) acc = acc + partials[(long)(c0 + c) * kRedBlocks + b];
-            s[c][tid] = acc;
+        // lane tid adds partials tid, tid + 256, tid + 512, tid + 768 of each column in
+        // order; the loads of all 16 columns are issued before any sum waits
+        static_assert(kRedBlocks == 4 * kRedThreads, "four partials per lane");
+        double pv[16][4];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                pv[c][q] = (c < nc) ? partials[(long)(c0 + c) * kRedBlocks + tid + q * kRedThreads] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            if (c < nc) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc = acc + pv[c][q];
+                s[c][tid] = acc;
+            }
         }
         __syncthreads();
         for (int st = kRedThreads / 2; st > 0; st >>= 1) {

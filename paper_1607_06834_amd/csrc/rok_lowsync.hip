@@ -103,13 +103,26 @@ __global__ __launch_bounds__(kSolveThreads) void k_ls_solve(const double* partia
     // (partial column MB + q - j - 1); each 256-thread group finishes one in
     // the canonical order
     const int nsum = 2 * j + 1;
-    for (int q0 = 0; q0 < nsum; q0 += kSolveThreads / kRedThreads) {
+    constexpr int G = kSolveThreads / kRedThreads;            // sums per round
+    constexpr int R = (2 * 24 - 1 + G - 1) / G;              // rounds for the widest column (M <= 24)
+    static_assert(kRedBlocks == 4 * kRedThreads, "four partials per lane");
+    // every partial this lane adds, loaded before any sum waits
+    double pv[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = r * G + grp;
+        const long col = (q <= j) ? q : MB + (q - j - 1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pv[r][u] = (q < nsum) ? partials[col * kRedBlocks + lane + u * kRedThreads] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q0 = r * G;
+        if (q0 >= nsum) break;
         const int q = q0 + grp;
         double a = 0.0;
-        if (q < nsum) {
-            const long col = (q <= j) ? q : MB + (q - j - 1);
-            for (int b = lane; b < kRedBlocks; b += kRedThreads) a = a + partials[col * kRedBlocks + b];
-        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a = a + pv[r][u];
         const double t = tree256(a, s);
         if (lane == 0 && q < nsum) {
             if (q <= j) {
