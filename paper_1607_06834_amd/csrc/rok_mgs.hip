@@ -154,12 +154,31 @@ __device__ __forceinline__ bool collect(double* part, int phase, unsigned* bar, 
 // devices: data format 32 (a zero format would make every access out of range).
 constexpr int kBufWord3 = 0x00020000;
 
+// Sixteenths of the next basis vector the waves 1-15 load before a pass's
+// exchange (the rest right after it).  Measured at 1024^2, column time in
+// HIP events: all before 105.7 us, half 103.4 us, a quarter 105.1 us, none
+// 106.0 us.
+constexpr int kPrefetchEarly = 8;
+
 // x[k] = src[t + k T] for the chunks of lane t that lie below n, +0.0 past
 // the end.  Raw buffer loads with the range n * 8 bytes: an offset past the
 // range reads as zero without touching memory, so the loads need no per-lane
 // condition (no exec-masked branches, whose joins would make the compiler
 // wait for every outstanding load, prefetches included).  All offsets are in
 // the lane's offset register, which is what the range check covers.
+// chunks k0 <= k < k1 only (the rest of x untouched)
+template <int PER, int K0, int K1, int AUX>
+__device__ __forceinline__ void load_chunks(const double* __restrict__ src, long n, int t, double (&x)[PER]) {
+    constexpr int T = kPB * kPT;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(src), (short)0, (int)(n * 8), kBufWord3);
+    int off = t * 8;
+    asm volatile("" : "+v"(off));
+#pragma unroll
+    for (int k = K0; k < K1; ++k)
+        x[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off + k * T * 8, 0, AUX));
+}
+
 template <int PER, int AUX = 0>
 __device__ __forceinline__ void load_lane(const double* __restrict__ src, long n, int t, double (&x)[PER]) {
     constexpr int T = kPB * kPT;
@@ -260,7 +279,10 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
         // waits for every outstanding load, the prefetch included
         asm volatile("" : "+v"(acc) : : "memory");
         const bool more = i < j;
-        if (more && prefetch) load_lane<PER, 2>(V + (long)(i + 1) * n, n, t, prev);
+        // waves 1-15: the first kPrefetchEarly sixteenths of v_{i+1} before the exchange, the
+        // rest after it (the exchange's loads queue behind whatever stream is in flight)
+        constexpr int KS = (PER * kPrefetchEarly) / 16;
+        if (more && prefetch) load_chunks<PER, 0, KS, 2>(V + (long)(i + 1) * n, n, t, prev);
         publish(acc, s, s_gs);
         // unconditional (v_j again after the last pass, 64 lanes' worth), so
         // that the sum's waits count exactly these loads behind the partials
@@ -270,6 +292,7 @@ __global__ __launch_bounds__(kPT) void k_mgs_resident(const double* wsrc, const 
             return;
         }
         phase ^= 1;
+        if (more && prefetch) load_chunks<PER, KS, PER, 2>(V + (long)(i + 1) * n, n, t, prev);
         if (threadIdx.x == 0) s_hcol[i] = h;
         if (blockIdx.x == 0 && threadIdx.x == 0) H[i * M + j] = h;
     };
