@@ -152,20 +152,17 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
         e = rok::launch_lu(W, M, h * tab->gamma, st);
         if (e != hipSuccess) return e;
     }
+    // Y_i = y_n + sum_{j<i} alpha_ij k_j is written by the recovery of k_{i-1}
+    // (into k_i's slot, free until k_i is formed), in the residual's order
+    auto has_terms = [&](int i) {
+        for (int j = 0; j < i; ++j)
+            if (tab->alpha[i * ROK_MAX_STAGES + j] != 0.0) return true;
+        return false;
+    };
     for (int i = 0; i < s; ++i) {
         double* Fi = W.F + (long)i * N;
         if (i > 0) {
-            rok::ResArgs A = plain_args(y_n, Fi);
-            int t = 0;
-            for (int j = 0; j < i; ++j) {
-                double a = tab->alpha[i * ROK_MAX_STAGES + j];
-                if (a != 0.0) {
-                    A.xs[t] = W.K + (long)j * N;
-                    A.cs[t] = a;
-                    ++t;
-                }
-            }
-            A.nterm = t;
+            rok::ResArgs A = plain_args(has_terms(i) ? W.K + (long)i * N : y_n, Fi);
             A.status = W.ints + 2;
             e = rok::launch_residual(c->G, c->pb.recon, ns, fp32(c), 0, true, A, st);
             if (e != hipSuccess) return e;
@@ -178,7 +175,10 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
             e = rok::launch_lambda(W, M, i, grow, h, st, sig);
             if (e != hipSuccess) return e;
         }
-        if (i + 1 < s)
+        if (i + 1 < s && has_terms(i + 1))
+            e = rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, y_n, W.K, 0, nullptr, st, sig,
+                                    W.K + (long)(i + 1) * N, tab->alpha + (i + 1) * ROK_MAX_STAGES);
+        else if (i + 1 < s)
             e = rok::launch_recover(W, W.V, Fi, N, M, i, h, W.K + (long)i * N, nullptr, nullptr, 0, nullptr, st, sig);
         else
             e = rok::launch_recover(W, W.V, Fi, N, M, i, h, y_np1, y_n, W.K, s, tab->b, st, sig);

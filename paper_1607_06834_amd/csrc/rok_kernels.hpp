@@ -96,9 +96,10 @@ hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, dou
                          const double* sig = nullptr);
 // k_i = V lambda_i + h (F_i - V phi_i) into k; if y is non-null (last stage)
 // writes y_{n+1} = y + sum_{q<s} b_q k_q into k instead, K holding k_0..k_{s-2}.
+// With ynext (stages i < s - 1; y and K given): also Y_{i+1} = y + sum_{q<=i} arow[q] k_q into ynext.
 hipError_t launch_recover(const Work& W, const double* V, const double* F, long n, int M, int i, double h, double* k,
                           const double* y, const double* K, int s, const double* b, hipStream_t st,
-                          const double* sig = nullptr);
+                          const double* sig = nullptr, double* ynext = nullptr, const double* arow = nullptr);
 
 // Discrete adjoint of the ROK step (rok_step_adjoint.hip).  Carved after the
 // forward step's workspace; lambar, phibar are s x M, Hbar (M+1) x M, Abar

@@ -391,13 +391,17 @@ struct BRow {
 };
 
 // k = V lambda + h (F - V phi), column sums in order from zero.  FINAL: the
-// last stage, which writes y_{n+1} = y + sum_i b_i k_i instead of k
+// last stage, which writes y_{n+1} = y + sum_i b_i k_i instead of k.  Other
+// stages i with ynext: also the next stage's input Y_{i+1} = y + sum_{q<=i}
+// a_q k_q (a = row i + 1 of alpha; terms with a_q = 0 skipped, k_i from
+// registers), in the order the residual forms it from y and the k_q
 // (sum in stage order, terms with b_i = 0 skipped).
 template <int MB, bool FINAL>
 __global__ __launch_bounds__(256) void k_recover(const double* __restrict__ V, const double* __restrict__ F, long n,
                                                 const int* ints, const double* lam, const double* phi, double h,
                                                 double* __restrict__ k, const double* __restrict__ y,
-                                                const double* __restrict__ K, int s, BRow br, const double* sig) {
+                                                const double* __restrict__ K, int s, BRow br, const double* sig,
+                                                double* __restrict__ ynext, int stage, BRow ar) {
     const int m = ints[0];
     // columns stored unnormalised (v_c = sig_c V_c): the scales go into the coefficients
     auto lamc = [&](int c) { return sig ? lam[c] * sig[c] : lam[c]; };
@@ -438,6 +442,13 @@ __global__ __launch_bounds__(256) void k_recover(const double* __restrict__ V, c
             k[e] = acc;
         } else {
             k[e] = ke;
+            if (ynext) {
+                double acc = ld_stream(y + e);
+                for (int q = 0; q < stage; ++q)
+                    if (ar.b[q] != 0.0) acc = acc + ar.b[q] * ld_stream(K + (long)q * n + e);
+                if (ar.b[stage] != 0.0) acc = acc + ar.b[stage] * ke;
+                ynext[e] = acc;
+            }
         }
     }
 }
@@ -690,18 +701,21 @@ hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, dou
 
 hipError_t launch_recover(const Work& W, const double* V, const double* F, long n, int M, int i, double h, double* k,
                           const double* y, const double* K, int s, const double* b, hipStream_t st,
-                          const double* sig) {
+                          const double* sig, double* ynext, const double* arow) {
     int Mm = M > 0 ? M : 1;
-    BRow br{};
+    BRow br{}, ar{};
     for (int q = 0; q < kMaxStages; ++q) br.b[q] = (b && q < s) ? b[q] : 0.0;
+    for (int q = 0; q < kMaxStages; ++q) ar.b[q] = (arow && q <= i) ? arow[q] : 0.0;
+    if (ynext && (!y || !K)) return hipErrorInvalidValue;
+    const bool fin = y && !ynext;   // the last stage: y_{n+1} into k
     const double* lam = W.lam + (long)i * Mm;
     const double* phi = W.phi + (long)i * Mm;
     const unsigned g = grid_for(n, 256);
 #define ROK_REC(MB)                                                                                             \
-    if (y) hipLaunchKernelGGL((k_recover<MB, true>), dim3(g), dim3(256), 0, st, V, F, n, W.ints, lam, phi, h, k, \
-                              y, K, s, br, sig);                                                                \
+    if (fin) hipLaunchKernelGGL((k_recover<MB, true>), dim3(g), dim3(256), 0, st, V, F, n, W.ints, lam, phi, h,  \
+                                k, y, K, s, br, sig, nullptr, 0, ar);                                         \
     else hipLaunchKernelGGL((k_recover<MB, false>), dim3(g), dim3(256), 0, st, V, F, n, W.ints, lam, phi, h, k,  \
-                            y, K, s, br, sig)
+                            y, K, s, br, sig, ynext, i, ar)
     ROK_MB_SWITCH(mbucket(M > 0 ? M : 1), ROK_REC)
 #undef ROK_REC
     return hipGetLastError();
