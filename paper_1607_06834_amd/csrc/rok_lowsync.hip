@@ -150,7 +150,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_ls_solve(const double* partia
 // basis column, distinct from V's columns 0..j and from w), partials of
 // ||w'||^2 at `partials`.  Two elements of a lane per iteration, both loaded
 // before either is stored (the lane's sum keeps index order).  With sig, the
-// coefficient of stored column c is h_c sig_c.
+// coefficient of stored column c is h_c sig_c.  The column is stored with the
+// non-temporal hint (it is read again only by the next product, from HBM).
 template <int MB>
 __global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* __restrict__ V,
                                                           const double* __restrict__ w, const double* H, long n,
@@ -184,8 +185,8 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* __restr
                 x0 = x0 - h[c] * q0[c];
                 x1 = x1 - h[c] * q1[c];
             }
-        out[e] = x0;
-        out[e + stride] = x1;
+        __builtin_nontemporal_store(x0, out + e);
+        __builtin_nontemporal_store(x1, out + e + stride);
         acc = acc + x0 * x0;
         acc = acc + x1 * x1;
     }
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_update(const double* __restr
 #pragma unroll
         for (int c = 0; c < MB; ++c)
             if (c <= j) x = x - h[c] * ld_stream(V + (long)c * n + e);
-        out[e] = x;
+        __builtin_nontemporal_store(x, out + e);
         acc = acc + x * x;
     }
     const double b = tree256(acc, s);

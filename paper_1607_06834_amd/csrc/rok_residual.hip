@@ -332,6 +332,21 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
         __syncthreads();
     }
 
+    // FD: the loads of f(y) at this thread's output cells are issued here and
+    // complete behind the face loops; they are needed only at the write-out
+    double f0pre[CPT][NV];
+    if constexpr (MODE == MODE_FD) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int cell = tid + k * kThreads;
+            const int gx = x0 + cell % TX, gy = y0 + (cell / TX) % TY, gz = z0 + cell / (TX * TY);
+            const bool in = gx < n0 && gy < n1 && (D != 3 || gz < n2);
+            const long gi = in ? ((long)gz * n1 + gy) * n0 + gx : 0;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) f0pre[k][m] = in ? A.f0[(long)m * G.ncell + gi] : 0.0;
+        }
+    }
+
     S res[CPT][NV];
 
 #pragma unroll
@@ -666,7 +681,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
             if constexpr (MODE == MODE_PLAIN) {
                 x = (OUT)res[k][m];
             } else if constexpr (MODE == MODE_FD) {
-                x = (OUT)((res[k][m] - A.f0[o]) / eps);
+                x = (OUT)((res[k][m] - f0pre[k][m]) / eps);
             } else {
                 x = (OUT)res[k][m].d;
             }
