@@ -81,9 +81,9 @@ def _nan(pb, y, cell):
     return U.reshape(-1)
 
 
-def _flags(dev, pb, precision, y, M, mode):
+def _flags(dev, pb, precision, y, M, mode, mgs="auto"):
     from paper_1607_06834_amd import Rok
-    g = Rok(pb, precision)
+    g = Rok(pb, precision, mgs)
     tab = ri.rok4_tableau()
     h = ri.cfl_step(pb, _initial(pb), 2.0)
     g.step(torch.tensor(y, device=dev), h, tab, M, mode)
@@ -143,6 +143,29 @@ def test_nan_state_sets_nonfinite_only(dev, name):
         f = _flags(dev, pb, prec, y, M, mode)
         assert f & NONFINITE, f
         assert not (f & NONPHYSICAL), f
+
+
+@pytest.mark.parametrize("name", ["euler2d_muscl", "ns3d_muscl", "ns2d_muscl_fp32", "ns3d_muscl_fp32"])
+def test_flags_same_on_every_gram_schmidt_form(dev, name):
+    """The status word does not depend on how the basis is orthogonalised: the
+    one-reduce form (whose columns rok_step keeps unnormalised, with their scales
+    on the device) and the pass-by-pass form report the flags of the resident
+    form, for a physical state, a negative pressure and a NaN."""
+    make, prec = CASES[name]
+    pb = make()
+    ncell = int(np.prod(pb["n"]))
+    y0 = _initial(pb)
+    states = [("physical", y0), ("negative pressure", _negative_pressure(pb, y0, ncell // 3)),
+              ("nan", _nan(pb, y0, ncell // 5))]
+    for label, y in states:
+        for mode, M in _modes(prec):
+            if M == 0:
+                continue   # no basis
+            ref = _flags(dev, pb, prec, y, M, mode)
+            for mgs in ("one_reduce", "pass"):
+                f = _flags(dev, pb, prec, y, M, mode, mgs)
+                say(label, name, mode, M, mgs, f, "resident:", ref)
+                assert f == ref
 
 
 def test_flags_cleared_by_next_step(dev):
