@@ -304,6 +304,47 @@ def test_rok_step_parity(dev, mode, recon, M, mgs):
         assert torch.equal(out, ref)             # canonical arithmetic: bit for bit
 
 
+def _dense_tableau(s, seed):
+    """A seeded s-stage table with every alpha_ij (j < i), gamma_ij (j < i) and b_i
+    nonzero: no order, only arithmetic to compare (each stage input then has
+    several terms, each lambda_i several gamma terms)."""
+    rng = np.random.default_rng(seed)
+    alpha = [[0.0] * 4 for _ in range(4)]
+    gam = [[0.0] * 4 for _ in range(4)]
+    for i in range(s):
+        for j in range(i):
+            alpha[i][j] = float(rng.uniform(0.1, 0.4))
+            gam[i][j] = float(rng.uniform(-0.3, 0.3))
+    b = [float(x) for x in rng.uniform(0.1, 0.4, s)]
+    return {"s": s, "alpha": alpha, "gam": gam, "gamma": 0.43, "b": b}
+
+
+@pytest.mark.parametrize("mgs", ["auto", "one_reduce", "pass"])
+@pytest.mark.parametrize("mode", ["fd", "exact"])
+def test_dense_tableau_step_parity(dev, mode, mgs):
+    """Every stage input a sum of several stages (formed by the recovery of the
+    previous stage), every lambda several gamma terms, every b nonzero: the step
+    against the oracle's eq. (9) with the same table (FD steps bit for bit on the
+    resident and pass-by-pass forms; the one-reduce form within its tolerances)."""
+    pb = ri.vortex_problem(24, "muscl")
+    pb["n"] = (24, 20)
+    P = oracle_problem(pb)
+    y = t64(ri.perturb_density(pb, ri.vortex_state(pb), 0.01, seed=13))
+    h = ri.cfl_step(pb, y.numpy(), 1.0)
+    tab = _dense_tableau(4, 29)
+    f, mv = rok.fv_system(P, mode)
+    ref = rok.rok_step(f, mv, tab, 8, h, y)
+    g = gpu(pb, mgs=mgs)
+    out = g.step(y.to(dev), h, tab, 8, "fd" if mode == "fd" else "exact").cpu()
+    flags, meff = g.last_status()
+    e, ei = relerr(out, ref), relerr(out - y, ref - y)
+    say("dense tableau", mode, mgs, f"{e:.2e} (increment {ei:.2e})", "bitwise" if torch.equal(out, ref) else "")
+    assert meff == 8 and flags == 0
+    assert e <= 1e-12 and ei <= 1e-10
+    if mode == "fd" and mgs != "one_reduce":
+        assert torch.equal(out, ref)
+
+
 def test_vortex32_first_order_trajectory(dev):
     """32^2 vortex, first order, FD products, M = 8, 10 steps at CFL 5."""
     pb, y0, w = ri.workload("vortex32_fo")
