@@ -136,12 +136,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
     // of the staging list (s_slot maps a box cell to its slot), which keeps the
     // LDS of a block small enough for three blocks per CU
     constexpr bool PACKED = ST::LIST;
-    // the temperature p / rho is staged only in unpacked FP64 boxes; elsewhere it
+    // the temperature p / rho is staged, except in packed (3-D) boxes: there it
     // is formed where a face needs it, in FP64 as the same division of the same
     // staged values (the same bits), in the FP32 form as the perturbation
-    // T - T0 = (r0 p' - p0 rho') / (r0 (r0 + rho')) of the staged perturbations
-    // (no cancellation beyond that of T - T0 itself)
-    constexpr bool TSTAGED = NSV && !PACKED && !PERT;
+    // T - T0 = (r0 p' - p0 rho') / (r0 (r0 + rho')) of the staged perturbations.
+    // The FP32 form keeps staging it in 2-D, where LDS allows: the two
+    // products nearly cancel for near-isentropic perturbations, which costs
+    // about half a bit (a transonic 2-D Roe state: 2.9e-6 against 2.0e-6)
+    constexpr bool TSTAGED = NSV && !PACKED;
     constexpr int NP = OFF_P + 1 + (TSTAGED ? 1 : 0);
     constexpr int NSLOT = PACKED ? ST::N : T::BOX;
     constexpr int kFaceUnroll = (D == 2 && sizeof(S) == 8 && !PERT && FLUX == 0) ? 2 : 1;
