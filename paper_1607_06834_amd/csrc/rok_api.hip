@@ -168,7 +168,9 @@ hipError_t step_core(const rok_ctx* c, const rok_tableau* tab, int M, int mode, 
             if (e != hipSuccess) return e;
         }
         if (M > 0) {
-            e = rok::launch_project(W, W.V, Fi, N, M, st);
+            // with the one-reduce basis (not the library's bitwise path) the first stage's
+            // projection is taken from F_1 = beta v_0 instead of a pass over the basis
+            e = (i == 0 && deferred) ? rok::launch_project_first(W, M, st) : rok::launch_project(W, W.V, Fi, N, M, st);
             if (e != hipSuccess) return e;
             double grow[ROK_MAX_STAGES];
             for (int j = 0; j < ROK_MAX_STAGES; ++j) grow[j] = (j < i) ? tab->gam[i * ROK_MAX_STAGES + j] : 0.0;

@@ -91,6 +91,8 @@ double ritz_residual(int m, const double* H, int ldh, double hlast, double tre, 
 hipError_t launch_copy_h(const Work& W, int M, double* Hout, int* meff_out, hipStream_t st);
 hipError_t launch_lu(const Work& W, int M, double hg, hipStream_t st);
 hipError_t launch_project(const Work& W, const double* V, const double* F, long n, int M, hipStream_t st);
+// phi_1 = beta e_1 (F_1 = f(y_n) = beta v_0) as projection partials, without reading V
+hipError_t launch_project_first(const Work& W, int M, hipStream_t st);
 // sig: the basis scales (W.sig) when V holds unnormalised columns, else null
 hipError_t launch_lambda(const Work& W, int M, int i, const double* gam_row, double h, hipStream_t st,
                          const double* sig = nullptr);

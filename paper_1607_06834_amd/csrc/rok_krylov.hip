@@ -682,6 +682,22 @@ static int mbucket(int M) {
         default: CALL(64); break;      \
     }
 
+// The first stage's projection without a pass over the basis: F_1 = f(y_n) =
+// beta v_0 (the basis starts from it), so phi_1 = V^T F_1 = beta e_1 in exact
+// arithmetic.  Leaves partials that k_lambda finishes to exactly that:
+// column 0 holds beta in its first partial, every other partial is zero.
+__global__ __launch_bounds__(kRedThreads) void k_project_first(int M, const double* scal, double* partials) {
+    const long t = (long)blockIdx.x * kRedThreads + threadIdx.x;
+    if (t < (long)M * kRedBlocks) partials[t] = (t == 0) ? scal[2] : 0.0;
+}
+
+hipError_t launch_project_first(const Work& W, int M, hipStream_t st) {
+    const long n = (long)(M > 0 ? M : 1) * kRedBlocks;
+    hipLaunchKernelGGL(k_project_first, dim3((unsigned)((n + kRedThreads - 1) / kRedThreads)), dim3(kRedThreads), 0,
+                       st, M, W.scal, W.partials);
+    return hipGetLastError();
+}
+
 hipError_t launch_project(const Work& W, const double* V, const double* F, long n, int M, hipStream_t st) {
 #define ROK_PROJ(MB) \
     hipLaunchKernelGGL((k_project<MB>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, F, n, W.ints, W.partials)
