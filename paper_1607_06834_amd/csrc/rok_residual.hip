@@ -25,6 +25,8 @@
 #include "rok_kernels.hpp"
 #include "rok_flux.hpp"
 
+#include <algorithm>
+
 namespace rok {
 
 enum { MODE_PLAIN = 0, MODE_FD = 1, MODE_TAN = 2 };
@@ -700,6 +702,355 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 // Launchers
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// 3-D MUSCL residual and FD product, FP64, Cartesian grid: column-marching form.
+// A block owns a 16 x 16 column of cells over a range of planes and walks up
+// z.  Three staged planes (z - 1, z, z + 1: primitive variables over the
+// 20 x 20 halo'd region) sit in LDS; the block's own cells of plane z + 2 come
+// straight from HBM into registers (the z face's reconstruction needs them
+// one plane early) and are staged from there one plane later, with the 144
+// halo cells, so every cell is loaded once per range.  Each thread computes
+// the x face and the y face on the low side of its cell and the z face above
+// it, and exchanges fluxes with its neighbours by lane shuffles; the faces on
+// the column's +x and +y edges are computed by two waves and passed through a
+// small LDS buffer.  LDS per block stays under a third of the CU's, so three
+// blocks (12 waves) share a CU.  Every face flux and every cell sum is the
+// same sequence of operations on the same values as in k_residual (the same
+// bits).
+// ---------------------------------------------------------------------------
+constexpr int kZW = 20;              // staged plane width (16 + 2 + 2)
+constexpr int kZR = kZW * kZW;       // cells of a staged plane
+constexpr int kZHalo = kZR - 256;    // its halo cells
+constexpr int kZBlocks = 768;        // three resident blocks on each of 256 CUs
+
+struct ZRef {
+    int s, c;   // LDS slot, index in the staged plane
+};
+
+// primitive variables (rho, u, v, w, p) of a conserved state, in the staging
+// order of k_residual; returns whether rho <= 0 or p <= 0
+__device__ __forceinline__ bool zprim(const Geom& G, const double* U, double* q) {
+    const double gm1 = G.gm1;
+    const double half = 0.5;
+    const double r = U[0];
+    double vel[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) vel[e] = U[1 + e] / r;
+    double ke = vel[0] * vel[0];
+#pragma unroll
+    for (int e = 1; e < 3; ++e) ke = ke + vel[e] * vel[e];
+    const double p = gm1 * (U[4] - (half * r) * ke);
+    q[0] = r;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) q[1 + e] = vel[e];
+    q[4] = p;
+    return r <= 0.0 || p <= 0.0;
+}
+
+// The flux through one face along d between cells a and b = a + e_d:
+// MUSCL-minmod reconstruction from the primitive states (qm, qa, qb, qp) of
+// the cells a - e_d, a, b, b + e_d, the inviscid flux and, with NSV, the
+// central viscous flux with the tangential derivatives from the neighbours
+// ta / tb (+/- along each direction bb != d, read from the staged planes).
+template <int d, bool NSV, int FLUX>
+__device__ __forceinline__ void zface(const Geom& G, int viscous_only, const double (*ring)[5][kZR],
+                                      const double (&qm)[5], const double (&qa)[5], const double (&qb)[5],
+                                      const double (&qp)[5], const ZRef (&tap)[3], const ZRef (&tam)[3],
+                                      const ZRef (&tbp)[3], const ZRef (&tbm)[3], double* Fh) {
+    auto V = [&](ZRef r, int k) -> double { return ring[r.s][k][r.c]; };
+    const double half = 0.5;
+    double qL[5], qR[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double am1 = qm[k], a0 = qa[k], ap1 = qb[k], ap2 = qp[k];
+        const double sl = minmod(a0 - am1, ap1 - a0);
+        const double sr = minmod(ap1 - a0, ap2 - ap1);
+        qL[k] = a0 + half * sl;
+        qR[k] = ap1 - half * sr;
+    }
+    double UL[5], UR[5], vL[3], vR[3];
+    const double rL = qL[0], rR = qR[0];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        vL[e] = qL[1 + e];
+        vR[e] = qR[1 + e];
+    }
+    const double pL = qL[4], pR = qR[4];
+    to_conserved<3>(G, rL, vL, pL, UL);
+    to_conserved<3>(G, rR, vR, pR, UR);
+    num_flux<3, FLUX>(G, d, UL, rL, vL, pL, UR, rR, vR, pR, Fh);
+    if constexpr (NSV) {
+        if (viscous_only) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) Fh[m] = 0.0;
+        }
+        const double mu = G.mu, c23mu = G.c23mu, kappa = G.kappa;
+        double Gr[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+                if (bb == d) {
+                    Gr[a][bb] = (qb[1 + a] - qa[1 + a]) * G.invdx[d];
+                } else {
+                    const double h = G.hinv[bb];
+                    double gca = (V(tap[bb], 1 + a) - V(tam[bb], 1 + a)) * h;
+                    double gcb = (V(tbp[bb], 1 + a) - V(tbm[bb], 1 + a)) * h;
+                    Gr[a][bb] = half * (gca + gcb);
+                }
+            }
+        }
+        double div = Gr[0][0];
+#pragma unroll
+        for (int a = 1; a < 3; ++a) div = div + Gr[a][a];
+        const double Ta = qa[4] / qa[0], Tb = qb[4] / qb[0];
+        auto viscous = [&](double mu_, double c23mu_, double kappa_) {
+            double work;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double tau = (a == d) ? mu_ * (Gr[a][d] + Gr[d][a]) - c23mu_ * div : mu_ * (Gr[a][d] + Gr[d][a]);
+                double uf = half * (qa[1 + a] + qb[1 + a]);
+                work = (a == 0) ? uf * tau : work + uf * tau;
+                Fh[1 + a] = Fh[1 + a] - tau;
+            }
+            double dTdn = (Tb - Ta) * G.invdx[d];
+            Fh[4] = Fh[4] - (work + kappa_ * dTdn);
+        };
+        if (G.suth) {
+            double Tf = half * (Ta + Tb);
+            const double th = Tf / G.t_ref;
+            const double muf = mu * th * sqrt(th) * G.suth_one_s / (th + G.suth_s);
+            viscous(muf, (2.0 / 3.0) * muf, muf * G.g / G.kden);
+        } else {
+            viscous(mu, c23mu, kappa);
+        }
+    }
+}
+
+// index in the staged plane of halo cell h (0 <= h < kZHalo): rows 0, 1, 18,
+// 19 whole, then columns 0, 1, 18, 19 of rows 2 .. 17
+__device__ __forceinline__ int zhalo(int h) {
+    if (h < 2 * kZW) return h;
+    if (h < 4 * kZW) return 16 * kZW + h;
+    const int k = h - 4 * kZW, c = k & 3;
+    return (2 + (k >> 2)) * kZW + (c < 2 ? c : c + 16);
+}
+
+template <bool NSV, int FLUX, int MODE>
+__global__ __launch_bounds__(kThreads, (NSV && FLUX == 1) ? 2 : 3) void k_res3z(Geom G, ResArgs A, int nbx, int nby, int nch) {
+    __shared__ double ring[3][5][kZR];
+    __shared__ double fedge_x[5][16];      // x faces on the column's +x edge, by row
+    __shared__ double frow_y[5][5][16];    // y faces below rows 0, 4, 8, 12 and above row 15
+    if (A.gate && A.gate_col + 1 < *A.gate) return;
+    if (A.stop && *A.stop) return;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4, wv = tid >> 6, lane = tid & 63;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ncol = nbx * nby, col = b % ncol, ch = b / ncol;
+    const int x0 = (col % nbx) * 16, y0 = (col / nbx) * 16;
+    const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+    const int zs = (int)((long)ch * n2 / nch), ze = (int)((long)(ch + 1) * n2 / nch);
+    double eps = 0.0;
+    if constexpr (MODE == MODE_FD) eps = A.eps_dev ? *A.eps_dev : A.eps;
+    double vs = 1.0;
+    if constexpr (MODE != MODE_PLAIN) {
+        if (A.vscale) vs = *A.vscale;
+    }
+    const double eps_st = (MODE == MODE_FD && A.vscale) ? eps * vs : eps;
+    int np = 0;
+    const int c0 = (ty + 2) * kZW + (tx + 2);          // this thread's cell in a staged plane
+    const int hc = tid < kZHalo ? zhalo(tid) : c0;      // the halo cell it stages
+    auto gidx = [&](int z, int c) -> long {
+        const int gx = wrap(x0 - 2 + c % kZW, n0), gy = wrap(y0 - 2 + c / kZW, n1);
+        return ((long)wrap(z, n2) * n1 + gy) * n0 + gx;
+    };
+    auto load_prim = [&](int z, int c, double* q) {
+        double U[5];
+        load_state<MODE, 5, double>(A, G.ncell, gidx(z, c), eps_st, U, vs);
+        np |= zprim(G, U, q) ? 1 : 0;
+    };
+    auto stage_halo = [&](int z, int s) {
+        if (tid < kZHalo) {
+            double q[5];
+            load_prim(z, hc, q);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) ring[s][k][hc] = q[k];
+        }
+    };
+    int sA = 0, sB = 1, sC = 2;   // slots of planes z - 1, z, z + 1
+    {
+        double q[5];
+#pragma unroll 1
+        for (int i = 0; i < 3; ++i) {
+            load_prim(zs - 1 + i, c0, q);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) ring[i][k][c0] = q[k];
+            stage_halo(zs - 1 + i, i);
+        }
+    }
+    double Fdown[5];   // flux through the z face below this thread's cell
+    {
+        double qm[5], qa[5], qb[5], qp[5];
+        load_prim(zs - 2, c0, qm);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            qa[k] = ring[0][k][c0];
+            qb[k] = ring[1][k][c0];
+            qp[k] = ring[2][k][c0];
+        }
+        ZRef tap[3], tam[3], tbp[3], tbm[3];
+        tap[0] = {0, c0 + 1};   tam[0] = {0, c0 - 1};   tbp[0] = {1, c0 + 1};   tbm[0] = {1, c0 - 1};
+        tap[1] = {0, c0 + kZW}; tam[1] = {0, c0 - kZW}; tbp[1] = {1, c0 + kZW}; tbm[1] = {1, c0 - kZW};
+        tap[2] = tam[2] = tbp[2] = tbm[2] = {0, c0};
+        zface<2, NSV, FLUX>(G, A.viscous_only, ring, qm, qa, qb, qp, tap, tam, tbp, tbm, Fdown);
+    }
+    const long gxy = (long)(y0 + ty) * n0 + (x0 + tx);
+    bool nonfin = false;
+    double* out = (double*)A.out;
+#pragma unroll 1
+    for (int z = zs; z < ze; ++z) {
+        const long go = (long)z * n0 * n1 + gxy;
+        double rx[5], ry[5];
+        // x face on the -x side of the cell; the +x side's from the next lane of the row
+        {
+            const int ca = c0 - 1, cb = c0;
+            double qm[5], qa[5], qb[5], qp[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                qm[k] = ring[sB][k][ca - 1];
+                qa[k] = ring[sB][k][ca];
+                qb[k] = ring[sB][k][cb];
+                qp[k] = ring[sB][k][cb + 1];
+            }
+            ZRef tap[3], tam[3], tbp[3], tbm[3];
+            tap[0] = tam[0] = tbp[0] = tbm[0] = {sB, ca};
+            tap[1] = {sB, ca + kZW}; tam[1] = {sB, ca - kZW}; tbp[1] = {sB, cb + kZW}; tbm[1] = {sB, cb - kZW};
+            tap[2] = {sC, ca};       tam[2] = {sA, ca};       tbp[2] = {sC, cb};       tbm[2] = {sA, cb};
+            double F[5];
+            zface<0, NSV, FLUX>(G, A.viscous_only, ring, qm, qa, qb, qp, tap, tam, tbp, tbm, F);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const double nb = __shfl_down(F[m], 1, 16);
+                rx[m] = (tx < 15) ? (F[m] - nb) * G.invdx[0] : F[m];
+            }
+        }
+        // y face on the -y side; the +y side's from the lane 16 up, or (last row of a wave) through LDS
+        {
+            const int ca = c0 - kZW, cb = c0;
+            double qm[5], qa[5], qb[5], qp[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                qm[k] = ring[sB][k][ca - kZW];
+                qa[k] = ring[sB][k][ca];
+                qb[k] = ring[sB][k][cb];
+                qp[k] = ring[sB][k][cb + kZW];
+            }
+            ZRef tap[3], tam[3], tbp[3], tbm[3];
+            tap[0] = {sB, ca + 1}; tam[0] = {sB, ca - 1}; tbp[0] = {sB, cb + 1}; tbm[0] = {sB, cb - 1};
+            tap[1] = tam[1] = tbp[1] = tbm[1] = {sB, ca};
+            tap[2] = {sC, ca};     tam[2] = {sA, ca};     tbp[2] = {sC, cb};     tbm[2] = {sA, cb};
+            double F[5];
+            zface<1, NSV, FLUX>(G, A.viscous_only, ring, qm, qa, qb, qp, tap, tam, tbp, tbm, F);
+            if ((ty & 3) == 0) {
+#pragma unroll
+                for (int m = 0; m < 5; ++m) frow_y[ty >> 2][m][tx] = F[m];
+            }
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const double nb = __shfl_down(F[m], 16, 64);
+                ry[m] = ((ty & 3) != 3) ? (F[m] - nb) * G.invdx[1] : F[m];
+            }
+        }
+        // the column's edge faces: two waves (alternating by plane), 16 lanes each
+        const int we = (z & 1) * 2;
+        if (wv == we && lane < 16) {
+            const int cb = (lane + 2) * kZW + 18, ca = cb - 1;
+            double qm[5], qa[5], qb[5], qp[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                qm[k] = ring[sB][k][ca - 1];
+                qa[k] = ring[sB][k][ca];
+                qb[k] = ring[sB][k][cb];
+                qp[k] = ring[sB][k][cb + 1];
+            }
+            ZRef tap[3], tam[3], tbp[3], tbm[3];
+            tap[0] = tam[0] = tbp[0] = tbm[0] = {sB, ca};
+            tap[1] = {sB, ca + kZW}; tam[1] = {sB, ca - kZW}; tbp[1] = {sB, cb + kZW}; tbm[1] = {sB, cb - kZW};
+            tap[2] = {sC, ca};       tam[2] = {sA, ca};       tbp[2] = {sC, cb};       tbm[2] = {sA, cb};
+            double F[5];
+            zface<0, NSV, FLUX>(G, A.viscous_only, ring, qm, qa, qb, qp, tap, tam, tbp, tbm, F);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) fedge_x[m][lane] = F[m];
+        } else if (wv == we + 1 && lane < 16) {
+            const int cb = 18 * kZW + lane + 2, ca = cb - kZW;
+            double qm[5], qa[5], qb[5], qp[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                qm[k] = ring[sB][k][ca - kZW];
+                qa[k] = ring[sB][k][ca];
+                qb[k] = ring[sB][k][cb];
+                qp[k] = ring[sB][k][cb + kZW];
+            }
+            ZRef tap[3], tam[3], tbp[3], tbm[3];
+            tap[0] = {sB, ca + 1}; tam[0] = {sB, ca - 1}; tbp[0] = {sB, cb + 1}; tbm[0] = {sB, cb - 1};
+            tap[1] = tam[1] = tbp[1] = tbm[1] = {sB, ca};
+            tap[2] = {sC, ca};     tam[2] = {sA, ca};     tbp[2] = {sC, cb};     tbm[2] = {sA, cb};
+            double F[5];
+            zface<1, NSV, FLUX>(G, A.viscous_only, ring, qm, qa, qb, qp, tap, tam, tbp, tbm, F);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) frow_y[4][m][lane] = F[m];
+        }
+        // z face above the cell (planes z - 1 .. z + 2 of this column)
+        double q2[5], Fup[5];
+        {
+            load_prim(z + 2, c0, q2);
+            double qm[5], qa[5], qb[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                qm[k] = ring[sA][k][c0];
+                qa[k] = ring[sB][k][c0];
+                qb[k] = ring[sC][k][c0];
+            }
+            ZRef tap[3], tam[3], tbp[3], tbm[3];
+            tap[0] = {sB, c0 + 1};   tam[0] = {sB, c0 - 1};   tbp[0] = {sC, c0 + 1};   tbm[0] = {sC, c0 - 1};
+            tap[1] = {sB, c0 + kZW}; tam[1] = {sB, c0 - kZW}; tbp[1] = {sC, c0 + kZW}; tbm[1] = {sC, c0 - kZW};
+            tap[2] = tam[2] = tbp[2] = tbm[2] = {sB, c0};
+            zface<2, NSV, FLUX>(G, A.viscous_only, ring, qm, qa, qb, q2, tap, tam, tbp, tbm, Fup);
+        }
+        __syncthreads();   // edge faces written; plane z - 1 no longer read
+        double f0v[5];
+        if constexpr (MODE == MODE_FD) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) f0v[m] = A.f0[(long)m * G.ncell + go];
+        }
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            if (tx == 15) rx[m] = (rx[m] - fedge_x[m][ty]) * G.invdx[0];
+            if ((ty & 3) == 3) ry[m] = (ry[m] - frow_y[(ty + 1) >> 2][m][tx]) * G.invdx[1];
+            double res = rx[m];
+            res = res + ry[m];
+            res = res + (Fdown[m] - Fup[m]) * G.invdx[2];
+            Fdown[m] = Fup[m];
+            double x;
+            if constexpr (MODE == MODE_FD) x = (res - f0v[m]) / eps;
+            else x = res;
+            out[(long)m * G.ncell + go] = x;
+            nonfin = nonfin || !(fabs(x) < __builtin_inf());
+        }
+        // plane z + 2 replaces plane z - 1
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ring[sA][k][c0] = q2[k];
+        stage_halo(z + 2, sA);
+        __syncthreads();   // plane z + 2 staged; the edge faces read
+        const int t = sA;
+        sA = sB;
+        sB = sC;
+        sC = t;
+    }
+    if (A.status && (np || nonfin))
+        atomicOr(A.status, (np ? (int)ROK_FLAG_NONPHYSICAL : 0) | (nonfin ? (int)ROK_FLAG_NONFINITE : 0));
+}
+
 template <int D, int RECON, bool NSV, int FLUX, int GEO, typename S, int MODE, typename OUT, int TX, int TY, int TZ>
 static hipError_t launch_t(const Geom& G, const ResArgs& A, hipStream_t st) {
     int nt0 = (G.n[0] + TX - 1) / TX;
@@ -722,6 +1073,22 @@ static hipError_t launch_v(const Geom& G, const ResArgs& A, hipStream_t st) {
         else if constexpr (RECON == 1 && wide) return launch_t<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, 32, 16, 1>(G, A, st);
         else return launch_t<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, 32, 8, 1>(G, A, st);
     } else {
+        if constexpr (RECON == 1 && GEO == 0 && std::is_same<S, double>::value && std::is_same<OUT, double>::value &&
+                      MODE != MODE_TAN) {
+            if (G.n[0] % 16 == 0 && G.n[1] % 16 == 0) {
+                // columns of 16 x 16 cells, each cut into nch ranges of planes: enough
+                // blocks to fill the chip once, ranges of at least 8 planes
+                const int nbx = G.n[0] / 16, nby = G.n[1] / 16;
+                const long ncol = (long)nbx * nby;
+                long nch = (kZBlocks + ncol - 1) / ncol;
+                nch = std::min<long>(nch, std::max(1, G.n[2] / 8));
+                const long nb = ncol * nch;
+                if (nb <= 0 || nb > 0x7fffffffL) return hipErrorInvalidValue;
+                hipLaunchKernelGGL((k_res3z<NSV, FLUX, MODE>), dim3((unsigned)nb), dim3(kThreads), 0, st, G, A, nbx,
+                                   nby, (int)nch);
+                return hipGetLastError();
+            }
+        }
         return launch_t<D, RECON, NSV, FLUX, GEO, S, MODE, OUT, 16, 4, 4>(G, A, st);
     }
 }
