@@ -957,7 +957,12 @@ def build_traffic(workload, cdir, out_path):
     single = {"mgs_pass": ("void rok::k_red<true, false>", KRED_SOURCES, 24 * N),
               "mgs_column": (f"void rok::k_mgs_resident<{m}>", MGS_SOURCES, col_alg)}
     res = f"void rok::k_residual<{D}, 1, {ns}, 0, 0, "
-    if w["precision"] == "fp64":
+    if w["precision"] == "fp64" and D == 3 and pb["n"][0] % 16 == 0 and pb["n"][1] % 16 == 0:
+        # 3-D FP64 MUSCL on columns of 16 x 16 cells: the column-marching kernel
+        fl = 1 if pb.get("flux", "rusanov") == "roe" else 0
+        single["fd_jvp"] = (f"void rok::k_res3z<{ns}, {fl}, 1>", RESIDUAL_SOURCES, 32 * N)
+        single["residual"] = (f"void rok::k_res3z<{ns}, {fl}, 0>", RESIDUAL_SOURCES, 16 * N)
+    elif w["precision"] == "fp64":
         single["fd_jvp"] = (res + "double, 1, double", RESIDUAL_SOURCES, 32 * N)
         single["residual"] = (res + "double, 0, double", RESIDUAL_SOURCES, 16 * N)
     else:   # the API's FP32 products and residual write FP32
