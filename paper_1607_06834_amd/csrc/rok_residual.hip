@@ -721,7 +721,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(Geom G, ResArgs A, int nt
 constexpr int kZW = 20;              // staged plane width (16 + 2 + 2)
 constexpr int kZR = kZW * kZW;       // cells of a staged plane
 constexpr int kZHalo = kZR - 256;    // its halo cells
-constexpr int kZBlocks = 768;        // three resident blocks on each of 256 CUs
+constexpr int kZBlocks = 1536;       // two rounds of three resident blocks on each of 256 CUs
 
 struct ZRef {
     int s, c;   // LDS slot, index in the staged plane
