@@ -5,8 +5,8 @@ multiples of 16, any n2), against the oracle bit for bit.
 The other 3-D parity tests use grids that take the tile kernel; these cover
 the marching form: its three staged planes and the plane read ahead into
 registers, the z face carried from one plane to the next, ranges of planes of
-unequal length, periodic wrap at the ends of a range (down to a grid of three
-planes), the edge faces exchanged through LDS, and every flux variant
+unequal length, periodic wrap at the ends of a range (down to grids of one, two
+and three planes), the edge faces exchanged through LDS, and every flux variant
 (Rusanov, Roe, constant viscosity, Sutherland's law, the split into inviscid
 and viscous parts).
 """
@@ -51,7 +51,7 @@ def _pb(shape, physics, flux="rusanov", suth=0.0):
 
 CASES = [((32, 32, 32), "ns", "rusanov", 0.0), ((48, 16, 64), "ns", "roe", 0.0), ((16, 32, 37), "ns", "rusanov", 0.4),
          ((32, 16, 20), "euler", "rusanov", 0.0), ((16, 16, 64), "euler", "roe", 0.0), ((16, 16, 3), "ns", "rusanov", 0.0),
-         ((16, 48, 5), "ns", "roe", 0.4)]
+         ((16, 48, 5), "ns", "roe", 0.4), ((32, 16, 2), "euler", "rusanov", 0.0), ((16, 16, 1), "ns", "rusanov", 0.0)]
 
 
 @pytest.mark.parametrize("shape,physics,flux,suth", CASES)
