@@ -76,6 +76,8 @@ enum { ROK_MGS_AUTO = 0, ROK_MGS_PER_PASS = 1, ROK_MGS_RESIDENT = 2, ROK_MGS_ONE
 
 #define ROK_MAX_STAGES 8
 #define ROK_MAX_M 64
+/* Largest Arnoldi dimension m of the eigenvalue estimate (rok_eigs). */
+#define ROK_EIGS_MAX_M 2048
 
 /*
  * The semi-discrete system y' = f(y) of Sec. 2, eq. (1): the compressible
@@ -512,7 +514,10 @@ rok_status rok_residual_vjp2(rok_ctx* ctx, const double* y, const double* v, con
  * and extended back to m, at most max_restarts times.  The small dense work
  * on H (m x m) runs on the host; the call synchronises `stream`.
  *   y, v0:  N doubles, device memory (v0 != 0: the start vector)
- *   k, m:   1 <= k, k + 2 <= m <= ROK_MAX_M - 1, m + 1 <= N
+ *   k, m:   1 <= k, k + 2 <= m <= ROK_EIGS_MAX_M, m + 1 <= N (m + 1 > ROK_MAX_M:
+ *           the passes of the Gram-Schmidt columns run one launch each,
+ *           whatever the context's Gram-Schmidt path; ROK_EUNSUPPORTED if the
+ *           context asks for ROK_MGS_RESIDENT)
  *   tol:    > 0;  max_restarts >= 0
  *   re, im, resid: host arrays of k doubles: the wanted Ritz values by
  *           decreasing magnitude and their residual estimates (0 when the

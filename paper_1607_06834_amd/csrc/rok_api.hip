@@ -668,7 +668,7 @@ EigLayout eig_layout(long N, int m) {
 }
 
 bool eig_args_ok(const rok_ctx* c, int k, int m) {
-    return c && m >= 3 && m <= ROK_MAX_M - 1 && k >= 1 && k + 2 <= m && (long)m + 1 <= c->G.N;
+    return c && m >= 3 && m <= ROK_EIGS_MAX_M && k >= 1 && k + 2 <= m && (long)m + 1 <= c->G.N;
 }
 }  // namespace
 
@@ -694,8 +694,10 @@ rok_status rok_eigs(rok_ctx* c, const double* y, const double* v0, int k, int m,
     // a second pass of every Gram-Schmidt column writes its coefficients here
     rok::Work W2 = W;
     W2.H = (double*)(p + L.work + 2 * L.basis + L.coef);
-    const bool resident =
-        c->mgs_path != ROK_MGS_PER_PASS && rok::mgs_resident_per(N) > 0 && rok::mgs_resident_available();
+    // the resident kernel holds a column of H in LDS (at most ROK_MAX_M entries): larger bases
+    // take the pass-by-pass kernels
+    const bool resident = c->mgs_path != ROK_MGS_PER_PASS && Mp <= ROK_MAX_M && rok::mgs_resident_per(N) > 0 &&
+                          rok::mgs_resident_available();
     if (c->mgs_path == ROK_MGS_RESIDENT && !resident) return ROK_EUNSUPPORTED;
     auto mgs = [&](const rok::Work& Wx, int j, double* vnext) -> hipError_t {
         return resident ? rok::launch_mgs_resident(Wx, Wx.w, V, N, Mp, j, vnext, st)

@@ -352,8 +352,9 @@ class Rok:
         self._metrics = met
 
     def eigs(self, y, v0, k: int = 6, m: int = 40, max_restarts: int = 50, tol: float = 1e-10):
-        """k largest-magnitude eigenvalues of J(y) (rok_eigs).  Returns (values as a complex
-        numpy array, residual estimates, restarts used, number converged)."""
+        """k largest-magnitude eigenvalues of J(y) (rok_eigs; k + 2 <= m <= 2048, m + 1 <= N).
+        Returns (values as a complex numpy array, residual estimates, restarts used, number
+        converged)."""
         import numpy as np
         self._vec(y, "y")
         self._vec(v0, "v0")

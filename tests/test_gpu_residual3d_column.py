@@ -94,6 +94,22 @@ def test_column_step_bitwise(dev, mgs):
         assert torch.equal(out, ref)
 
 
+def test_column_exact_step(dev):
+    """An exact-product step on a marching-size grid: the stage residuals go
+    through the marching kernel and the tangent products through the tile
+    kernel's dual-number form; within 1e-12 of the oracle's step."""
+    say("column exact step")
+    pb = _pb((16, 32, 32), "ns", "roe", 0.4)
+    P = oracle_problem(pb)
+    y = t64(ri.smooth_random_state(pb, seed=7, amplitude=0.2))
+    h = ri.cfl_step(pb, y.numpy(), 2.0)
+    tab = ri.rok4_tableau()
+    f, mv = rok.fv_system(P, "exact")
+    ref = rok.rok_step(f, mv, tab, 6, h, y)
+    out = gpu(pb).step(y.to(dev), h, tab, 6, "exact").cpu()
+    assert relerr(out, ref) <= 1e-12
+
+
 def test_column_flags(dev):
     """A negative pressure in the top plane of a chunk (staged by the chunk
     above as its lower halo too) sets NONPHYSICAL and, through the NaN sound

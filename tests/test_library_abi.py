@@ -70,7 +70,9 @@ def test_host_validation_without_gpu():
     # eigenvalue estimate: sizes are validated on the host
     assert lib.rok_eigs_workspace_bytes(ctx, 6, 40) > 0
     assert lib.rok_eigs_workspace_bytes(ctx, 9, 10) == 0 and lib.rok_eigs_workspace_bytes(ctx, 0, 10) == 0
-    assert lib.rok_eigs_workspace_bytes(ctx, 4, 64) == 0
+    assert lib.rok_eigs_workspace_bytes(ctx, 4, 64) > 0            # past ROK_MAX_M: the pass-by-pass kernels
+    assert lib.rok_eigs_workspace_bytes(ctx, 4, 255) > 0 and lib.rok_eigs_workspace_bytes(ctx, 4, 256) == 0  # m + 1 <= N
+    assert lib.rok_eigs_workspace_bytes(ctx, 4, 2049) == 0           # past ROK_EIGS_MAX_M (and N)
     re_, im_, rs_ = (ctypes.c_double * 4)(), (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
     inf = (ctypes.c_int * 2)()
     assert lib.rok_eigs(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), 4, 5, 10, 1e-8, re_, im_, rs_, inf,
