@@ -73,6 +73,15 @@ def test_host_validation_without_gpu():
     assert lib.rok_eigs_workspace_bytes(ctx, 4, 64) > 0            # past ROK_MAX_M: the pass-by-pass kernels
     assert lib.rok_eigs_workspace_bytes(ctx, 4, 255) > 0 and lib.rok_eigs_workspace_bytes(ctx, 4, 256) == 0  # m + 1 <= N
     assert lib.rok_eigs_workspace_bytes(ctx, 4, 2049) == 0           # past ROK_EIGS_MAX_M (and N)
+    # a basis past ROK_MAX_M is orthogonalised pass by pass: an explicit request for the resident kernel is
+    # refused before any device work
+    assert lib.rok_set_mgs_path(ctx, 2) == rok.ROK_OK                  # ROK_MGS_RESIDENT
+    nb = lib.rok_eigs_workspace_bytes(ctx, 4, 100)
+    re_, im_, rs_ = (ctypes.c_double * 4)(), (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
+    info = (ctypes.c_int * 2)()
+    assert lib.rok_eigs(ctx, ctypes.c_void_p(256), ctypes.c_void_p(512), 4, 100, 1, 1e-8, re_, im_, rs_, info,
+                        ctypes.c_void_p(1 << 20), nb, None) == rok.ROK_EUNSUPPORTED
+    assert lib.rok_set_mgs_path(ctx, 0) == rok.ROK_OK
     re_, im_, rs_ = (ctypes.c_double * 4)(), (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
     inf = (ctypes.c_int * 2)()
     assert lib.rok_eigs(ctx, ctypes.c_void_p(8), ctypes.c_void_p(16), 4, 5, 10, 1e-8, re_, im_, rs_, inf,
