@@ -260,6 +260,14 @@ struct GamRow {
     double g[kMaxStages];
 };
 
+// The value of v held by lane `lane` (uniform across the wave) of the calling wave.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // phi_i = V^T F_i finished from the projection partials (all columns at once,
 // canonical order per column), then
 // lambda_i = LU^{-1} (h phi_i + h H sum_{j<i} gamma_ij lambda_j) on the same block.
@@ -268,19 +276,44 @@ __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const d
                                                        double* phi, double* lam, int* ints, const double* sig) {
     __shared__ double s[16][kRedThreads];
     __shared__ double sphi[kMaxM];
-    const int m = ints[0];
+    __shared__ double sLU[kMaxM * kMaxM], sH[kMaxM * kMaxM];
+    __shared__ double g[kMaxM];
+    __shared__ int sperm[kMaxM];
     const int tid = threadIdx.x;
+    // Every load whose address does not depend on M_eff is issued first, for the
+    // compiled size M (entries past M_eff are loaded and never used): the first
+    // 16 columns' partials (lane tid adds partials tid, tid + 256, tid + 512,
+    // tid + 768 of each column in order), then LU, H, the pivots and the earlier
+    // lambdas, staged in LDS; one round trip to memory instead of three.
+    static_assert(kRedBlocks == 4 * kRedThreads, "four partials per lane");
+    const int n16 = M < 16 ? M : 16;
+    double pv[16][4];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pv[c][q] = (c < n16) ? partials[(long)c * kRedBlocks + tid + q * kRedThreads] : 0.0;
+    for (int e = tid; e < M * M; e += kRedThreads) {
+        const int r = e / M, c = e % M;
+        sLU[r * kMaxM + c] = LU[e];
+        sH[r * kMaxM + c] = H[e];
+    }
+    if (tid < M) {
+        sperm[tid] = perm[tid];
+        double a = 0.0;
+        for (int j = 0; j < i; ++j)
+            if (gr.g[j] != 0.0) a = a + gr.g[j] * lam[j * M + tid];
+        g[tid] = a;
+    }
+    const int m = ints[0];
     for (int c0 = 0; c0 < m; c0 += 16) {
         const int nc = (m - c0) < 16 ? (m - c0) : 16;
-        // lane tid adds partials tid, tid + 256, tid + 512, tid + 768 of each column in
-        // order; the loads of all 16 columns are issued before any sum waits
-        static_assert(kRedBlocks == 4 * kRedThreads, "four partials per lane");
-        double pv[16][4];
+        if (c0 > 0) {   // columns past the first 16 (M > 16)
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
+            for (int c = 0; c < 16; ++c)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                pv[c][q] = (c < nc) ? partials[(long)(c0 + c) * kRedBlocks + tid + q * kRedThreads] : 0.0;
+                for (int q = 0; q < 4; ++q)
+                    pv[c][q] = (c < nc) ? partials[(long)(c0 + c) * kRedBlocks + tid + q * kRedThreads] : 0.0;
+        }
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             if (c < nc) {
@@ -300,52 +333,34 @@ __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const d
         if (tid < nc) sphi[c0 + tid] = sig ? s[tid][0] * sig[c0 + tid] : s[tid][0];
         __syncthreads();
     }
-    // The reduced solve.  H, LU, the pivots and the earlier lambdas are staged
-    // in LDS; the right-hand side is formed row-parallel and the forward
-    // substitution column-parallel (each entry still sees its updates in
-    // increasing column order); the back substitution, whose entries each
-    // need the next one first, runs on one lane from LDS.
-    __shared__ double sLU[kMaxM * kMaxM], sH[kMaxM * kMaxM];
-    __shared__ double g[kMaxM], y[kMaxM];
-    __shared__ int sperm[kMaxM];
-    for (int e = tid; e < m * m; e += kRedThreads) {
-        const int r = e / m, c = e % m;
-        sLU[r * kMaxM + c] = LU[r * M + c];
-        sH[r * kMaxM + c] = H[r * M + c];
-    }
-    if (tid < m) {
-        sperm[tid] = perm[tid];
-        double a = 0.0;
-        for (int j = 0; j < i; ++j)
-            if (gr.g[j] != 0.0) a = a + gr.g[j] * lam[j * M + tid];
-        g[tid] = a;
-        phi[i * M + tid] = sphi[tid];
-    }
-    __syncthreads();
-    if (tid < m) {   // x_r = h phi_r + h (H g)_r, placed at its pivoted position
+    if (tid < m) phi[i * M + tid] = sphi[tid];
+    // The reduced solve: the right-hand side row-parallel, the forward substitution
+    // column-parallel (each entry still sees its updates in increasing column order),
+    // the back substitution one row at a time (each row's sum in increasing column
+    // order) with the finished entries broadcast from their lanes.
+    // From here on wave 0 alone (m <= kMaxM = 64: row r on lane r), with no block barrier:
+    // lane values move by lane shuffles and broadcasts.
+    if (tid >= 64) return;
+    double x = 0.0;
+    if (tid < m) {   // x_r = h phi_r + h (H g)_r
         double hg = 0.0;
         for (int c = 0; c < m; ++c) hg = hg + sH[tid * kMaxM + c] * g[c];
-        s[0][tid] = h * sphi[tid] + h * hg;
+        x = h * sphi[tid] + h * hg;
     }
-    __syncthreads();
-    if (tid < m) y[tid] = s[0][sperm[tid]];
-    __syncthreads();
+    double yr = __shfl(x, tid < m ? sperm[tid] : tid, 64);   // placed at its pivoted position
     for (int c = 0; c + 1 < m; ++c) {   // forward substitution with the unit lower factor
-        if (tid > c && tid < m) y[tid] = y[tid] - sLU[tid * kMaxM + c] * y[c];
-        __syncthreads();
+        const double yc = lane_value(yr, c);
+        if (tid > c && tid < m) yr = yr - sLU[tid * kMaxM + c] * yc;
     }
-    if (tid != 0) return;
-    for (int r = m - 1; r >= 0; --r) {
-        double a = y[r];
-        for (int c = r + 1; c < m; ++c) a = a - sLU[r * kMaxM + c] * y[c];
-        y[r] = a / sLU[r * kMaxM + r];
+    for (int r = m - 1; r >= 0; --r) {   // back substitution: row r's sum in increasing column order
+        double a = lane_value(yr, r);
+        for (int c = r + 1; c < m; ++c) a = a - sLU[r * kMaxM + c] * lane_value(yr, c);
+        a = a / sLU[r * kMaxM + r];
+        if (tid == r) yr = a;
     }
-    bool bad = false;
-    for (int r = 0; r < m; ++r) {
-        lam[i * M + r] = y[r];
-        bad = bad || nonfinite(y[r]);
-    }
-    if (bad) ints[2] |= ROK_FLAG_NONFINITE;
+    if (tid < m) lam[i * M + tid] = yr;
+    const bool bad = __any(tid < m && nonfinite(yr));
+    if (tid == 0 && bad) ints[2] |= ROK_FLAG_NONFINITE;
 }
 
 // Projection partials: for c < M_eff, canonical per-block partial sums of
