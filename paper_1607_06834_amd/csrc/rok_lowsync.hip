@@ -94,9 +94,10 @@ constexpr int kSolveThreads = 4 * kRedThreads;   // four of the column's sums fi
 // s_c = (sig_j sig_c) <V_j, V_c>.
 __global__ __launch_bounds__(kSolveThreads) void k_ls_solve(const double* partials, int MB, int j, int M, double* L,
                                                            double* H, int* ints, const double* sig) {
+    constexpr int kW = 24;   // widest compiled column
     __shared__ double s[kSolveThreads];
     __shared__ double sr[kMaxM], ss[kMaxM];
-    if (ints[1]) return;
+    __shared__ double sL[kW * kW], sh[kW];
     const int tid = threadIdx.x;
     const int grp = tid / kRedThreads, lane = tid % kRedThreads;
     // sums q = 0..j are r_q (partial column q), q = j+1..2j are s_{q-j-1}
@@ -104,9 +105,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_ls_solve(const double* partia
     // the canonical order
     const int nsum = 2 * j + 1;
     constexpr int G = kSolveThreads / kRedThreads;            // sums per round
-    constexpr int R = (2 * 24 - 1 + G - 1) / G;              // rounds for the widest column (M <= 24)
+    constexpr int R = (2 * kW - 1 + G - 1) / G;              // rounds for the widest column (M <= 24)
     static_assert(kRedBlocks == 4 * kRedThreads, "four partials per lane");
-    // every partial this lane adds, loaded before any sum waits
+    // every partial this lane adds, loaded before any sum waits, and rows 0..j-1 of L
+    // staged in LDS meanwhile: one memory round trip before the sums
     double pv[R][4];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -115,6 +117,11 @@ __global__ __launch_bounds__(kSolveThreads) void k_ls_solve(const double* partia
 #pragma unroll
         for (int u = 0; u < 4; ++u) pv[r][u] = (q < nsum) ? partials[col * kRedBlocks + lane + u * kRedThreads] : 0.0;
     }
+    for (int e = tid; e < j * j; e += kSolveThreads) {
+        const int r = e / j, c = e % j;
+        if (c < r) sL[r * kW + c] = L[r * M + c];
+    }
+    if (ints[1]) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int q0 = r * G;
@@ -135,11 +142,13 @@ __global__ __launch_bounds__(kSolveThreads) void k_ls_solve(const double* partia
         __syncthreads();
     }
     if (tid != 0) return;
+    // (I + L) h = r by forward substitution, row j of L being the new s row
     for (int c = 0; c < j; ++c) L[j * M + c] = ss[c];
     bool bad = false;
     for (int i = 0; i <= j; ++i) {
         double hi = sr[i];
-        for (int l = 0; l < i; ++l) hi = hi - L[i * M + l] * H[l * M + j];
+        for (int l = 0; l < i; ++l) hi = hi - (i < j ? sL[i * kW + l] : ss[l]) * sh[l];
+        sh[i] = hi;
         H[i * M + j] = hi;
         bad = bad || !(hi == hi) || fabs(hi) == __builtin_inf();
     }
