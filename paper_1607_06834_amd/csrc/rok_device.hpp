@@ -163,6 +163,48 @@ __device__ __forceinline__ double tree256(double v, double* s) {
     return v;
 }
 
+// tree256 for many values of every thread of a 256-thread block at once:
+// values v[C0 .. C0 + 16) (those below nact) go through the tree of tree256
+// together, the two LDS levels shared by all of them (three block barriers
+// per 16 values, the last before `s` is reused), with the same additions in
+// the same order for each; thread 0 passes each sum to store(index, sum).
+// `s` holds 16 x 256 doubles of LDS.  nact must be the same in every thread.
+template <int C0, int N, typename F>
+__device__ __forceinline__ void tree256_chunks(const double (&v)[N], int nact, double (*s)[256], F store) {
+    if constexpr (C0 < N) {
+        if (C0 >= nact) return;
+        const int tid = threadIdx.x;
+        constexpr int K = (N - C0) < 16 ? (N - C0) : 16;
+        double x[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) s[c][tid] = v[C0 + c];
+        __syncthreads();
+        if (tid < 128) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                x[c] = v[C0 + c] + s[c][tid + 128];
+                s[c][tid] = x[c];
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                x[c] = x[c] + s[c][tid + 64];
+#pragma unroll
+                for (int h = 32; h > 0; h >>= 1) x[c] = x[c] + __shfl_down(x[c], h, 64);
+            }
+        }
+        if (tid == 0) {
+#pragma unroll
+            for (int c = 0; c < K; ++c)
+                if (C0 + c < nact) store(C0 + c, x[c]);
+        }
+        __syncthreads();
+        tree256_chunks<C0 + 16, N>(v, nact, s, store);
+    }
+}
+
 // Periodic wrap of an index that may lie anywhere in [-n, 2n) (fast path) or
 // beyond (small grids).
 __device__ __forceinline__ int wrap(int i, int n) {

@@ -369,7 +369,6 @@ __global__ __launch_bounds__(kRedThreads) void k_lambda(const double* H, const d
 template <int MB>
 __global__ __launch_bounds__(kRedThreads) void k_project(const double* V, const double* F, long n, const int* ints,
                                                         double* partials) {
-    __shared__ double s[kRedThreads];
     const int m = ints[0];
     double acc[MB];
 #pragma unroll
@@ -392,13 +391,8 @@ __global__ __launch_bounds__(kRedThreads) void k_project(const double* V, const 
                 if (c < m) acc[c] = acc[c] + ld_stream(V + (long)c * n + e) * fe;
         }
     }
-#pragma unroll
-    for (int c = 0; c < MB; ++c) {
-        if (c < m) {
-            double bs = block_sum(acc[c], s);
-            if (threadIdx.x == 0) partials[(long)c * kRedBlocks + blockIdx.x] = bs;
-        }
-    }
+    __shared__ double sm[16][kRedThreads];
+    tree256_chunks<0, MB>(acc, m, sm, [&](int c, double b) { partials[(long)c * kRedBlocks + blockIdx.x] = b; });
 }
 
 struct BRow {

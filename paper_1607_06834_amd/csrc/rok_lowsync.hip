@@ -46,7 +46,6 @@ namespace rok {
 template <int MB>
 __global__ __launch_bounds__(kRedThreads) void k_ls_dots(const double* V, const double* w, long n, int j,
                                                         const int* ints, double* partials) {
-    __shared__ double s[kRedThreads];
     if (ints[1]) return;
     double ar[MB], as[MB];
 #pragma unroll
@@ -69,19 +68,10 @@ __global__ __launch_bounds__(kRedThreads) void k_ls_dots(const double* V, const 
             if (c < j) as[c] = as[c] + qj * q[c];
         }
     }
-#pragma unroll
-    for (int c = 0; c < MB; ++c) {
-        if (c <= j) {
-            const double b = tree256(ar[c], s);
-            if (threadIdx.x == 0) partials[(long)c * kRedBlocks + blockIdx.x] = b;
-            __syncthreads();
-        }
-        if (c < j) {
-            const double b = tree256(as[c], s);
-            if (threadIdx.x == 0) partials[(long)(MB + c) * kRedBlocks + blockIdx.x] = b;
-            __syncthreads();
-        }
-    }
+    // the block's sums of every column at once (the canonical tree of each)
+    __shared__ double sm[16][kRedThreads];
+    tree256_chunks<0, MB>(ar, j + 1, sm, [&](int c, double b) { partials[(long)c * kRedBlocks + blockIdx.x] = b; });
+    tree256_chunks<0, MB>(as, j, sm, [&](int c, double b) { partials[(long)(MB + c) * kRedBlocks + blockIdx.x] = b; });
 }
 
 constexpr int kSolveThreads = 4 * kRedThreads;   // four of the column's sums finished at once
