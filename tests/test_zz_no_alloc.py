@@ -39,6 +39,9 @@ PAIRS = [
     ("vortex 96^2 then 24^2", lambda: ri.vortex_problem(96, "muscl"), lambda: ri.vortex_problem(24, "muscl")),
     ("ns3d 20^3 then 7x5x3", lambda: ri.tgv_problem(20, 3),
      lambda: ri.problem((7, 5, 3), (0, 0, 0), (1.0, 0.9, 1.2), "ns", "muscl", mu=0.05)),
+    # column-marching grids (n0, n1 multiples of 16)
+    ("ns3d 32^3 then 16x16x5", lambda: ri.tgv_problem(32, 3),
+     lambda: ri.problem((16, 16, 5), (0, 0, 0), (1.0, 0.9, 1.2), "ns", "muscl", mu=0.05)),
 ]
 
 
